@@ -1,0 +1,211 @@
+/*
+ * isira.h -- C ABI of the MI355X (gfx950) implementation of iSIRA, the integrated
+ * shift-invert residual Arnoldi method for the smallest positive eigenpairs of a graph
+ * Laplacian (Huang, Lin, Lu, Yau, arXiv 1710.07080).
+ *
+ * Problem (Section 1.1, Algorithm 3.2): given a simple, connected, undirected graph with
+ * positive edge weights W (Remark 1.3), find the k smallest positive eigenvalues of
+ * L = D - W (eq. (1.1)) and orthonormal eigenvectors, all orthogonal to the null vector 1
+ * (Theorem 1.2).
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: ISIRA_OK (0), ISIRA_NOT_CONVERGED (1), or a negative ISIRA_E_* code.
+ *     No exception crosses the ABI.  isira_strerror() names a code; isira_last_error()
+ *     gives the message of the last failure on this thread.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP device memory
+ *     of the GPU the context was created on (e.g. torch CUDA tensors on ROCm).  The caller
+ *     owns every pointer it passes; the library copies what it keeps.
+ *   - Vectors passed to or returned from a context use the caller's vertex labels.
+ *     Internally the library relabels vertices (by decreasing row length) and maps back.
+ *   - Dense n-by-c blocks are column-major with leading dimension n unless stated.
+ *   - A context is not thread-safe; calls on one context must not overlap.
+ *   - All GPU work of a context runs on the stream given at creation (NULL = default).
+ */
+#ifndef ISIRA_H
+#define ISIRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define ISIRA_OK 0
+#define ISIRA_NOT_CONVERGED 1   /* max_outer reached: the first stats->n_converged pairs are valid */
+#define ISIRA_E_ARG (-1)        /* bad argument (k, sigma, tol, m, q, sizes, null pointers) */
+#define ISIRA_E_GRAPH (-2)      /* CSR not simple/undirected: bad index, self loop, unsorted or
+                                   duplicate column, asymmetric pattern or weight, weight <= 0 */
+#define ISIRA_E_DISCONNECTED (-3) /* the graph has more than one connected component */
+#define ISIRA_E_HIP (-4)        /* a HIP runtime call failed (allocation, launch, copy) */
+#define ISIRA_E_PRECOND (-5)    /* the learned preconditioner is missing or not usable */
+#define ISIRA_E_STATE (-6)      /* entry point called in the wrong state */
+
+/* ---- weight dtypes ---- */
+#define ISIRA_W_NONE 0 /* unit weights (plain adjacency A) */
+#define ISIRA_W_F32 1
+#define ISIRA_W_F64 2
+
+/* ---- inner-solve precision ---- */
+#define ISIRA_FP64 0
+#define ISIRA_FP32 1
+
+/* ---- inner preconditioner ---- */
+#define ISIRA_PC_JACOBI 0  /* M-hat_sigma = diag(d - sigma), Remark 3.2, with eq. (3.5) */
+#define ISIRA_PC_LEARNED 1 /* learned sparse approximate inverse, with eq. (3.5) */
+
+#define ISIRA_MAX_K 64        /* at most 64 wanted pairs per solve */
+#define ISIRA_MAX_BASIS 192   /* m (maximal search-space dimension) is at most 192 */
+
+typedef struct isira_ctx isira_ctx;
+
+/* Options of one solve.  Zero / negative fields select the documented default. */
+typedef struct {
+  int32_t m;            /* maximal search-space dimension (Algorithm 3.2); default 2*q */
+  int32_t q;            /* restart size; default k + 10 */
+  int32_t k0;           /* start-block columns; default 4 */
+  double inner_rtol;    /* inner PCG stop: ||r_hat - K_hat z|| <= inner_rtol ||r_hat||; default 1e-4 */
+  int32_t max_inner;    /* PCG iteration cap per inner solve; default 1000 */
+  int32_t max_outer;    /* cap on outer iterations of the whole solve; default 20000 */
+  int32_t inner_prec;   /* ISIRA_FP64 (default) or ISIRA_FP32 */
+  int32_t precond;      /* ISIRA_PC_JACOBI (default) or ISIRA_PC_LEARNED */
+  int64_t trim_index;   /* trimmed vertex (caller label); -1 = max degree, lowest label on ties */
+  double delta;         /* deflation shift; <= 0 selects 2 * max diag(L) (Remark 4.1(ii)) */
+  uint64_t seed;        /* seed of the SplitMix64 replacement vectors (breakdowns, default start) */
+  const double* u0;     /* host, n-by-k0 column-major start block (caller labels), or NULL:
+                           then column j is SplitMix64(seed) at counters (j*n + l) */
+  int32_t check_every;  /* PCG iterations launched between convergence read-backs; default 8 */
+  int32_t verbose;      /* 1: print one line per locked pair to stderr */
+  /* optional capture of inner-solve pairs (device, caller labels), for preconditioner
+     training: column j of capture_z (n-by-capture_cap, FP64) receives the solution z_hat
+     of inner solve j (trimmed entry 0) and column j of capture_r receives
+     (L-hat - sigma I) z_hat, i.e. the pair an approximate inverse of L-hat - sigma I
+     should map onto each other; *capture_count (host) is the number written. */
+  double* capture_r;
+  double* capture_z;
+  int32_t capture_cap;
+  int32_t* capture_count;
+} isira_options;
+
+#define ISIRA_STATS_MAX 64
+typedef struct {
+  int32_t n_converged;
+  int32_t outer_total;                 /* outer (Rayleigh-Ritz) iterations */
+  int64_t inner_total;                 /* PCG iterations */
+  int64_t spmv_total;                  /* Laplacian applications (all precisions) */
+  int32_t restarts, breakdowns, refreshes, inner_fallbacks, inner_capped;
+  int32_t outer_per_pair[ISIRA_STATS_MAX];
+  int32_t inner_per_pair[ISIRA_STATS_MAX];
+  double ms_total, ms_inner, ms_ortho, ms_rr_host, ms_residual, ms_restart;
+  int64_t trim_index;                  /* caller label of the trimmed vertex */
+  double delta;
+} isira_stats;
+
+typedef struct {
+  int64_t n, nnz;
+  int64_t trim_index;    /* caller label of the default trim vertex */
+  double max_degree, min_degree, delta_default, norm1; /* norm1 = ||L||_1 = 2 max diag(L) */
+  int32_t n_spmv_units, n_spmv_blocks, n_split_rows;
+  int32_t has_learned;   /* 1 once learned preconditioner values are installed */
+} isira_info;
+
+/* Fill *opt with the defaults. */
+int isira_default_options(isira_options* opt);
+
+/* Create a context for one graph.  row_ptr (n+1), col (nnz) and w (nnz, or NULL when
+ * w_dtype == ISIRA_W_NONE) are HOST arrays of the off-diagonal adjacency in CSR form:
+ * sorted unique columns, no self loops, symmetric pattern and weights, weights > 0.
+ * The library validates the graph (E_GRAPH), checks connectivity (E_DISCONNECTED),
+ * relabels it, uploads its own copy, and computes on the GPU the weighted degrees,
+ * the trim index (Remark 4.1(i)) and delta (Remark 4.1(ii)).
+ * stream: a hipStream_t (NULL = default stream).  validate: 0 skips the O(nnz log d)
+ * symmetry check (the caller vouches for the input). */
+int isira_create(isira_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                 const int32_t* col, const void* w, int32_t w_dtype, void* stream,
+                 int32_t validate);
+
+void isira_destroy(isira_ctx* ctx);
+int isira_get_info(const isira_ctx* ctx, isira_info* info);
+
+/* Algorithm 3.2: the k smallest positive eigenpairs (1 <= k <= min(ISIRA_MAX_K, n-2)).
+ * sigma: fixed shift of the inner systems, 0 <= sigma < min degree (the caller
+ *   promises sigma < lambda_1 so the trimmed system (2.15) stays positive definite).
+ * tol: outer tolerance on ||W s_1 - theta_1 U s_1||_2; a pair is locked only when the
+ *   fresh FP64 residual ||L y - theta y||_2 also satisfies it.
+ * evals: host, k, ascending order of locking.  evecs: device, n-by-k column-major FP64,
+ *   caller labels, unit norm, orthogonal to 1, largest-magnitude entry positive.
+ * resid: host, k, ||L v - lambda v||_2 in FP64.  stats: host, may be NULL.
+ * Returns ISIRA_OK, ISIRA_NOT_CONVERGED (max_outer hit), or an error. */
+int isira_solve(isira_ctx* ctx, int32_t k, double sigma, double tol, const isira_options* opt,
+                double* evals, double* evecs, double* resid, isira_stats* stats);
+
+/* ---- operator-level entry points (kernel parity and measurement) ---- */
+
+/* y = L x in FP64 (eq. (1.1)); x, y device, n, caller labels. */
+int isira_laplacian_apply(isira_ctx* ctx, const double* x, double* y);
+/* y = L x with FP32 vectors and FP32 weights (the inner-solve operator precision). */
+int isira_laplacian_apply_f32(isira_ctx* ctx, const float* x, float* y);
+/* Time `reps` back-to-back FP64 (prec 0) or FP32 (prec 1) Laplacian products on
+ * internal vectors with HIP events on the context stream; *ms_per = average ms. */
+int isira_time_spmv(isira_ctx* ctx, int32_t prec, int32_t reps, double* ms_per);
+
+/* One inner solve of Algorithm 3.2's expansion step: solve the trimmed, shifted,
+ * deflated system (2.15) for r_hat = r with entry `trim` deleted, by PCG with the
+ * Remark 3.2 preconditioner (Jacobi or learned, with eq. (3.5) when c > 0), then enlarge
+ * by eq. (2.5).  r: device n FP64 (must be orthogonal to 1), V: device n-by-c FP64
+ * (orthonormal, orthogonal to 1; c <= ISIRA_MAX_K), trim: caller label or -1,
+ * delta <= 0 selects the default.  z: device n FP64 output.  *iters, *relres: host. */
+int isira_inner_solve(isira_ctx* ctx, const double* r, const double* V, int32_t c,
+                      double sigma, double delta, int64_t trim, double rtol, int32_t max_it,
+                      int32_t prec, int32_t precond, double* z, int32_t* iters,
+                      double* relres);
+
+/* Classical Gram-Schmidt applied twice against the ncols orthonormal columns of Q and
+ * the unit vector 1/sqrt(n), then normalization (the orthonormalization step of
+ * Algorithm 3.2).  Q: device n-by-ncols (ld n), z: device n input, u: device n output;
+ * norms (host, 2): ||z|| before and after.  Returns ISIRA_OK even on breakdown (u is then
+ * z scaled by 1/after, possibly inf); the caller inspects norms. */
+int isira_orthonormalize(isira_ctx* ctx, const double* Q, int32_t ncols, const double* z,
+                         double* u, double* norms);
+
+/* Host-only: all eigenpairs of a symmetric k-by-k matrix H (column-major), eigenvalues
+ * ascending in theta (k), unit eigenvectors in the columns of S (k-by-k column-major)
+ * -- the Rayleigh-Ritz step of Algorithm 3.2.  Householder tridiagonalization followed
+ * by the implicit QL iteration.  No GPU needed. */
+int isira_symeig(int32_t k, const double* H, double* theta, double* S);
+
+/* ---- learned sparse approximate inverse (SPAI) preconditioner ---- */
+/* The network maps per-vertex features through a vertex MLP, one mean-aggregation over
+ * neighbours, a diagonal head and a symmetric edge head to the values of a matrix M on
+ * the pattern of L-hat that is symmetric and strictly diagonally dominant with a
+ * positive diagonal, hence SPD; M approximates (L-hat - sigma I)^{-1}.
+ * Parameters are one flat FP32 vector of ISIRA_SPAI_NPARAM values (layout in the
+ * binding); the forward pass rounds them to BF16 and accumulates in FP32. */
+#define ISIRA_SPAI_F 8   /* vertex features */
+#define ISIRA_SPAI_H 16  /* hidden width */
+int32_t isira_spai_nparam(void);
+/* Compute M for (graph, sigma, trim) from params (device FP32) and install it in the
+ * context as the ISIRA_PC_LEARNED preconditioner. */
+int isira_spai_install(isira_ctx* ctx, const float* params, double sigma, int64_t trim);
+/* Export the installed M: diag (device n FP32, caller labels) and off-diagonal values
+ * (device nnz FP32) in the caller's CSR order. */
+int isira_spai_export(isira_ctx* ctx, float* diag, float* offd);
+/* Loss and gradient for a batch of samples: loss = (1/S) sum_s ||M r_s - z_s||^2 /
+ * ||z_s||^2 with r_s, z_s device n-by-S FP32 column-major (caller labels, trimmed entry
+ * 0).  grad: device FP32 (nparam), overwritten.  *loss: host. */
+int isira_spai_loss_grad(isira_ctx* ctx, const float* params, double sigma, int64_t trim,
+                         const float* r, const float* z, int32_t S, float* grad,
+                         double* loss);
+/* One Adam step on device FP32 vectors (param, grad, m, v of length count). */
+int isira_adam_step(isira_ctx* ctx, float* param, const float* grad, float* m, float* v,
+                    int32_t count, float lr, float beta1, float beta2, float eps,
+                    int32_t step);
+
+const char* isira_strerror(int code);
+const char* isira_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISIRA_H */

@@ -1,0 +1,1242 @@
+// Host side of the gfx950 iSIRA library: context creation (validation, connectivity,
+// relabelling, SpMV plan, degrees / trim index / delta on the GPU), the outer loop of
+// Algorithm 3.2, the inner PCG driver and the operator-level entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "spai.h"
+
+using namespace isira;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define CKH(expr)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ISIRA_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess)
+    return fail(ISIRA_E_HIP, std::string("hipMalloc(") + std::to_string(count * sizeof(T)) +
+                                 " bytes): " + hipGetErrorString(e));
+  return ISIRA_OK;
+}
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+int hw_threads() {
+  unsigned h = std::thread::hardware_concurrency();
+  return h == 0 ? 1 : (h > 16 ? 16 : (int)h);
+}
+
+template <typename F>
+void parallel_for(int64_t n, F f) {
+  const int nt = hw_threads();
+  if (n < 100000 || nt == 1) {
+    f(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int64_t b = t * chunk, e = std::min(n, b + chunk);
+    if (b < e) th.emplace_back([=] { f(b, e); });
+  }
+  for (auto& x : th) x.join();
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------ context
+
+struct isira_ctx {
+  int64_t n = 0, nnz = 0;
+  int ld = 0;  // leading dimension of dense n-by-m blocks
+  int wdt = ISIRA_W_NONE;
+  hipStream_t stream = nullptr;
+  std::vector<int32_t> perm, iperm;  // perm[new] = caller label, iperm[label] = new
+  // device graph (relabelled)
+  int32_t* rp = nullptr;
+  int32_t* col = nullptr;
+  double* w64 = nullptr;
+  float* w32 = nullptr;
+  double* deg = nullptr;
+  float* deg32 = nullptr;
+  int32_t* d_perm = nullptr;   // new -> label
+  int32_t* d_iperm = nullptr;  // label -> new
+  int32_t* d_emap = nullptr;   // internal stored entry -> caller entry index
+  SpmvPlan plan;
+  RedBuf rb{nullptr, nullptr};
+  DevState* st = nullptr;
+  DevState* st_host = nullptr;  // pinned
+  double* hbuf = nullptr;       // device kMaxCols
+  double* hbuf_host = nullptr;  // pinned kMaxCols
+  double* scal4 = nullptr;      // device 4
+  int trim_default = 0;         // internal index
+  int64_t trim_label = 0;
+  double max_deg = 0, min_deg = 0;
+  // solve workspace
+  int ws_m = 0, ws_k = 0;
+  double *U = nullptr, *W = nullptr, *Vout = nullptr;
+  double *Vin64 = nullptr, *Y64 = nullptr;
+  float *Vin32 = nullptr, *Y32 = nullptr;
+  double *r64 = nullptr, *z64 = nullptr, *tmp64 = nullptr;
+  double *x64 = nullptr, *ri64 = nullptr, *p64 = nullptr, *q64 = nullptr, *dinv64 = nullptr,
+         *y64 = nullptr;
+  float *x32 = nullptr, *ri32 = nullptr, *p32 = nullptr, *q32 = nullptr, *dinv32 = nullptr,
+        *y32 = nullptr;
+  double* svec = nullptr;  // device ISIRA_MAX_BASIS
+  double* Sdev = nullptr;  // device ISIRA_MAX_BASIS^2
+  double* Ginv = nullptr;  // device kMaxC^2
+  // learned preconditioner: values of M in internal order (spw.diag32/diag64/offd)
+  double spai_sigma = 0.0;
+  int spai_trim = -1;
+  bool has_learned = false;
+  spai::SpaiWork spw;
+};
+
+static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp) {
+  const int n = (int)ctx->n;
+  SpmvPlan& P = ctx->plan;
+  P.segs.nseg = 0;
+  auto lanes_for = [](int cnt) {
+    if (cnt > kSplitChunk) return -1;
+    if (cnt > kBlockRowMin) return kBlock;
+    int G = 1;
+    while (G < 64 && G * 4 < cnt) G <<= 1;
+    return G;
+  };
+  std::vector<int32_t> srow, schunk, sslot, sbase, snch;
+  int units = 0;
+  int row = 0;
+  int nchunks_total = 0;
+  while (row < n) {
+    const int G = lanes_for(rp[row + 1] - rp[row]);
+    int end = row;
+    while (end < n && lanes_for(rp[end + 1] - rp[end]) == G) ++end;
+    if (P.segs.nseg >= kMaxSegs) return fail(ISIRA_E_STATE, "too many SpMV segments");
+    SpmvSeg& sg = P.segs.s[P.segs.nseg++];
+    sg.row_begin = row;
+    sg.row_end = end;
+    sg.lanes = G;
+    sg.unit_begin = units;
+    if (G == -1) {
+      for (int r = row; r < end; ++r) {
+        const int cnt = rp[r + 1] - rp[r];
+        const int nch = (cnt + kSplitChunk - 1) / kSplitChunk;
+        const int slot = (int)sbase.size();
+        sbase.push_back(nchunks_total);
+        snch.push_back(nch);
+        for (int c = 0; c < nch; ++c) {
+          srow.push_back(r);
+          schunk.push_back(c);
+          sslot.push_back(slot);
+        }
+        nchunks_total += nch;
+        units += nch;
+      }
+    } else if (G == kBlock) {
+      units += end - row;
+    } else {
+      const int R = kBlock / G;
+      units += (end - row + R - 1) / R;
+    }
+    row = end;
+  }
+  P.segs.n_units = units;
+  P.grid = std::max(1, std::min(units, kSpmvGrid));
+  P.n_split_units = (int)srow.size();
+  P.n_split_rows = (int)sbase.size();
+  int rc;
+  if ((rc = dalloc(&P.split_row, srow.size()))) return rc;
+  if ((rc = dalloc(&P.split_chunk, srow.size()))) return rc;
+  if ((rc = dalloc(&P.split_slot, srow.size()))) return rc;
+  if ((rc = dalloc(&P.split_base, sbase.size()))) return rc;
+  if ((rc = dalloc(&P.split_nchunk, sbase.size()))) return rc;
+  if ((rc = dalloc(&P.split_cnt, sbase.size()))) return rc;
+  if ((rc = dalloc(&P.split_part, (size_t)nchunks_total))) return rc;
+  if ((rc = dalloc(&P.split_red, sbase.size()))) return rc;
+  if (!srow.empty()) {
+    CKH(hipMemcpy(P.split_row, srow.data(), srow.size() * 4, hipMemcpyHostToDevice));
+    CKH(hipMemcpy(P.split_chunk, schunk.data(), srow.size() * 4, hipMemcpyHostToDevice));
+    CKH(hipMemcpy(P.split_slot, sslot.data(), srow.size() * 4, hipMemcpyHostToDevice));
+    CKH(hipMemcpy(P.split_base, sbase.data(), sbase.size() * 4, hipMemcpyHostToDevice));
+    CKH(hipMemcpy(P.split_nchunk, snch.data(), sbase.size() * 4, hipMemcpyHostToDevice));
+    CKH(hipMemset(P.split_cnt, 0, sbase.size() * 4));
+    CKH(hipMemset(P.split_red, 0, sbase.size() * 8));
+  }
+  return ISIRA_OK;
+}
+
+static void free_workspace(isira_ctx* c) {
+  dfree(c->U); dfree(c->W); dfree(c->Vout); dfree(c->Vin64); dfree(c->Y64); dfree(c->Vin32);
+  dfree(c->Y32); dfree(c->r64); dfree(c->z64); dfree(c->tmp64); dfree(c->x64); dfree(c->ri64);
+  dfree(c->p64); dfree(c->q64); dfree(c->dinv64); dfree(c->y64); dfree(c->x32); dfree(c->ri32);
+  dfree(c->p32); dfree(c->q32); dfree(c->dinv32); dfree(c->y32);
+  c->ws_m = c->ws_k = 0;
+}
+
+static int ensure_workspace(isira_ctx* c, int m, int kmax) {
+  if (c->ws_m >= m && c->ws_k >= kmax && c->r64) return ISIRA_OK;
+  free_workspace(c);
+  const size_t ld = (size_t)c->ld;
+  int rc;
+  if ((rc = dalloc(&c->U, ld * m))) return rc;
+  if ((rc = dalloc(&c->W, ld * m))) return rc;
+  if ((rc = dalloc(&c->Vout, ld * kmax))) return rc;
+  if ((rc = dalloc(&c->Vin64, ld * kmax))) return rc;
+  if ((rc = dalloc(&c->Y64, ld * kmax))) return rc;
+  if ((rc = dalloc(&c->Vin32, ld * kmax))) return rc;
+  if ((rc = dalloc(&c->Y32, ld * kmax))) return rc;
+  for (double** p : {&c->r64, &c->z64, &c->tmp64, &c->x64, &c->ri64, &c->p64, &c->q64,
+                     &c->dinv64, &c->y64})
+    if ((rc = dalloc(p, ld))) return rc;
+  for (float** p : {&c->x32, &c->ri32, &c->p32, &c->q32, &c->dinv32, &c->y32})
+    if ((rc = dalloc(p, ld))) return rc;
+  c->ws_m = m;
+  c->ws_k = kmax;
+  return ISIRA_OK;
+}
+
+extern "C" int isira_default_options(isira_options* o) {
+  if (!o) return ISIRA_E_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->m = 0;
+  o->q = 0;
+  o->k0 = 4;
+  o->inner_rtol = 1e-4;
+  o->max_inner = 1000;
+  o->max_outer = 20000;
+  o->inner_prec = ISIRA_FP64;
+  o->precond = ISIRA_PC_JACOBI;
+  o->trim_index = -1;
+  o->delta = 0.0;
+  o->seed = 12345;
+  o->u0 = nullptr;
+  o->check_every = 8;
+  return ISIRA_OK;
+}
+
+static int validate_graph(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                          const void* w, int wdt, int check_sym) {
+  if (rp[0] != 0 || rp[n] != nnz) return fail(ISIRA_E_GRAPH, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+  std::atomic<int> bad{0};
+  std::atomic<int64_t> where{-1};
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e && !bad.load(std::memory_order_relaxed); ++i) {
+      const int s = rp[i], t = rp[i + 1];
+      if (t < s) { bad = 1; where = i; return; }
+      for (int j = s; j < t; ++j) {
+        const int c = col[j];
+        if (c < 0 || c >= n) { bad = 2; where = i; return; }
+        if (c == i) { bad = 3; where = i; return; }
+        if (j > s && col[j - 1] >= c) { bad = 4; where = i; return; }
+        if (wdt == ISIRA_W_F32) {
+          const float v = ((const float*)w)[j];
+          if (!(v > 0.0f) || !std::isfinite(v)) { bad = 5; where = i; return; }
+        } else if (wdt == ISIRA_W_F64) {
+          const double v = ((const double*)w)[j];
+          if (!(v > 0.0) || !std::isfinite(v)) { bad = 5; where = i; return; }
+        }
+        if (check_sym) {
+          const int32_t* lo = col + rp[c];
+          const int32_t* hi = col + rp[c + 1];
+          const int32_t* f = std::lower_bound(lo, hi, (int32_t)i);
+          if (f == hi || *f != i) { bad = 6; where = i; return; }
+          const int64_t jt = f - col;
+          if (wdt == ISIRA_W_F32 && ((const float*)w)[jt] != ((const float*)w)[j]) { bad = 7; where = i; return; }
+          if (wdt == ISIRA_W_F64 && ((const double*)w)[jt] != ((const double*)w)[j]) { bad = 7; where = i; return; }
+        }
+      }
+    }
+  });
+  static const char* msg[] = {"", "row_ptr decreasing", "column index out of range",
+                              "self loop", "columns not sorted/unique", "weight not positive",
+                              "pattern not symmetric", "weights not symmetric"};
+  if (bad) return fail(ISIRA_E_GRAPH, std::string(msg[bad.load()]) + " at row " + std::to_string(where.load()));
+  return ISIRA_OK;
+}
+
+static bool connected(int64_t n, const int32_t* rp, const int32_t* col) {
+  std::vector<uint8_t> seen(n, 0);
+  std::vector<int32_t> stack;
+  stack.reserve(1024);
+  stack.push_back(0);
+  seen[0] = 1;
+  int64_t count = 1;
+  while (!stack.empty()) {
+    const int v = stack.back();
+    stack.pop_back();
+    for (int j = rp[v]; j < rp[v + 1]; ++j) {
+      const int u = col[j];
+      if (!seen[u]) {
+        seen[u] = 1;
+        ++count;
+        stack.push_back(u);
+      }
+    }
+  }
+  return count == n;
+}
+
+extern "C" int isira_create(isira_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                            const int32_t* col, const void* w, int32_t w_dtype, void* stream,
+                            int32_t validate) {
+  if (!out) return fail(ISIRA_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 3 || n >= (1ll << 31) - 64 || nnz < 2 || nnz >= (1ll << 31) || !row_ptr || !col)
+    return fail(ISIRA_E_ARG, "need 3 <= n < 2^31, 2 <= nnz < 2^31 and non-NULL CSR arrays");
+  if (w_dtype != ISIRA_W_NONE && w_dtype != ISIRA_W_F32 && w_dtype != ISIRA_W_F64)
+    return fail(ISIRA_E_ARG, "bad w_dtype");
+  if (w_dtype != ISIRA_W_NONE && !w) return fail(ISIRA_E_ARG, "weights are NULL");
+  int rc = validate_graph(n, nnz, row_ptr, col, w, w_dtype, validate);
+  if (rc) return rc;
+  if (!connected(n, row_ptr, col)) return fail(ISIRA_E_DISCONNECTED, "graph is not connected");
+
+  isira_ctx* ctx = new isira_ctx();
+  ctx->n = n;
+  ctx->nnz = nnz;
+  ctx->ld = (int)((n + 63) / 64 * 64);
+  ctx->wdt = w_dtype;
+  ctx->stream = (hipStream_t)stream;
+  // relabel: stable sort by decreasing row length
+  std::vector<int32_t> cnt(n);
+  int32_t maxc = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    cnt[i] = row_ptr[i + 1] - row_ptr[i];
+    maxc = std::max(maxc, cnt[i]);
+  }
+  {
+    std::vector<int64_t> bucket((size_t)maxc + 2, 0);
+    for (int64_t i = 0; i < n; ++i) bucket[maxc - cnt[i] + 1]++;
+    for (size_t b = 1; b < bucket.size(); ++b) bucket[b] += bucket[b - 1];
+    ctx->perm.resize(n);
+    ctx->iperm.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t pos = bucket[maxc - cnt[i]]++;
+      ctx->perm[pos] = (int32_t)i;
+      ctx->iperm[i] = (int32_t)pos;
+    }
+  }
+  std::vector<int32_t> rp2(n + 1), col2(nnz);
+  rp2[0] = 0;
+  for (int64_t r = 0; r < n; ++r) rp2[r + 1] = rp2[r] + cnt[ctx->perm[r]];
+  std::vector<double> w2d;
+  std::vector<float> w2f;
+  if (w_dtype != ISIRA_W_NONE) {
+    w2d.resize(nnz);
+    w2f.resize(nnz);
+  }
+  std::vector<int32_t> emap(nnz);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    std::vector<std::pair<int32_t, int32_t>> tmp;
+    for (int64_t r = b; r < e; ++r) {
+      const int old = ctx->perm[r];
+      const int s = row_ptr[old], t = row_ptr[old + 1];
+      tmp.resize(t - s);
+      for (int j = s; j < t; ++j) tmp[j - s] = {ctx->iperm[col[j]], j};
+      std::sort(tmp.begin(), tmp.end());
+      const int o = rp2[r];
+      for (size_t j = 0; j < tmp.size(); ++j) {
+        col2[o + j] = tmp[j].first;
+        emap[o + j] = tmp[j].second;
+        double wv = 1.0;
+        if (w_dtype == ISIRA_W_F32) wv = ((const float*)w)[tmp[j].second];
+        if (w_dtype == ISIRA_W_F64) wv = ((const double*)w)[tmp[j].second];
+        if (w_dtype != ISIRA_W_NONE) {
+          w2d[o + j] = wv;
+          w2f[o + j] = (float)wv;
+        }
+      }
+    }
+  });
+  auto cleanup = [&](int code) {
+    isira_destroy(ctx);
+    return code;
+  };
+  if ((rc = dalloc(&ctx->rp, n + 1))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->col, nnz))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->deg, ctx->ld))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->deg32, ctx->ld))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->d_perm, n))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->d_iperm, n))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->d_emap, nnz))) return cleanup(rc);
+  if (w_dtype != ISIRA_W_NONE) {
+    if ((rc = dalloc(&ctx->w64, nnz))) return cleanup(rc);
+    if ((rc = dalloc(&ctx->w32, nnz))) return cleanup(rc);
+  }
+  const size_t npart = std::max((size_t)kMaxCols * kStreamGrid, (size_t)4 * kSpmvGrid);
+  if ((rc = dalloc(&ctx->rb.partials, npart))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->rb.counters, 64))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->st, 1))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->hbuf, kMaxCols))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->scal4, 4))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->svec, ISIRA_MAX_BASIS))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->Sdev, (size_t)ISIRA_MAX_BASIS * ISIRA_MAX_BASIS))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->Ginv, (size_t)kMaxC * kMaxC))) return cleanup(rc);
+  if (hipHostMalloc((void**)&ctx->st_host, sizeof(DevState)) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->hbuf_host, kMaxCols * sizeof(double)) != hipSuccess)
+    return cleanup(fail(ISIRA_E_HIP, "hipHostMalloc failed"));
+  hipStream_t s = ctx->stream;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  if (up(ctx->rp, rp2.data(), (n + 1) * 4) || up(ctx->col, col2.data(), nnz * 4) ||
+      up(ctx->d_perm, ctx->perm.data(), n * 4) || up(ctx->d_iperm, ctx->iperm.data(), n * 4) ||
+      up(ctx->d_emap, emap.data(), nnz * 4))
+    return cleanup(fail(ISIRA_E_HIP, "upload failed"));
+  if (w_dtype != ISIRA_W_NONE &&
+      (up(ctx->w64, w2d.data(), nnz * 8) || up(ctx->w32, w2f.data(), nnz * 4)))
+    return cleanup(fail(ISIRA_E_HIP, "weight upload failed"));
+  if (hipMemsetAsync(ctx->rb.counters, 0, 64 * sizeof(unsigned), s) ||
+      hipMemsetAsync(ctx->st, 0, sizeof(DevState), s) ||
+      hipMemsetAsync(ctx->deg, 0, ctx->ld * 8, s) || hipMemsetAsync(ctx->deg32, 0, ctx->ld * 4, s))
+    return cleanup(fail(ISIRA_E_HIP, "memset failed"));
+  if ((rc = build_plan(ctx, rp2))) return cleanup(rc);
+  // degrees, trim index (Remark 4.1(i)) and delta (Remark 4.1(ii)) on the GPU
+  launch_degree(ctx->rp, w_dtype == ISIRA_W_NONE ? nullptr : (w_dtype == ISIRA_W_F32 ? (const void*)ctx->w32 : (const void*)ctx->w64),
+                w_dtype == ISIRA_W_NONE ? ISIRA_W_NONE : (w_dtype == ISIRA_W_F32 ? ISIRA_W_F32 : ISIRA_W_F64),
+                (int)n, ctx->deg, ctx->deg32, s);
+  launch_argmax_degree(ctx->deg, ctx->d_perm, (int)n, ctx->st, ctx->rb, ctx->scal4, s);
+  double out4[4];
+  if (hipMemcpyAsync(out4, ctx->scal4, sizeof(out4), hipMemcpyDeviceToHost, s) ||
+      hipStreamSynchronize(s))
+    return cleanup(fail(ISIRA_E_HIP, std::string("setup kernels failed: ") + hipGetErrorString(hipGetLastError())));
+  ctx->max_deg = out4[0];
+  ctx->trim_default = (int)out4[1];
+  ctx->min_deg = out4[2];
+  ctx->trim_label = (int64_t)out4[3];
+  *out = ctx;
+  return ISIRA_OK;
+}
+
+extern "C" void isira_destroy(isira_ctx* c) {
+  if (!c) return;
+  free_workspace(c);
+  dfree(c->rp); dfree(c->col); dfree(c->w64); dfree(c->w32); dfree(c->deg); dfree(c->deg32);
+  dfree(c->d_perm); dfree(c->d_iperm); dfree(c->d_emap);
+  dfree(c->plan.split_row); dfree(c->plan.split_chunk); dfree(c->plan.split_slot);
+  dfree(c->plan.split_base); dfree(c->plan.split_nchunk); dfree(c->plan.split_cnt);
+  dfree(c->plan.split_part); dfree(c->plan.split_red);
+  dfree(c->rb.partials); dfree(c->rb.counters); dfree(c->st); dfree(c->hbuf); dfree(c->scal4);
+  dfree(c->svec); dfree(c->Sdev); dfree(c->Ginv);
+  spai::free_work(c->spw);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  if (c->hbuf_host) (void)hipHostFree(c->hbuf_host);
+  delete c;
+}
+
+extern "C" int isira_get_info(const isira_ctx* c, isira_info* info) {
+  if (!c || !info) return fail(ISIRA_E_ARG, "NULL argument");
+  info->n = c->n;
+  info->nnz = c->nnz;
+  info->trim_index = c->trim_label;
+  info->max_degree = c->max_deg;
+  info->min_degree = c->min_deg;
+  info->delta_default = 2.0 * c->max_deg;
+  info->norm1 = 2.0 * c->max_deg;
+  info->n_spmv_units = c->plan.segs.n_units;
+  info->n_spmv_blocks = c->plan.grid;
+  info->n_split_rows = c->plan.n_split_rows;
+  info->has_learned = c->has_learned ? 1 : 0;
+  return ISIRA_OK;
+}
+
+// ------------------------------------------------------------------------------ helpers
+
+namespace {
+
+int valmode64(const isira_ctx* c) { return c->wdt == ISIRA_W_NONE ? kUnitNeg : kF64Neg; }
+int valmode32(const isira_ctx* c) { return c->wdt == ISIRA_W_NONE ? kUnitNeg : kF32Neg; }
+
+// y = L x (+ delta V t) in FP64 on internal vectors; red: see SpmvArgs.
+void spmv64(isira_ctx* c, const double* x, double* y, const double* V, int nv,
+            const double* tvec, double delta, int red, double theta) {
+  SpmvArgs<double> a{};
+  a.rp = c->rp;
+  a.col = c->col;
+  a.vals = c->w64;
+  a.x = x;
+  a.y = y;
+  a.diag = c->deg;
+  a.n = (int)c->n;
+  a.trim = -1;
+  a.V = V;
+  a.ldv = c->ld;
+  a.c = nv;
+  a.tvec = tvec;
+  a.delta = delta;
+  a.red = red;
+  a.theta = theta;
+  a.st = c->st;
+  launch_spmv<double>(c->plan, valmode64(c), a, c->rb, c->stream);
+}
+
+int sync_state(isira_ctx* c) {
+  CKH(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+  CKH(hipStreamSynchronize(c->stream));
+  return ISIRA_OK;
+}
+
+int read_h(isira_ctx* c, int count) {
+  CKH(hipMemcpyAsync(c->hbuf_host, c->hbuf, count * sizeof(double), hipMemcpyDeviceToHost,
+                     c->stream));
+  return ISIRA_OK;
+}
+
+// G^{-1} for G = I + delta C (SPD, c x c) by Cholesky; column-major output.
+bool spd_inverse(int c, const std::vector<double>& G, std::vector<double>& Ginv) {
+  std::vector<double> L((size_t)c * c, 0.0);
+  for (int j = 0; j < c; ++j) {
+    double s = G[j + (size_t)j * c];
+    for (int t = 0; t < j; ++t) s -= L[j + (size_t)t * c] * L[j + (size_t)t * c];
+    if (!(s > 0.0)) return false;
+    const double ljj = std::sqrt(s);
+    L[j + (size_t)j * c] = ljj;
+    for (int i = j + 1; i < c; ++i) {
+      double v = G[i + (size_t)j * c];
+      for (int t = 0; t < j; ++t) v -= L[i + (size_t)t * c] * L[j + (size_t)t * c];
+      L[i + (size_t)j * c] = v / ljj;
+    }
+  }
+  Ginv.assign((size_t)c * c, 0.0);
+  for (int col = 0; col < c; ++col) {
+    std::vector<double> y(c, 0.0);
+    for (int i = 0; i < c; ++i) {  // L y = e_col
+      double v = (i == col) ? 1.0 : 0.0;
+      for (int t = 0; t < i; ++t) v -= L[i + (size_t)t * c] * y[t];
+      y[i] = v / L[i + (size_t)i * c];
+    }
+    for (int i = c - 1; i >= 0; --i) {  // L^T x = y
+      double v = y[i];
+      for (int t = i + 1; t < c; ++t) v -= L[t + (size_t)i * c] * Ginv[t + (size_t)col * c];
+      Ginv[i + (size_t)col * c] = v / L[i + (size_t)i * c];
+    }
+  }
+  return true;
+}
+
+// Inner-solve configuration of one solve.
+struct InnerCfg {
+  int prec;     // ISIRA_FP64 / ISIRA_FP32
+  int precond;  // ISIRA_PC_JACOBI / ISIRA_PC_LEARNED
+  double sigma, delta, rtol;
+  int trim;     // internal index
+  int maxit, check_every;
+};
+
+// Solve the trimmed shifted deflated system (2.15) for right-hand side r64 (internal order,
+// FP64, mean `mean` removed here) with c deflation columns already in Vin/Y and Ginv.
+// The solution (still trimmed, inner precision) is left in x32/x64.
+template <typename T>
+int inner_pcg(isira_ctx* c, const InnerCfg& cfg, const double* r64, double mean, int nc,
+              int* iters, int* status, double* relres) {
+  const int n = (int)c->n;
+  T *x, *r, *p, *q, *dinv, *y;
+  const T *V, *Y;
+  if constexpr (sizeof(T) == 8) {
+    x = c->x64; r = c->ri64; p = c->p64; q = c->q64; dinv = c->dinv64; y = c->y64;
+    V = c->Vin64; Y = c->Y64;
+  } else {
+    x = c->x32; r = c->ri32; p = c->p32; q = c->q32; dinv = c->dinv32; y = c->y32;
+    V = c->Vin32; Y = c->Y32;
+  }
+  hipStream_t s = c->stream;
+  DevState init{};
+  init.rtol2 = cfg.rtol * cfg.rtol;
+  init.maxit = cfg.maxit;
+  CKH(hipMemcpyAsync(c->st, &init, sizeof(DevState), hipMemcpyHostToDevice, s));
+  launch_rhs_prep<T>(n, r64, mean, cfg.trim, r, x, s);
+  const bool learned = cfg.precond == ISIRA_PC_LEARNED;
+  const int vm = sizeof(T) == 8 ? valmode64(c) : valmode32(c);
+  SpmvArgs<T> a{};
+  a.rp = c->rp;
+  a.col = c->col;
+  a.vals = sizeof(T) == 8 ? (const void*)c->w64 : (const void*)c->w32;
+  a.x = p;
+  a.y = q;
+  a.diag = sizeof(T) == 8 ? (const T*)c->deg : (const T*)c->deg32;
+  a.n = n;
+  a.trim = cfg.trim;
+  a.sigma = cfg.sigma;
+  a.sig_over_n = cfg.sigma / (double)n;
+  a.V = V;
+  a.ldv = c->ld;
+  a.c = nc;
+  a.tvec = nullptr;
+  a.delta = cfg.delta;
+  a.red = 1;
+  a.st = c->st;
+  a.check_done = 1;
+  // learned variant: y = M r with the dots V-hat^T y and r^T y, then eq. (3.5)
+  auto precond_apply = [&](int initflag) {
+    spai::apply<T>(c->spw, c->plan, c->rp, c->col, r, y, n, cfg.trim, V, c->ld, nc, c->st,
+                   c->rb, s);
+    launch_spai_finish_rho(nc, c->Ginv, cfg.delta, initflag, c->st, s);
+    launch_pcg_update2_learned<T>(n, y, p, Y, c->ld, nc, V, cfg.delta, initflag, c->st, c->rb, s);
+  };
+  if (learned) {
+    launch_pcg_update1_plain<T>(n, x, r, p, q, 1, c->st, c->rb, s);
+    precond_apply(1);
+  } else {
+    launch_pcg_update1<T>(n, x, r, p, q, dinv, V, c->ld, nc, c->Ginv, cfg.delta, 1, c->st, c->rb, s);
+    launch_pcg_update2<T>(n, r, p, dinv, V, c->ld, nc, cfg.delta, 1, c->st, c->rb, s);
+  }
+  int rc;
+  for (;;) {
+    for (int b = 0; b < cfg.check_every; ++b) {
+      launch_spmv<T>(c->plan, vm, a, c->rb, s);
+      if (learned) {
+        launch_pcg_update1_plain<T>(n, x, r, p, q, 0, c->st, c->rb, s);
+        precond_apply(0);
+      } else {
+        launch_pcg_update1<T>(n, x, r, p, q, dinv, V, c->ld, nc, c->Ginv, cfg.delta, 0, c->st, c->rb, s);
+        launch_pcg_update2<T>(n, r, p, dinv, V, c->ld, nc, cfg.delta, 0, c->st, c->rb, s);
+      }
+    }
+    if ((rc = sync_state(c))) return rc;
+    if (c->st_host->done) break;
+  }
+  *iters = c->st_host->it;
+  *status = c->st_host->status;
+  *relres = c->st_host->rr0 > 0 ? std::sqrt(c->st_host->rr / c->st_host->rr0) : 0.0;
+  return ISIRA_OK;
+}
+
+// Classical Gram-Schmidt twice against [U(:,0:nu) Vout(:,0:nv) 1/sqrt(n)] in place on z;
+// norms[0] = ||z|| before, norms[1] = after.
+int cgs2(isira_ctx* c, const double* U, int nu, const double* V, int nv, double* z,
+         double* norms) {
+  const int n = (int)c->n;
+  hipStream_t s = c->stream;
+  const int nc = nu + nv;
+  launch_multidot<double>(n, U, c->ld, nu, V, c->ld, nv, z, nullptr, 1, 1, c->hbuf, c->rb, s);
+  int rc;
+  if ((rc = read_h(c, nc + 2))) return rc;  // async; read after the stream sync below
+  launch_gemv_sub(n, U, c->ld, nu, V, c->ld, nv, c->hbuf, 1, z, 0, c->st, c->rb, s);
+  // the second pass reuses hbuf only after the copy above was queued (stream order)
+  double before2;
+  CKH(hipStreamSynchronize(s));
+  before2 = c->hbuf_host[nc + 1];
+  launch_multidot<double>(n, U, c->ld, nu, V, c->ld, nv, z, nullptr, 1, 0, c->hbuf, c->rb, s);
+  launch_gemv_sub(n, U, c->ld, nu, V, c->ld, nv, c->hbuf, 1, z, 1, c->st, c->rb, s);
+  if ((rc = sync_state(c))) return rc;
+  norms[0] = std::sqrt(std::max(0.0, before2));
+  norms[1] = std::sqrt(std::max(0.0, c->st_host->red[2]));
+  return ISIRA_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------ solve
+
+extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
+                           const isira_options* optp, double* evals, double* evecs,
+                           double* resid, isira_stats* stats) {
+  if (!c) return fail(ISIRA_E_ARG, "NULL context");
+  isira_options opt;
+  if (optp) opt = *optp; else isira_default_options(&opt);
+  const int n = (int)c->n;
+  const int q = opt.q > 0 ? opt.q : k + 10;
+  const int m = opt.m > 0 ? opt.m : 2 * q;
+  const int k0 = opt.k0 > 0 ? opt.k0 : 4;
+  if (k < 1 || k > ISIRA_MAX_K || k > n - 2) return fail(ISIRA_E_ARG, "need 1 <= k <= min(64, n-2)");
+  if (!(tol > 0.0)) return fail(ISIRA_E_ARG, "tol must be > 0");
+  if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
+  if (q < k || m <= q || m > ISIRA_MAX_BASIS || m + k > n - 1 || k0 >= m || k0 > n - 2)
+    return fail(ISIRA_E_ARG, "need k <= q < m <= 192, m + k <= n - 1 and k0 < m");
+  if (!evals || !evecs || !resid) return fail(ISIRA_E_ARG, "NULL output");
+  if (opt.inner_prec != ISIRA_FP64 && opt.inner_prec != ISIRA_FP32) return fail(ISIRA_E_ARG, "bad inner_prec");
+  if (opt.precond == ISIRA_PC_LEARNED && (!c->has_learned)) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
+  if (opt.precond != ISIRA_PC_JACOBI && opt.precond != ISIRA_PC_LEARNED) return fail(ISIRA_E_ARG, "bad precond");
+  int trim = c->trim_default;
+  if (opt.trim_index >= 0) {
+    if (opt.trim_index >= n) return fail(ISIRA_E_ARG, "trim_index out of range");
+    trim = c->iperm[opt.trim_index];
+  }
+  if (opt.precond == ISIRA_PC_LEARNED && (c->spai_trim != trim || c->spai_sigma != sigma))
+    return fail(ISIRA_E_PRECOND, "learned preconditioner was installed for another sigma or trim index");
+  const double delta = opt.delta > 0 ? opt.delta : 2.0 * c->max_deg;
+  int rc = ensure_workspace(c, m, k);
+  if (rc) return rc;
+  hipStream_t s = c->stream;
+  const int ld = c->ld;
+  isira_stats S{};
+  const double t_start = now_ms();
+  InnerCfg cfg;
+  cfg.prec = opt.inner_prec;
+  cfg.precond = opt.precond;
+  cfg.sigma = sigma;
+  cfg.delta = delta;
+  cfg.rtol = opt.inner_rtol > 0 ? opt.inner_rtol : 1e-4;
+  cfg.trim = trim;
+  cfg.maxit = opt.max_inner > 0 ? opt.max_inner : 1000;
+  cfg.check_every = opt.check_every > 0 ? opt.check_every : 8;
+  const int max_outer = opt.max_outer > 0 ? opt.max_outer : 20000;
+  // Jacobi inverse diagonal (Remark 3.2) in both precisions
+  launch_dinv<double>(n, c->deg, sigma, trim, c->dinv64, s);
+  launch_dinv<float>(n, c->deg, sigma, trim, c->dinv32, s);
+  uint64_t draws = 0;
+  int capture_count = 0;
+
+  // ---- start block: column means removed, orthonormalized (CGS2 against 1 and previous)
+  if (opt.u0) {
+    std::vector<double> col(n);
+    for (int j = 0; j < k0; ++j) {
+      CKH(hipMemcpyAsync(c->tmp64, opt.u0 + (size_t)j * n, (size_t)n * 8, hipMemcpyHostToDevice, s));
+      launch_gather<double, double>(n, c->tmp64, c->d_perm, c->z64, s);
+      // z64[new] = u0[perm[new]]
+      double nrm[2];
+      if ((rc = cgs2(c, c->U, j, c->Vout, 0, c->z64, nrm))) return rc;
+      while (!(nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0)) {
+        S.breakdowns++;
+        launch_fill_replacement(n, opt.seed, draws++, c->d_perm, c->z64, s);
+        if ((rc = cgs2(c, c->U, j, c->Vout, 0, c->z64, nrm))) return rc;
+      }
+      launch_scale(n, c->z64, 1.0 / nrm[1], c->U + (size_t)j * ld, s);
+    }
+  } else {
+    for (int j = 0; j < k0; ++j) {
+      double nrm[2];
+      do {
+        launch_fill_replacement(n, opt.seed, draws++, c->d_perm, c->z64, s);
+        if ((rc = cgs2(c, c->U, j, c->Vout, 0, c->z64, nrm))) return rc;
+      } while (!(nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0));
+      launch_scale(n, c->z64, 1.0 / nrm[1], c->U + (size_t)j * ld, s);
+    }
+  }
+  int kk = k0;  // current basis size
+  std::vector<double> H((size_t)m * m, 0.0);  // column-major, leading dimension m
+  for (int j = 0; j < kk; ++j) {
+    spmv64(c, c->U + (size_t)j * ld, c->W + (size_t)j * ld, nullptr, 0, nullptr, 0.0, 0, 0.0);
+    S.spmv_total++;
+  }
+  for (int j = 0; j < kk; ++j) {
+    launch_multidot<double>(n, c->U, ld, kk, nullptr, ld, 0, c->W + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+    if ((rc = read_h(c, kk))) return rc;
+    CKH(hipStreamSynchronize(s));
+    for (int i = 0; i < kk; ++i) H[i + (size_t)j * m] = c->hbuf_host[i];
+  }
+  for (int i = 0; i < kk; ++i)
+    for (int j = 0; j < i; ++j) {
+      const double v = 0.5 * (H[i + (size_t)j * m] + H[j + (size_t)i * m]);
+      H[i + (size_t)j * m] = H[j + (size_t)i * m] = v;
+    }
+
+  int nconv = 0;
+  std::vector<double> Hk, theta, Sm, Spack;
+  std::vector<double> Cmat;  // c x c Gram V-hat^T M^-1 V-hat (column-major, ld kMaxC)
+  Cmat.assign((size_t)kMaxC * kMaxC, 0.0);
+  int outer = 0;
+  int its_pair = 0;
+  int64_t inner_pair = 0;
+  bool not_conv = false;
+
+  auto refresh_smw = [&](int cnew) -> int {
+    // new column cnew of C = V-hat^T P0 V-hat (P0 = M^-1 Jacobi or learned M); then G^-1
+    const int cc = cnew + 1;
+    if (cfg.precond == ISIRA_PC_LEARNED) {
+      if (cfg.prec == ISIRA_FP64) {
+        spai::apply_plain<double>(c->spw, c->plan, c->rp, c->col,
+                                  c->Vin64 + (size_t)cnew * ld, c->Y64 + (size_t)cnew * ld, n, trim, s);
+        launch_multidot<double>(n, c->Vin64, ld, cc, nullptr, ld, 0, c->Y64 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+      } else {
+        spai::apply_plain<float>(c->spw, c->plan, c->rp, c->col,
+                                 c->Vin32 + (size_t)cnew * ld, c->Y32 + (size_t)cnew * ld, n, trim, s);
+        launch_multidot<float>(n, c->Vin32, ld, cc, nullptr, ld, 0, c->Y32 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+      }
+    } else if (cfg.prec == ISIRA_FP64) {
+      launch_multidot<double>(n, c->Vin64, ld, cc, nullptr, ld, 0, c->Vin64 + (size_t)cnew * ld, c->dinv64, 0, 0, c->hbuf, c->rb, s);
+    } else {
+      launch_multidot<float>(n, c->Vin32, ld, cc, nullptr, ld, 0, c->Vin32 + (size_t)cnew * ld, c->dinv32, 0, 0, c->hbuf, c->rb, s);
+    }
+    int r2 = read_h(c, cc);
+    if (r2) return r2;
+    CKH(hipStreamSynchronize(s));
+    for (int i = 0; i < cc; ++i) {
+      Cmat[i + (size_t)cnew * kMaxC] = c->hbuf_host[i];
+      Cmat[cnew + (size_t)i * kMaxC] = c->hbuf_host[i];
+    }
+    std::vector<double> G((size_t)cc * cc), Gi;
+    for (int j = 0; j < cc; ++j)
+      for (int i = 0; i < cc; ++i)
+        G[i + (size_t)j * cc] = (i == j ? 1.0 : 0.0) + delta * Cmat[i + (size_t)j * kMaxC];
+    if (!spd_inverse(cc, G, Gi)) return fail(ISIRA_E_PRECOND, "SMW capacitance matrix not positive definite");
+    CKH(hipMemcpyAsync(c->Ginv, Gi.data(), Gi.size() * 8, hipMemcpyHostToDevice, s));
+    CKH(hipStreamSynchronize(s));
+    return ISIRA_OK;
+  };
+
+  auto expand_with = [&](double* z) -> int {
+    // orthonormalize z against [U V 1] and append u, w = (L + delta V V^T) u, H column
+    double nrm[2];
+    int r2;
+    double t0 = now_ms();
+    if ((r2 = cgs2(c, c->U, kk, c->Vout, nconv, z, nrm))) return r2;
+    while (!(nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0)) {
+      S.breakdowns++;
+      launch_fill_replacement(n, opt.seed, draws++, c->d_perm, z, s);
+      if ((r2 = cgs2(c, c->U, kk, c->Vout, nconv, z, nrm))) return r2;
+    }
+    double* u = c->U + (size_t)kk * ld;
+    double* w = c->W + (size_t)kk * ld;
+    launch_scale(n, z, 1.0 / nrm[1], u, s);
+    S.ms_ortho += now_ms() - t0;
+    if (nconv > 0)
+      launch_multidot<double>(n, c->Vout, ld, nconv, nullptr, ld, 0, u, nullptr, 0, 0, c->hbuf, c->rb, s);
+    spmv64(c, u, w, c->Vout, nconv, c->hbuf, delta, 0, 0.0);
+    S.spmv_total++;
+    launch_multidot<double>(n, c->U, ld, kk + 1, nullptr, ld, 0, w, nullptr, 0, 0, c->hbuf, c->rb, s);
+    if ((r2 = read_h(c, kk + 1))) return r2;
+    CKH(hipStreamSynchronize(s));
+    for (int i = 0; i <= kk; ++i) {
+      H[i + (size_t)kk * m] = c->hbuf_host[i];
+      H[kk + (size_t)i * m] = c->hbuf_host[i];
+    }
+    kk += 1;
+    return ISIRA_OK;
+  };
+
+  while (nconv < k) {
+    if (outer >= max_outer) {
+      not_conv = true;
+      break;
+    }
+    outer++;
+    its_pair++;
+    // ---- Rayleigh-Ritz: all eigenpairs of H, ascending
+    double t0 = now_ms();
+    Hk.assign((size_t)kk * kk, 0.0);
+    for (int j = 0; j < kk; ++j)
+      for (int i = 0; i < kk; ++i) Hk[i + (size_t)j * kk] = H[i + (size_t)j * m];
+    theta.assign(kk, 0.0);
+    Sm.assign((size_t)kk * kk, 0.0);
+    if ((rc = isira_symeig(kk, Hk.data(), theta.data(), Sm.data())))
+      return fail(rc, "Rayleigh-Ritz eigensolver did not converge");
+    S.ms_rr_host += now_ms() - t0;
+    // ---- Ritz residual r = W s1 - theta1 U s1
+    t0 = now_ms();
+    CKH(hipMemcpyAsync(c->svec, Sm.data(), kk * 8, hipMemcpyHostToDevice, s));
+    launch_ritz_residual(n, c->U, c->W, ld, kk, c->svec, theta[0], c->r64, c->st, c->rb, s);
+    if ((rc = sync_state(c))) return rc;
+    const double rn = std::sqrt(std::max(0.0, c->st_host->red[0]));
+    const double rsum = c->st_host->red[1];
+    S.ms_residual += now_ms() - t0;
+    if (rn < tol) {
+      // fresh FP64 residual of the Ritz pair before locking
+      double* v = c->Vout + (size_t)nconv * ld;
+      launch_ritz_vector(n, c->U, ld, kk, c->svec, v, s);
+      spmv64(c, v, c->tmp64, nullptr, 0, nullptr, 0.0, 2, theta[0]);
+      S.spmv_total++;
+      if ((rc = sync_state(c))) return rc;
+      const double true_r = std::sqrt(std::max(0.0, c->st_host->red[0]));
+      if (true_r < tol) {
+        evals[nconv] = theta[0];
+        resid[nconv] = true_r;
+        if (nconv < ISIRA_STATS_MAX) {
+          S.outer_per_pair[nconv] = its_pair;
+          S.inner_per_pair[nconv] = (int32_t)inner_pair;
+        }
+        if (opt.verbose)
+          fprintf(stderr, "isira: pair %d lambda=%.15g resid=%.3e outer=%d inner=%lld\n", nconv,
+                  theta[0], true_r, its_pair, (long long)inner_pair);
+        its_pair = 0;
+        inner_pair = 0;
+        launch_masked_copy<double>(n, v, trim, c->Vin64 + (size_t)nconv * ld, s);
+        launch_masked_copy<float>(n, v, trim, c->Vin32 + (size_t)nconv * ld, s);
+        // eigenvector purging: U <- U S(:, 2:k), W <- W S(:, 2:k), H <- diag(theta_2..)
+        t0 = now_ms();
+        if (kk > 1) {
+          Spack.assign((size_t)kk * (kk - 1), 0.0);
+          for (int j = 1; j < kk; ++j)
+            for (int i = 0; i < kk; ++i) Spack[i + (size_t)(j - 1) * kk] = Sm[i + (size_t)j * kk];
+          CKH(hipMemcpyAsync(c->Sdev, Spack.data(), Spack.size() * 8, hipMemcpyHostToDevice, s));
+          launch_tsgemm_inplace(n, c->U, ld, kk, c->Sdev, kk - 1, s);
+          launch_tsgemm_inplace(n, c->W, ld, kk, c->Sdev, kk - 1, s);
+        }
+        std::fill(H.begin(), H.end(), 0.0);
+        for (int j = 1; j < kk; ++j) H[(j - 1) + (size_t)(j - 1) * m] = theta[j];
+        kk -= 1;
+        S.ms_restart += now_ms() - t0;
+        nconv += 1;
+        if (nconv < k) {
+          if ((rc = refresh_smw(nconv - 1))) return rc;
+          if (kk == 0) {  // empty basis: start again from a replacement vector
+            launch_fill_replacement(n, opt.seed, draws++, c->d_perm, c->z64, s);
+            if ((rc = expand_with(c->z64))) return rc;
+          }
+        }
+        continue;
+      }
+      // the carried W has drifted: recompute W = (L + delta V V^T) U and H = U^T W
+      S.refreshes++;
+      for (int j = 0; j < kk; ++j) {
+        if (nconv > 0)
+          launch_multidot<double>(n, c->Vout, ld, nconv, nullptr, ld, 0, c->U + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+        spmv64(c, c->U + (size_t)j * ld, c->W + (size_t)j * ld, c->Vout, nconv, c->hbuf, delta, 0, 0.0);
+        S.spmv_total++;
+      }
+      for (int j = 0; j < kk; ++j) {
+        launch_multidot<double>(n, c->U, ld, kk, nullptr, ld, 0, c->W + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+        if ((rc = read_h(c, kk))) return rc;
+        CKH(hipStreamSynchronize(s));
+        for (int i = 0; i < kk; ++i) H[i + (size_t)j * m] = c->hbuf_host[i];
+      }
+      for (int i = 0; i < kk; ++i)
+        for (int j = 0; j < i; ++j) {
+          const double v2 = 0.5 * (H[i + (size_t)j * m] + H[j + (size_t)i * m]);
+          H[i + (size_t)j * m] = H[j + (size_t)i * m] = v2;
+        }
+      continue;
+    }
+    if (kk == m) {
+      // subspace restart: U <- U S(:, 1:q), W <- W S(:, 1:q), H <- diag(theta_1..theta_q)
+      t0 = now_ms();
+      S.restarts++;
+      CKH(hipMemcpyAsync(c->Sdev, Sm.data(), (size_t)kk * q * 8, hipMemcpyHostToDevice, s));
+      launch_tsgemm_inplace(n, c->U, ld, kk, c->Sdev, q, s);
+      launch_tsgemm_inplace(n, c->W, ld, kk, c->Sdev, q, s);
+      std::fill(H.begin(), H.end(), 0.0);
+      for (int j = 0; j < q; ++j) H[j + (size_t)j * m] = theta[j];
+      kk = q;
+      S.ms_restart += now_ms() - t0;
+    }
+    // ---- subspace expansion: trimmed deflated inner solve, enlargement (2.5)
+    t0 = now_ms();
+    int its = 0, status = 0;
+    double rel = 0.0;
+    const double mean = rsum / (double)n;
+    if (cfg.prec == ISIRA_FP64) {
+      rc = inner_pcg<double>(c, cfg, c->r64, mean, nconv, &its, &status, &rel);
+    } else {
+      rc = inner_pcg<float>(c, cfg, c->r64, mean, nconv, &its, &status, &rel);
+    }
+    if (rc) return rc;
+    if (status == kPcgBreakdown) S.inner_fallbacks++;
+    if (status == kPcgCapped) S.inner_capped++;
+    S.inner_total += its;
+    S.spmv_total += its;
+    inner_pair += its;
+    if (cfg.prec == ISIRA_FP64) {
+      launch_enlarge<double>(n, c->x64, c->z64, c->st, c->rb, s);
+    } else {
+      launch_enlarge<float>(n, c->x32, c->z64, c->st, c->rb, s);
+    }
+    if (opt.capture_r && opt.capture_z && opt.capture_count && capture_count < opt.capture_cap) {
+      double* cr = opt.capture_r + (size_t)capture_count * n;
+      double* cz = opt.capture_z + (size_t)capture_count * n;
+      // z_hat (trimmed entry 0) and r' = (L-hat - sigma I) z_hat: the pair that an
+      // approximate inverse of L-hat - sigma I should map onto each other
+      const double* zin = c->x64;
+      if (cfg.prec != ISIRA_FP64) {
+        launch_gather<float, double>(n, c->x32, c->d_iperm, cz, s);
+        launch_gather<double, double>(n, cz, c->d_perm, c->y64, s);
+        zin = c->y64;
+      } else {
+        launch_gather<double, double>(n, c->x64, c->d_iperm, cz, s);
+      }
+      SpmvArgs<double> ca{};
+      ca.rp = c->rp; ca.col = c->col; ca.vals = c->w64; ca.x = zin; ca.y = c->tmp64;
+      ca.diag = c->deg; ca.n = n; ca.trim = trim; ca.sigma = sigma;
+      launch_spmv<double>(c->plan, valmode64(c), ca, c->rb, s);
+      launch_gather<double, double>(n, c->tmp64, c->d_iperm, cr, s);
+      capture_count++;
+      *opt.capture_count = capture_count;
+    }
+    S.ms_inner += now_ms() - t0;
+    if ((rc = expand_with(c->z64))) return rc;
+  }
+  // ---- outputs: sign-normalized eigenvectors in caller labels
+  for (int j = 0; j < nconv; ++j) {
+    double* v = c->Vout + (size_t)j * ld;
+    launch_signed_gather(n, v, c->d_perm, c->d_iperm, evecs + (size_t)j * n, c->scal4, c->rb, s);
+  }
+  CKH(hipStreamSynchronize(s));
+  S.n_converged = nconv;
+  S.outer_total = outer;
+  S.ms_total = now_ms() - t_start;
+  S.trim_index = c->perm[trim];
+  S.delta = delta;
+  if (stats) *stats = S;
+  return not_conv ? ISIRA_NOT_CONVERGED : ISIRA_OK;
+}
+
+// ------------------------------------------------------------------------------ operators
+
+extern "C" int isira_laplacian_apply(isira_ctx* c, const double* x, double* y) {
+  if (!c || !x || !y) return fail(ISIRA_E_ARG, "NULL argument");
+  int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
+  if (rc) return rc;
+  const int n = (int)c->n;
+  launch_gather<double, double>(n, x, c->d_perm, c->x64, c->stream);
+  spmv64(c, c->x64, c->y64, nullptr, 0, nullptr, 0.0, 0, 0.0);
+  launch_gather<double, double>(n, c->y64, c->d_iperm, y, c->stream);
+  CKH(hipStreamSynchronize(c->stream));
+  return ISIRA_OK;
+}
+
+extern "C" int isira_laplacian_apply_f32(isira_ctx* c, const float* x, float* y) {
+  if (!c || !x || !y) return fail(ISIRA_E_ARG, "NULL argument");
+  int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
+  if (rc) return rc;
+  const int n = (int)c->n;
+  launch_gather<float, float>(n, x, c->d_perm, c->x32, c->stream);
+  SpmvArgs<float> a{};
+  a.rp = c->rp;
+  a.col = c->col;
+  a.vals = c->w32;
+  a.x = c->x32;
+  a.y = c->y32;
+  a.diag = c->deg32;
+  a.n = n;
+  a.trim = -1;
+  launch_spmv<float>(c->plan, valmode32(c), a, c->rb, c->stream);
+  launch_gather<float, float>(n, c->y32, c->d_iperm, y, c->stream);
+  CKH(hipStreamSynchronize(c->stream));
+  return ISIRA_OK;
+}
+
+extern "C" int isira_time_spmv(isira_ctx* c, int32_t prec, int32_t reps, double* ms_per) {
+  if (!c || reps < 1 || !ms_per) return fail(ISIRA_E_ARG, "bad argument");
+  int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
+  if (rc) return rc;
+  const int n = (int)c->n;
+  hipStream_t s = c->stream;
+  launch_fill_replacement(n, 7, 0, c->d_perm, c->x64, s);
+  launch_gather<double, float>(n, c->x64, c->d_iperm, c->x32, s);  // any FP32 data will do
+  hipEvent_t e0, e1;
+  CKH(hipEventCreate(&e0));
+  CKH(hipEventCreate(&e1));
+  SpmvArgs<float> a32{};
+  a32.rp = c->rp; a32.col = c->col; a32.vals = c->w32; a32.x = c->x32; a32.y = c->y32;
+  a32.diag = c->deg32; a32.n = n; a32.trim = -1;
+  for (int w = 0; w < 3; ++w) {
+    if (prec == ISIRA_FP64) spmv64(c, c->x64, c->y64, nullptr, 0, nullptr, 0.0, 0, 0.0);
+    else launch_spmv<float>(c->plan, valmode32(c), a32, c->rb, s);
+  }
+  CKH(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) {
+    if (prec == ISIRA_FP64) spmv64(c, c->x64, c->y64, nullptr, 0, nullptr, 0.0, 0, 0.0);
+    else launch_spmv<float>(c->plan, valmode32(c), a32, c->rb, s);
+  }
+  CKH(hipEventRecord(e1, s));
+  CKH(hipEventSynchronize(e1));
+  float ms = 0;
+  CKH(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_per = ms / reps;
+  return ISIRA_OK;
+}
+
+extern "C" int isira_inner_solve(isira_ctx* c, const double* r, const double* V, int32_t nc,
+                                 double sigma, double delta, int64_t trim, double rtol,
+                                 int32_t max_it, int32_t prec, int32_t precond, double* z,
+                                 int32_t* iters, double* relres) {
+  if (!c || !r || !z || (nc > 0 && !V)) return fail(ISIRA_E_ARG, "NULL argument");
+  if (nc < 0 || nc > kMaxC || nc > c->n - 3) return fail(ISIRA_E_ARG, "bad c");
+  if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
+  if (prec != ISIRA_FP64 && prec != ISIRA_FP32) return fail(ISIRA_E_ARG, "bad prec");
+  if (precond == ISIRA_PC_LEARNED && !c->has_learned) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
+  int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, std::max(1, (int)nc)));
+  if (rc) return rc;
+  const int n = (int)c->n;
+  const int ld = c->ld;
+  hipStream_t s = c->stream;
+  InnerCfg cfg;
+  cfg.prec = prec;
+  cfg.precond = precond;
+  cfg.sigma = sigma;
+  cfg.delta = delta > 0 ? delta : 2.0 * c->max_deg;
+  cfg.rtol = rtol;
+  cfg.trim = trim >= 0 ? c->iperm[trim] : c->trim_default;
+  if (precond == ISIRA_PC_LEARNED && (c->spai_trim != cfg.trim || c->spai_sigma != sigma))
+    return fail(ISIRA_E_PRECOND, "learned preconditioner was installed for another sigma or trim index");
+  cfg.maxit = max_it > 0 ? max_it : 1000;
+  cfg.check_every = 8;
+  launch_dinv<double>(n, c->deg, sigma, cfg.trim, c->dinv64, s);
+  launch_dinv<float>(n, c->deg, sigma, cfg.trim, c->dinv32, s);
+  // deflation columns (internal order, trimmed row zeroed) and the SMW capacitance
+  std::vector<double> Cm((size_t)nc * nc);
+  for (int j = 0; j < nc; ++j) {
+    launch_gather<double, double>(n, V + (size_t)j * n, c->d_perm, c->tmp64, s);
+    launch_masked_copy<double>(n, c->tmp64, cfg.trim, c->Vin64 + (size_t)j * ld, s);
+    launch_masked_copy<float>(n, c->tmp64, cfg.trim, c->Vin32 + (size_t)j * ld, s);
+  }
+  for (int j = 0; j < nc; ++j) {
+    if (precond == ISIRA_PC_LEARNED) {
+      if (prec == ISIRA_FP64) {
+        spai::apply_plain<double>(c->spw, c->plan, c->rp, c->col,
+                                  c->Vin64 + (size_t)j * ld, c->Y64 + (size_t)j * ld, n, cfg.trim, s);
+        launch_multidot<double>(n, c->Vin64, ld, nc, nullptr, ld, 0, c->Y64 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+      } else {
+        spai::apply_plain<float>(c->spw, c->plan, c->rp, c->col,
+                                 c->Vin32 + (size_t)j * ld, c->Y32 + (size_t)j * ld, n, cfg.trim, s);
+        launch_multidot<float>(n, c->Vin32, ld, nc, nullptr, ld, 0, c->Y32 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+      }
+    } else if (prec == ISIRA_FP64) {
+      launch_multidot<double>(n, c->Vin64, ld, nc, nullptr, ld, 0, c->Vin64 + (size_t)j * ld, c->dinv64, 0, 0, c->hbuf, c->rb, s);
+    } else {
+      launch_multidot<float>(n, c->Vin32, ld, nc, nullptr, ld, 0, c->Vin32 + (size_t)j * ld, c->dinv32, 0, 0, c->hbuf, c->rb, s);
+    }
+    if ((rc = read_h(c, nc))) return rc;
+    CKH(hipStreamSynchronize(s));
+    for (int i = 0; i < nc; ++i) Cm[i + (size_t)j * nc] = c->hbuf_host[i];
+  }
+  if (nc > 0) {
+    std::vector<double> G((size_t)nc * nc), Gi;
+    for (int j = 0; j < nc; ++j)
+      for (int i = 0; i < nc; ++i)
+        G[i + (size_t)j * nc] = (i == j ? 1.0 : 0.0) + cfg.delta * 0.5 * (Cm[i + (size_t)j * nc] + Cm[j + (size_t)i * nc]);
+    if (!spd_inverse(nc, G, Gi)) return fail(ISIRA_E_PRECOND, "SMW capacitance matrix not positive definite");
+    CKH(hipMemcpyAsync(c->Ginv, Gi.data(), Gi.size() * 8, hipMemcpyHostToDevice, s));
+  }
+  CKH(hipMemcpyAsync(c->tmp64, r, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+  launch_gather<double, double>(n, c->tmp64, c->d_perm, c->r64, s);
+  int its = 0, status = 0;
+  double rel = 0.0;
+  if (prec == ISIRA_FP64) rc = inner_pcg<double>(c, cfg, c->r64, 0.0, nc, &its, &status, &rel);
+  else rc = inner_pcg<float>(c, cfg, c->r64, 0.0, nc, &its, &status, &rel);
+  if (rc) return rc;
+  if (prec == ISIRA_FP64) launch_enlarge<double>(n, c->x64, c->z64, c->st, c->rb, s);
+  else launch_enlarge<float>(n, c->x32, c->z64, c->st, c->rb, s);
+  launch_gather<double, double>(n, c->z64, c->d_iperm, z, s);
+  CKH(hipStreamSynchronize(s));
+  if (iters) *iters = its;
+  if (relres) *relres = rel;
+  return ISIRA_OK;
+}
+
+extern "C" int isira_orthonormalize(isira_ctx* c, const double* Q, int32_t ncols,
+                                    const double* z, double* u, double* norms) {
+  if (!c || !z || !u || !norms || (ncols > 0 && !Q)) return fail(ISIRA_E_ARG, "NULL argument");
+  if (ncols < 0 || ncols > ISIRA_MAX_BASIS) return fail(ISIRA_E_ARG, "bad ncols");
+  int rc = ensure_workspace(c, std::max(c->ws_m, ncols + 1), std::max(c->ws_k, 1));
+  if (rc) return rc;
+  const int n = (int)c->n;
+  const int ld = c->ld;
+  hipStream_t s = c->stream;
+  for (int j = 0; j < ncols; ++j) launch_gather<double, double>(n, Q + (size_t)j * n, c->d_perm, c->U + (size_t)j * ld, s);
+  launch_gather<double, double>(n, z, c->d_perm, c->z64, s);
+  if ((rc = cgs2(c, c->U, ncols, c->Vout, 0, c->z64, norms))) return rc;
+  launch_scale(n, c->z64, norms[1] > 0 ? 1.0 / norms[1] : 0.0, c->tmp64, s);
+  launch_gather<double, double>(n, c->tmp64, c->d_iperm, u, s);
+  CKH(hipStreamSynchronize(s));
+  return ISIRA_OK;
+}
+
+// ------------------------------------------------------------------------------ learned SPAI
+
+extern "C" int32_t isira_spai_nparam(void) { return spai::nparam(); }
+
+static int spai_trim_internal(const isira_ctx* c, int64_t trim, int* out) {
+  if (trim >= c->n) return fail(ISIRA_E_ARG, "trim index out of range");
+  *out = trim >= 0 ? c->iperm[trim] : c->trim_default;
+  return ISIRA_OK;
+}
+
+extern "C" int isira_spai_install(isira_ctx* c, const float* params, double sigma, int64_t trim) {
+  if (!c || !params) return fail(ISIRA_E_ARG, "NULL argument");
+  if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
+  int t, rc;
+  if ((rc = spai_trim_internal(c, trim, &t))) return rc;
+  const void* wts = c->wdt == ISIRA_W_NONE ? nullptr : (const void*)c->w32;
+  const int wdt = c->wdt == ISIRA_W_NONE ? ISIRA_W_NONE : ISIRA_W_F32;
+  if (spai::forward(c->spw, c->rp, c->col, wts, wdt, c->deg, (int)c->n, c->nnz, sigma, t, params,
+                    c->stream))
+    return fail(ISIRA_E_HIP, "SPAI forward failed");
+  CKH(hipStreamSynchronize(c->stream));
+  c->has_learned = true;
+  c->spai_sigma = sigma;
+  c->spai_trim = t;
+  return ISIRA_OK;
+}
+
+extern "C" int isira_spai_export(isira_ctx* c, float* diag, float* offd) {
+  if (!c || !diag || !offd) return fail(ISIRA_E_ARG, "NULL argument");
+  if (!c->has_learned) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
+  launch_gather<float, float>((int)c->n, c->spw.diag32, c->d_iperm, diag, c->stream);
+  spai::scatter_offd(c->nnz, c->spw.offd, c->d_emap, offd, c->stream);
+  CKH(hipStreamSynchronize(c->stream));
+  return ISIRA_OK;
+}
+
+extern "C" int isira_spai_loss_grad(isira_ctx* c, const float* params, double sigma, int64_t trim,
+                                    const float* r, const float* z, int32_t S, float* grad,
+                                    double* loss) {
+  if (!c || !params || !r || !z || !grad || !loss) return fail(ISIRA_E_ARG, "NULL argument");
+  if (S < 1 || S > 64) return fail(ISIRA_E_ARG, "need 1 <= S <= 64 samples per call");
+  if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
+  int t, rc;
+  if ((rc = spai_trim_internal(c, trim, &t))) return rc;
+  const void* wts = c->wdt == ISIRA_W_NONE ? nullptr : (const void*)c->w32;
+  const int wdt = c->wdt == ISIRA_W_NONE ? ISIRA_W_NONE : ISIRA_W_F32;
+  c->has_learned = false;  // the forward pass below overwrites the installed values
+  if (spai::loss_grad(c->spw, c->rp, c->col, wts, wdt, c->deg, (int)c->n, c->nnz, sigma, t, params,
+                      c->d_perm, r, z, S, grad, loss, c->rb, c->stream))
+    return fail(ISIRA_E_HIP, "SPAI loss/gradient failed");
+  return ISIRA_OK;
+}
+
+extern "C" int isira_adam_step(isira_ctx* c, float* param, const float* grad, float* m, float* v,
+                               int32_t count, float lr, float beta1, float beta2, float eps,
+                               int32_t step) {
+  if (!c || !param || !grad || !m || !v || count < 1 || step < 1) return fail(ISIRA_E_ARG, "bad argument");
+  spai::adam(param, grad, m, v, count, lr, beta1, beta2, eps, step, c->stream);
+  CKH(hipStreamSynchronize(c->stream));
+  return ISIRA_OK;
+}
+
+extern "C" const char* isira_strerror(int code) {
+  switch (code) {
+    case ISIRA_OK: return "ok";
+    case ISIRA_NOT_CONVERGED: return "not converged (max_outer reached)";
+    case ISIRA_E_ARG: return "invalid argument";
+    case ISIRA_E_GRAPH: return "invalid graph";
+    case ISIRA_E_DISCONNECTED: return "graph not connected";
+    case ISIRA_E_HIP: return "HIP runtime error";
+    case ISIRA_E_PRECOND: return "preconditioner error";
+    case ISIRA_E_STATE: return "invalid state";
+    default: return "unknown error";
+  }
+}
+
+extern "C" const char* isira_last_error(void) { return g_err.c_str(); }
+
+// shared with spai.hip
+namespace isira {
+int set_error(int code, const char* msg) { return fail(code, msg); }
+}

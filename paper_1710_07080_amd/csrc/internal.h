@@ -1,0 +1,164 @@
+// Internal declarations of the gfx950 iSIRA library: device state, SpMV plan, launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "isira.h"
+
+namespace isira {
+
+constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
+constexpr int kStreamGrid = 1024;      // max workgroups of grid-stride streaming kernels
+constexpr int kSpmvGrid = 2048;        // max workgroups of the persistent SpMV grid
+constexpr int kSplitChunk = 4096;      // nnz per chunk of a split (very long) row
+constexpr int kBlockRowMin = 1024;     // rows longer than this get a whole workgroup
+constexpr int kMaxSegs = 16;           // SpMV segments (row-length classes)
+constexpr int kMaxC = ISIRA_MAX_K;     // deflation columns in the inner solve
+constexpr int kTile = 512;             // rows per tile of the column-dot kernels
+constexpr int kMaxCols = 2 * ISIRA_MAX_BASIS + 2;  // columns of one multi-dot
+
+// One row-length class of the SpMV: rows [row_begin, row_end) of the relabelled graph.
+// lanes in 1..64: `lanes` lanes per row, 256/lanes rows per unit; 256: one workgroup per
+// row; -1: split rows (units are chunks of kSplitChunk nonzeros).
+struct SpmvSeg {
+  int32_t row_begin, row_end, lanes, unit_begin;
+};
+
+struct SpmvSegs {
+  SpmvSeg s[kMaxSegs];
+  int32_t nseg;
+  int32_t n_units;
+};
+
+// Scalars of the inner PCG and of the outer reductions, living in device memory.
+struct DevState {
+  double alpha, beta, rho, pq, rr, rr0, rmr, thresh2, rtol2, sump, sumx;
+  double red[4];  // generic reduction outputs
+  int32_t it, done, status, maxit;
+  double t1[kMaxC];  // V-hat^T p
+  double t2[kMaxC + 1];  // V-hat^T (M^-1 r); learned variant: [V-hat^T y, r^T y]
+  double g[kMaxC];   // G^{-1} t2
+};
+
+enum PcgStatus { kPcgOk = 0, kPcgCapped = 1, kPcgBreakdown = 2 };
+
+// Reduction scratch shared by kernels on one stream (kernels run one after another).
+struct RedBuf {
+  double* partials;   // kMaxCols * kSpmvGrid doubles
+  unsigned* counters; // 64 counters, zeroed at creation and reset by each last workgroup
+};
+
+// SpMV execution plan (device arrays for split rows).
+struct SpmvPlan {
+  SpmvSegs segs;
+  int32_t grid = 0;
+  int32_t n_split_units = 0, n_split_rows = 0;
+  int32_t* split_row = nullptr;    // per split unit: row
+  int32_t* split_chunk = nullptr;  // per split unit: chunk index within the row
+  int32_t* split_slot = nullptr;   // per split unit: slot of its row (0..n_split_rows-1)
+  int32_t* split_base = nullptr;   // per split row slot: first chunk partial index
+  int32_t* split_nchunk = nullptr; // per split row slot: number of chunks
+  unsigned* split_cnt = nullptr;   // per split row slot: arrival counter
+  double* split_part = nullptr;    // per chunk partial neighbour sums
+  double* split_red = nullptr;     // per split row slot: reduction contribution
+};
+
+// Value mode of the sparse product y = diag .* x + sgn * sum_j v_ij x_j.
+enum ValMode { kUnitNeg = 0, kF32Neg = 1, kF64Neg = 2, kF32Pos = 3 };
+
+// Arguments of the fused sparse product.
+template <typename T>
+struct SpmvArgs {
+  const int32_t* rp;
+  const int32_t* col;
+  const void* vals;    // weights (kF32Neg/kF64Neg) or learned values (kF32Pos)
+  const T* x;
+  T* y;
+  const T* diag;
+  int32_t n;
+  int32_t trim;        // row forced to zero (-1: none)
+  double sigma;        // y -= sigma x
+  double sig_over_n;   // y += sig_over_n * st->sump
+  const T* V;          // y += delta * V t, t = st->t1 (inner) or tvec
+  int64_t ldv;
+  int32_t c;
+  const double* tvec;
+  double delta;
+  int32_t red;         // 0 none; 1 PCG p^T q -> alpha; 2 ||y - theta x||^2 -> st->red[0];
+                       // 3 x^T y -> st->red[1]
+  double theta;
+  DevState* st;
+  int32_t check_done;  // return at once when st->done
+};
+
+// ---- launchers (kernels.hip) ----
+void launch_degree(const int32_t* rp, const void* w, int wdt, int n, double* d, float* d32,
+                   hipStream_t s);
+void launch_argmax_degree(const double* d, const int32_t* perm, int n, DevState* st,
+                          RedBuf rb, double* out3, hipStream_t s);
+
+template <typename T>
+void launch_spmv(const SpmvPlan& plan, int valmode, const SpmvArgs<T>& a, RedBuf rb,
+                 hipStream_t s);
+
+template <typename T>
+void launch_pcg_update1(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const T* V,
+                        int64_t ldv, int c, const double* Ginv, double delta, int init,
+                        DevState* st, RedBuf rb, hipStream_t s);
+template <typename T>
+void launch_pcg_update2(int n, const T* r, T* p, const T* dinv, const T* V, int64_t ldv,
+                        int c, double delta, int init, DevState* st, RedBuf rb, hipStream_t s);
+// learned preconditioner variants: update1 without the Jacobi dots; apply y = M r with
+// the SMW dots; update2 with z = y - delta Y g.
+template <typename T>
+void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, int init,
+                              DevState* st, RedBuf rb, hipStream_t s);
+template <typename T>
+void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv, int c,
+                                const T* V, double delta, int init, DevState* st, RedBuf rb,
+                                hipStream_t s);
+void launch_spai_finish_rho(int c, const double* Ginv, double delta, int init, DevState* st,
+                            hipStream_t s);
+
+template <typename T>
+void launch_rhs_prep(int n, const double* r64, double mean, int trim, T* rin, T* x,
+                     hipStream_t s);
+template <typename T>
+void launch_enlarge(int n, const T* x, double* z, DevState* st, RedBuf rb, hipStream_t s);
+
+// Column dots h_j = sum_l A[l,j] * (w_l * z_l), j < na, then B, then (optional) sum z,
+// then (optional) z^T z.  Result into h (device).
+template <typename T>
+void launch_multidot(int n, const T* A, int64_t lda, int na, const T* B, int64_t ldb, int nb,
+                     const T* z, const T* wz, int with_sum, int with_self, double* h,
+                     RedBuf rb, hipStream_t s);
+// z -= A hA + B hB + (with_sum ? h_sum/n : 0); optional ||z||^2 into st->red[2].
+void launch_gemv_sub(int n, const double* A, int64_t lda, int na, const double* B,
+                     int64_t ldb, int nb, const double* h, int with_sum, double* z,
+                     int with_norm, DevState* st, RedBuf rb, hipStream_t s);
+void launch_scale(int n, const double* z, double scale, double* u, hipStream_t s);
+void launch_ritz_residual(int n, const double* U, const double* W, int64_t ld, int k,
+                          const double* svec, double theta, double* r, DevState* st, RedBuf rb,
+                          hipStream_t s);
+void launch_ritz_vector(int n, const double* U, int64_t ld, int k, const double* svec,
+                        double* y, hipStream_t s);
+void launch_tsgemm_inplace(int n, double* U, int64_t ld, int k, const double* S, int q,
+                           hipStream_t s);
+template <typename T>
+void launch_masked_copy(int n, const double* src, int trim, T* dst, hipStream_t s);
+template <typename T>
+void launch_dinv(int n, const double* d, double sigma, int trim, T* dinv, hipStream_t s);
+template <typename Ts, typename Td>
+void launch_gather(int n, const Ts* src, const int32_t* idx, Td* dst, hipStream_t s);
+void launch_fill_replacement(int n, uint64_t seed, uint64_t draw, const int32_t* perm,
+                             double* out, hipStream_t s);
+// out[label] = sign * v[iperm[label]], sign making the largest-magnitude entry positive
+// (lowest caller label among ties); scal4: device scratch of 4 doubles.
+void launch_signed_gather(int n, const double* v, const int32_t* perm, const int32_t* iperm,
+                          double* out, double* scal4, RedBuf rb, hipStream_t s);
+int set_error(int code, const char* msg);
+
+}  // namespace isira

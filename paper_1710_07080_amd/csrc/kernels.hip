@@ -1,0 +1,1154 @@
+// gfx950 kernels of the iSIRA hot path: Laplacian SpMV (binned, persistent, split long
+// rows), fused PCG updates for the trimmed shifted deflated system (2.15) with the
+// Jacobi + Sherman-Morrison-Woodbury preconditioner (3.5), enlargement (2.5), column dots
+// and updates of classical Gram-Schmidt, Ritz residuals and tall-skinny basis rotations.
+//
+// Reductions are deterministic: every workgroup writes one partial per value, and the last
+// workgroup to arrive (integer arrival counter) sums the partials in a fixed order.
+#include "internal.h"
+
+namespace isira {
+
+// ------------------------------------------------------------------ reduction helpers
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum one double over the workgroup; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum1(double v, double* sh4) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh4[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = (sh4[0] + sh4[1]) + (sh4[2] + sh4[3]);
+  return s;
+}
+
+// Publish this workgroup's partials and report whether it is the last to arrive.
+__device__ __forceinline__ bool arrive_last(unsigned* counter) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(counter, 1u);
+    s_last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = s_last != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// Last workgroup: out[v] = sum over workgroups of partials[v * nblk + b] (fixed order).
+__device__ void final_reduce(const double* partials, int nv, int nblk, double* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int v = wid; v < nv; v += 4) {
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += partials[(size_t)v * nblk + b];
+    s = wave_sum(s);
+    if (lane == 0) out[v] = s;
+  }
+  __syncthreads();
+}
+
+template <int NV>
+__device__ void write_partials(const double (&acc)[NV], int nv, double* partials) {
+  __shared__ double sh[4][NV];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if (v < nv) {
+      double s = wave_sum(acc[v]);
+      if (lane == 0) sh[wid][v] = s;
+    }
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < nv; v += blockDim.x)
+    partials[(size_t)v * gridDim.x + blockIdx.x] = (sh[0][v] + sh[1][v]) + (sh[2][v] + sh[3][v]);
+}
+
+static inline int stream_grid(int n) {
+  int g = (n + kBlock - 1) / kBlock;
+  return g < 1 ? 1 : (g > kStreamGrid ? kStreamGrid : g);
+}
+
+#define HIP_LAUNCH_CHECK() (void)hipGetLastError()
+
+// ------------------------------------------------------------------ setup kernels
+
+__global__ __launch_bounds__(kBlock) void k_degree(const int32_t* rp, const void* w, int wdt,
+                                                   int n, double* d, float* d32) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * kBlock) >> 6;
+  for (int row = wave; row < n; row += nwaves) {
+    const int b = rp[row], e = rp[row + 1];
+    double s = 0.0;
+    if (wdt == ISIRA_W_NONE) {
+      s = (lane == 0) ? (double)(e - b) : 0.0;
+    } else if (wdt == ISIRA_W_F32) {
+      for (int j = b + lane; j < e; j += 64) s += (double)((const float*)w)[j];
+    } else {
+      for (int j = b + lane; j < e; j += 64) s += ((const double*)w)[j];
+    }
+    s = wave_sum(s);
+    if (lane == 0) {
+      d[row] = s;
+      d32[row] = (float)s;
+    }
+  }
+}
+
+void launch_degree(const int32_t* rp, const void* w, int wdt, int n, double* d, float* d32,
+                   hipStream_t s) {
+  int grid = (n + 3) / 4;
+  if (grid > 4096) grid = 4096;
+  k_degree<<<grid, kBlock, 0, s>>>(rp, w, wdt, n, d, d32);
+  HIP_LAUNCH_CHECK();
+}
+
+// max degree (lowest caller label among ties), its internal index, min degree.
+__global__ __launch_bounds__(kBlock) void k_argmax_degree(const double* d, const int32_t* perm,
+                                                          int n, int use_abs, double* partials,
+                                                          unsigned* counter, double* out3) {
+  double best = -1.0, best_lab = 1e300, best_int = -1.0, mn = 1e300;
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    const double v = use_abs ? fabs(d[l]) : d[l];
+    const double lab = (double)perm[l];
+    if (v > best || (v == best && lab < best_lab)) {
+      best = v;
+      best_lab = lab;
+      best_int = (double)l;
+    }
+    mn = v < mn ? v : mn;
+  }
+  // workgroup reduction by shared arrays (4 values per thread)
+  __shared__ double sb[kBlock], sl[kBlock], si[kBlock], sm[kBlock];
+  sb[threadIdx.x] = best;
+  sl[threadIdx.x] = best_lab;
+  si[threadIdx.x] = best_int;
+  sm[threadIdx.x] = mn;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const int t = threadIdx.x + o;
+      if (sb[t] > sb[threadIdx.x] || (sb[t] == sb[threadIdx.x] && sl[t] < sl[threadIdx.x])) {
+        sb[threadIdx.x] = sb[t];
+        sl[threadIdx.x] = sl[t];
+        si[threadIdx.x] = si[t];
+      }
+      sm[threadIdx.x] = sm[t] < sm[threadIdx.x] ? sm[t] : sm[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  const int G = gridDim.x;
+  if (threadIdx.x == 0) {
+    partials[0 * G + blockIdx.x] = sb[0];
+    partials[1 * G + blockIdx.x] = sl[0];
+    partials[2 * G + blockIdx.x] = si[0];
+    partials[3 * G + blockIdx.x] = sm[0];
+  }
+  if (!arrive_last(counter)) return;
+  if (threadIdx.x == 0) {
+    double b = -1.0, bl = 1e300, bi = -1.0, m = 1e300;
+    for (int k = 0; k < G; ++k) {
+      const double v = partials[k], lab = partials[G + k];
+      if (v > b || (v == b && lab < bl)) {
+        b = v;
+        bl = lab;
+        bi = partials[2 * G + k];
+      }
+      m = partials[3 * G + k] < m ? partials[3 * G + k] : m;
+    }
+    out3[0] = b;
+    out3[1] = bi;
+    out3[2] = m;
+    out3[3] = bl;
+    *counter = 0u;
+  }
+}
+
+void launch_argmax_degree(const double* d, const int32_t* perm, int n, DevState*, RedBuf rb,
+                          double* out4, hipStream_t s) {
+  int grid = stream_grid(n);
+  if (grid > 256) grid = 256;
+  k_argmax_degree<<<grid, kBlock, 0, s>>>(d, perm, n, 0, rb.partials, rb.counters + 0, out4);
+  HIP_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(kBlock) void k_signed_gather(int n, const double* __restrict__ v,
+                                                          const int32_t* __restrict__ iperm,
+                                                          const double* scal4,
+                                                          double* __restrict__ out) {
+  const double sgn = v[(int)scal4[1]] < 0.0 ? -1.0 : 1.0;
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
+    out[l] = sgn * v[iperm[l]];
+}
+
+void launch_signed_gather(int n, const double* v, const int32_t* perm, const int32_t* iperm,
+                          double* out, double* scal4, RedBuf rb, hipStream_t s) {
+  int grid = stream_grid(n);
+  if (grid > 256) grid = 256;
+  k_argmax_degree<<<grid, kBlock, 0, s>>>(v, perm, n, 1, rb.partials, rb.counters + 0, scal4);
+  k_signed_gather<<<stream_grid(n), kBlock, 0, s>>>(n, v, iperm, scal4, out);
+  HIP_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ sparse product
+
+struct SplitInfo {
+  const int32_t* row;
+  const int32_t* chunk;
+  const int32_t* slot;
+  const int32_t* base;
+  const int32_t* nchunk;
+  unsigned* cnt;
+  double* part;
+  double* red;
+  int32_t nslots;
+};
+
+template <int VM, typename T>
+__device__ __forceinline__ T edge_val(const void* vals, int j) {
+  if constexpr (VM == kUnitNeg) {
+    return T(1);
+  } else if constexpr (VM == kF64Neg) {
+    return (T)((const double*)vals)[j];
+  } else {
+    return (T)((const float*)vals)[j];
+  }
+}
+
+template <int VM, typename T>
+__device__ __forceinline__ T row_gather(const SpmvArgs<T>& a, int b, int e, int start,
+                                        int stride) {
+  T s = T(0);
+  const T* __restrict__ x = a.x;
+  const int32_t* __restrict__ col = a.col;
+  int j = b + start;
+  // two independent chains for memory-level parallelism
+  T s2 = T(0);
+  for (; j + stride < e; j += 2 * stride) {
+    const int c0 = col[j], c1 = col[j + stride];
+    s += edge_val<VM, T>(a.vals, j) * x[c0];
+    s2 += edge_val<VM, T>(a.vals, j + stride) * x[c1];
+  }
+  if (j < e) s += edge_val<VM, T>(a.vals, j) * x[col[j]];
+  return s + s2;
+}
+
+// Finish row `row` given the neighbour sum; returns this row's reduction contribution.
+template <int VM, typename T>
+__device__ __forceinline__ double finish_row(const SpmvArgs<T>& a, int row, T nsum,
+                                             const double* sh_t, T shift_add) {
+  const T xl = a.x[row];
+  T y = a.diag[row] * xl;
+  if constexpr (VM == kF32Pos) {
+    y += nsum;
+  } else {
+    y -= nsum;
+  }
+  if (a.sigma != 0.0) y -= (T)a.sigma * xl;
+  y += shift_add;
+  if (a.c > 0) {
+    T s = T(0);
+    const T* __restrict__ V = a.V + row;
+    for (int j = 0; j < a.c; ++j) s += V[(int64_t)j * a.ldv] * (T)sh_t[j];
+    y += (T)a.delta * s;
+  }
+  if (row == a.trim) y = T(0);
+  a.y[row] = y;
+  if (a.red == 2) {
+    const double dd = (double)y - a.theta * (double)xl;
+    return dd * dd;
+  }
+  if (a.red == 1 || a.red == 3) return (double)xl * (double)y;
+  return 0.0;
+}
+
+template <typename T, int VM>
+__global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs<T> a, SpmvSegs segs, SplitInfo sp,
+                                                 double* partials, unsigned* counter) {
+  if (a.check_done && a.st->done) return;
+  __shared__ double sh_t[kMaxC];
+  __shared__ double sh4[4];
+  __shared__ T shT[4];
+  const int tid = threadIdx.x;
+  const double* tv = a.tvec ? a.tvec : (a.st ? a.st->t1 : nullptr);
+  for (int j = tid; j < a.c; j += kBlock) sh_t[j] = tv[j];
+  const T shift_add = (a.sig_over_n != 0.0) ? (T)(a.sig_over_n * a.st->sump) : T(0);
+  __syncthreads();
+  double acc = 0.0;
+  for (int u = blockIdx.x; u < segs.n_units; u += gridDim.x) {
+    int si = 0;
+    while (si + 1 < segs.nseg && u >= segs.s[si + 1].unit_begin) ++si;
+    const SpmvSeg sg = segs.s[si];
+    if (sg.lanes > 0 && sg.lanes <= 64) {
+      const int lanes = sg.lanes;
+      const int R = kBlock / lanes;
+      const int grp = tid / lanes, gl = tid - grp * lanes;
+      const int row = sg.row_begin + (u - sg.unit_begin) * R + grp;
+      T s = T(0);
+      if (row < sg.row_end) s = row_gather<VM, T>(a, a.rp[row], a.rp[row + 1], gl, lanes);
+      s = group_sum(s, lanes);
+      if (gl == 0 && row < sg.row_end) acc += finish_row<VM, T>(a, row, s, sh_t, shift_add);
+    } else if (sg.lanes == kBlock) {
+      const int row = sg.row_begin + (u - sg.unit_begin);
+      T s = row_gather<VM, T>(a, a.rp[row], a.rp[row + 1], tid, kBlock);
+      s = wave_sum(s);
+      __syncthreads();
+      if ((tid & 63) == 0) shT[tid >> 6] = s;
+      __syncthreads();
+      if (tid == 0) acc += finish_row<VM, T>(a, row, (shT[0] + shT[1]) + (shT[2] + shT[3]), sh_t,
+                                             shift_add);
+    } else {
+      // split row: one chunk of kSplitChunk nonzeros
+      const int su = u - sg.unit_begin;
+      const int row = sp.row[su], ch = sp.chunk[su], slot = sp.slot[su];
+      const int b = a.rp[row] + ch * kSplitChunk;
+      int e = b + kSplitChunk;
+      if (e > a.rp[row + 1]) e = a.rp[row + 1];
+      T s = row_gather<VM, T>(a, b, e, tid, kBlock);
+      s = wave_sum(s);
+      __syncthreads();
+      if ((tid & 63) == 0) shT[tid >> 6] = s;
+      __syncthreads();
+      if (tid == 0) {
+        sp.part[sp.base[slot] + ch] = (double)((shT[0] + shT[1]) + (shT[2] + shT[3]));
+        __threadfence();
+        const unsigned prev = atomicAdd(&sp.cnt[slot], 1u);
+        if (prev == (unsigned)(sp.nchunk[slot] - 1)) {
+          __threadfence();
+          double tot = 0.0;
+          const int nb = sp.nchunk[slot], pb = sp.base[slot];
+          for (int k = 0; k < nb; ++k) tot += sp.part[pb + k];
+          sp.red[slot] = finish_row<VM, T>(a, row, (T)tot, sh_t, shift_add);
+          sp.cnt[slot] = 0u;
+        }
+      }
+    }
+  }
+  if (a.red == 0) return;
+  const double bs = block_sum1(acc, sh4);
+  if (tid == 0) partials[blockIdx.x] = bs;
+  if (!arrive_last(counter)) return;
+  __shared__ double sh_out[1];
+  final_reduce(partials, 1, gridDim.x, sh_out);
+  if (tid == 0) {
+    double tot = sh_out[0];
+    for (int k = 0; k < sp.nslots; ++k) tot += sp.red[k];
+    DevState* st = a.st;
+    if (a.red == 1) {
+      st->pq = tot;
+      const double alpha = st->rho / tot;
+      if (!(tot > 0.0) || !isfinite(alpha)) {
+        st->done = 1;
+        st->status = kPcgBreakdown;
+      }
+      st->alpha = alpha;
+    } else if (a.red == 2) {
+      st->red[0] = tot;
+    } else {
+      st->red[1] = tot;
+    }
+    *counter = 0u;
+  }
+}
+
+template <typename T>
+void launch_spmv(const SpmvPlan& plan, int valmode, const SpmvArgs<T>& a, RedBuf rb,
+                 hipStream_t s) {
+  SplitInfo sp{plan.split_row, plan.split_chunk, plan.split_slot, plan.split_base,
+               plan.split_nchunk, plan.split_cnt, plan.split_part, plan.split_red,
+               plan.n_split_rows};
+  unsigned* cnt = rb.counters + 1;
+  switch (valmode) {
+    case kUnitNeg:
+      k_spmv<T, kUnitNeg><<<plan.grid, kBlock, 0, s>>>(a, plan.segs, sp, rb.partials, cnt);
+      break;
+    case kF32Neg:
+      k_spmv<T, kF32Neg><<<plan.grid, kBlock, 0, s>>>(a, plan.segs, sp, rb.partials, cnt);
+      break;
+    case kF64Neg:
+      k_spmv<T, kF64Neg><<<plan.grid, kBlock, 0, s>>>(a, plan.segs, sp, rb.partials, cnt);
+      break;
+    default:
+      k_spmv<T, kF32Pos><<<plan.grid, kBlock, 0, s>>>(a, plan.segs, sp, rb.partials, cnt);
+      break;
+  }
+  HIP_LAUNCH_CHECK();
+}
+template void launch_spmv<double>(const SpmvPlan&, int, const SpmvArgs<double>&, RedBuf,
+                                  hipStream_t);
+template void launch_spmv<float>(const SpmvPlan&, int, const SpmvArgs<float>&, RedBuf,
+                                 hipStream_t);
+
+// ------------------------------------------------------------------ PCG updates
+
+// x += alpha p; r -= alpha q; partials ||r||^2, r^T M^-1 r, V-hat^T (M^-1 r).  The last
+// workgroup forms g = G^-1 t2 and rho = r^T z (eq. (3.5) makes r^T z = r^T M^-1 r -
+// delta t2^T g), tests convergence and sets beta.
+template <typename T, int CM>
+__global__ __launch_bounds__(kBlock) void k_pcg_update1(int n, T* __restrict__ x,
+                                                        T* __restrict__ r,
+                                                        const T* __restrict__ p,
+                                                        const T* __restrict__ q,
+                                                        const T* __restrict__ dinv,
+                                                        const T* __restrict__ V, int64_t ldv,
+                                                        int c, const double* Ginv,
+                                                        double delta, int init, DevState* st,
+                                                        double* partials, unsigned* counter) {
+  if (st->done) return;
+  constexpr int NV = 2 + (CM > 0 ? CM : 0);
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  const T alpha = init ? T(0) : (T)st->alpha;
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    T rl = r[l];
+    if (!init) {
+      x[l] += alpha * p[l];
+      rl -= alpha * q[l];
+      r[l] = rl;
+    }
+    const T u = dinv[l] * rl;
+    acc[0] += (double)rl * (double)rl;
+    acc[1] += (double)rl * (double)u;
+#pragma unroll
+    for (int j = 0; j < CM; ++j)
+      if (j < c) acc[2 + j] += (double)V[l + (int64_t)j * ldv] * (double)u;
+  }
+  const int nv = 2 + c;
+  write_partials<NV>(acc, nv, partials);
+  if (!arrive_last(counter)) return;
+  __shared__ double red[NV];
+  final_reduce(partials, nv, gridDim.x, red);
+  // g = Ginv t2 (c x c, column-major)
+  for (int j = threadIdx.x; j < c; j += kBlock) {
+    double gj = 0.0;
+    for (int i = 0; i < c; ++i) gj += Ginv[j + i * c] * red[2 + i];
+    st->g[j] = gj;
+    st->t2[j] = red[2 + j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tg = 0.0;
+    for (int j = 0; j < c; ++j) tg += red[2 + j] * st->g[j];
+    const double rr = red[0];
+    const double rho_new = red[1] - delta * tg;
+    st->rr = rr;
+    st->rmr = red[1];
+    if (init) {
+      st->rr0 = rr;
+      st->thresh2 = st->rtol2 * rr;
+      st->rho = rho_new;
+      st->beta = 0.0;
+      st->it = 0;
+      if (!(rr > 0.0)) st->done = 1;
+      if (!(rho_new > 0.0) && rr > 0.0) {
+        st->done = 1;
+        st->status = kPcgBreakdown;
+      }
+    } else {
+      st->it += 1;
+      if (!(rr <= st->thresh2)) {
+        if (st->it >= st->maxit) {
+          st->done = 1;
+          st->status = kPcgCapped;
+        } else if (!(rho_new > 0.0) || !isfinite(rho_new)) {
+          st->done = 1;
+          st->status = kPcgBreakdown;
+        } else {
+          st->beta = rho_new / st->rho;
+          st->rho = rho_new;
+        }
+      } else {
+        st->done = 1;
+      }
+    }
+    *counter = 0u;
+  }
+}
+
+// z = M^-1 (r - delta V-hat g); p = z + beta p; partials V-hat^T p and sum(p).
+template <typename T, int CM>
+__global__ __launch_bounds__(kBlock) void k_pcg_update2(int n, const T* __restrict__ r,
+                                                        T* __restrict__ p,
+                                                        const T* __restrict__ dinv,
+                                                        const T* __restrict__ V, int64_t ldv,
+                                                        int c, double delta, int init,
+                                                        DevState* st, double* partials,
+                                                        unsigned* counter) {
+  if (st->done) return;
+  constexpr int NV = 1 + (CM > 0 ? CM : 0);
+  __shared__ T sg[CM > 0 ? CM : 1];
+  for (int j = threadIdx.x; j < c; j += kBlock) sg[j] = (T)st->g[j];
+  __syncthreads();
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  const T beta = init ? T(0) : (T)st->beta;
+  const T dl = (T)delta;
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    T vreg[CM > 0 ? CM : 1];
+    T s = T(0);
+#pragma unroll
+    for (int j = 0; j < CM; ++j) {
+      vreg[j] = T(0);
+      if (j < c) {
+        vreg[j] = V[l + (int64_t)j * ldv];
+        s += vreg[j] * sg[j];
+      }
+    }
+    const T z = dinv[l] * (r[l] - dl * s);
+    const T pn = init ? z : z + beta * p[l];
+    p[l] = pn;
+    acc[0] += (double)pn;
+#pragma unroll
+    for (int j = 0; j < CM; ++j)
+      if (j < c) acc[1 + j] += (double)vreg[j] * (double)pn;
+  }
+  const int nv = 1 + c;
+  write_partials<NV>(acc, nv, partials);
+  if (!arrive_last(counter)) return;
+  __shared__ double red[NV];
+  final_reduce(partials, nv, gridDim.x, red);
+  for (int j = threadIdx.x; j < c; j += kBlock) st->t1[j] = red[1 + j];
+  if (threadIdx.x == 0) {
+    st->sump = red[0];
+    *counter = 0u;
+  }
+}
+
+static inline int pick_cm(int c) {
+  if (c <= 0) return 0;
+  if (c <= 8) return 8;
+  if (c <= 16) return 16;
+  if (c <= 32) return 32;
+  return 64;
+}
+
+template <typename T>
+void launch_pcg_update1(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const T* V,
+                        int64_t ldv, int c, const double* Ginv, double delta, int init,
+                        DevState* st, RedBuf rb, hipStream_t s) {
+  const int grid = stream_grid(n);
+  unsigned* cnt = rb.counters + 2;
+  switch (pick_cm(c)) {
+    case 0:
+      k_pcg_update1<T, 0><<<grid, kBlock, 0, s>>>(n, x, r, p, q, dinv, V, ldv, c, Ginv, delta,
+                                                  init, st, rb.partials, cnt);
+      break;
+    case 8:
+      k_pcg_update1<T, 8><<<grid, kBlock, 0, s>>>(n, x, r, p, q, dinv, V, ldv, c, Ginv, delta,
+                                                  init, st, rb.partials, cnt);
+      break;
+    case 16:
+      k_pcg_update1<T, 16><<<grid, kBlock, 0, s>>>(n, x, r, p, q, dinv, V, ldv, c, Ginv, delta,
+                                                   init, st, rb.partials, cnt);
+      break;
+    case 32:
+      k_pcg_update1<T, 32><<<grid, kBlock, 0, s>>>(n, x, r, p, q, dinv, V, ldv, c, Ginv, delta,
+                                                   init, st, rb.partials, cnt);
+      break;
+    default:
+      k_pcg_update1<T, 64><<<grid, kBlock, 0, s>>>(n, x, r, p, q, dinv, V, ldv, c, Ginv, delta,
+                                                   init, st, rb.partials, cnt);
+      break;
+  }
+  HIP_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_pcg_update2(int n, const T* r, T* p, const T* dinv, const T* V, int64_t ldv, int c,
+                        double delta, int init, DevState* st, RedBuf rb, hipStream_t s) {
+  const int grid = stream_grid(n);
+  unsigned* cnt = rb.counters + 3;
+  switch (pick_cm(c)) {
+    case 0:
+      k_pcg_update2<T, 0><<<grid, kBlock, 0, s>>>(n, r, p, dinv, V, ldv, c, delta, init, st,
+                                                  rb.partials, cnt);
+      break;
+    case 8:
+      k_pcg_update2<T, 8><<<grid, kBlock, 0, s>>>(n, r, p, dinv, V, ldv, c, delta, init, st,
+                                                  rb.partials, cnt);
+      break;
+    case 16:
+      k_pcg_update2<T, 16><<<grid, kBlock, 0, s>>>(n, r, p, dinv, V, ldv, c, delta, init, st,
+                                                   rb.partials, cnt);
+      break;
+    case 32:
+      k_pcg_update2<T, 32><<<grid, kBlock, 0, s>>>(n, r, p, dinv, V, ldv, c, delta, init, st,
+                                                   rb.partials, cnt);
+      break;
+    default:
+      k_pcg_update2<T, 64><<<grid, kBlock, 0, s>>>(n, r, p, dinv, V, ldv, c, delta, init, st,
+                                                   rb.partials, cnt);
+      break;
+  }
+  HIP_LAUNCH_CHECK();
+}
+template void launch_pcg_update1<double>(int, double*, double*, const double*, const double*,
+                                         const double*, const double*, int64_t, int,
+                                         const double*, double, int, DevState*, RedBuf,
+                                         hipStream_t);
+template void launch_pcg_update1<float>(int, float*, float*, const float*, const float*,
+                                        const float*, const float*, int64_t, int, const double*,
+                                        double, int, DevState*, RedBuf, hipStream_t);
+template void launch_pcg_update2<double>(int, const double*, double*, const double*,
+                                         const double*, int64_t, int, double, int, DevState*,
+                                         RedBuf, hipStream_t);
+template void launch_pcg_update2<float>(int, const float*, float*, const float*, const float*,
+                                        int64_t, int, double, int, DevState*, RedBuf,
+                                        hipStream_t);
+
+// ---- learned preconditioner variants ----
+
+// x += alpha p; r -= alpha q; partial ||r||^2; the last workgroup tests convergence.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_update1_plain(int n, T* __restrict__ x,
+                                                              T* __restrict__ r,
+                                                              const T* __restrict__ p,
+                                                              const T* __restrict__ q, int init,
+                                                              DevState* st, double* partials,
+                                                              unsigned* counter) {
+  if (st->done) return;
+  double acc[1] = {0.0};
+  const T alpha = init ? T(0) : (T)st->alpha;
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    T rl = r[l];
+    if (!init) {
+      x[l] += alpha * p[l];
+      rl -= alpha * q[l];
+      r[l] = rl;
+    }
+    acc[0] += (double)rl * (double)rl;
+  }
+  write_partials<1>(acc, 1, partials);
+  if (!arrive_last(counter)) return;
+  __shared__ double red[1];
+  final_reduce(partials, 1, gridDim.x, red);
+  if (threadIdx.x == 0) {
+    const double rr = red[0];
+    st->rr = rr;
+    if (init) {
+      st->rr0 = rr;
+      st->thresh2 = st->rtol2 * rr;
+      st->it = 0;
+      if (!(rr > 0.0)) st->done = 1;
+    } else {
+      st->it += 1;
+      if (rr <= st->thresh2) {
+        st->done = 1;
+      } else if (st->it >= st->maxit) {
+        st->done = 1;
+        st->status = kPcgCapped;
+      } else if (!isfinite(rr)) {
+        st->done = 1;
+        st->status = kPcgBreakdown;
+      }
+    }
+    *counter = 0u;
+  }
+}
+
+// After y = M r with dots t = V-hat^T y (st->t2[0..c)) and r^T y (st->t2[c]):
+// g = G^-1 t, rho = r^T y - delta t^T g, beta.
+__global__ void k_spai_finish_rho(int c, const double* Ginv, double delta, int init,
+                                  DevState* st) {
+  if (st->done) return;
+  for (int j = threadIdx.x; j < c; j += blockDim.x) {
+    double gj = 0.0;
+    for (int i = 0; i < c; ++i) gj += Ginv[j + i * c] * st->t2[i];
+    st->g[j] = gj;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tg = 0.0;
+    for (int j = 0; j < c; ++j) tg += st->t2[j] * st->g[j];
+    const double rho_new = st->t2[c] - delta * tg;
+    if (!(rho_new > 0.0) || !isfinite(rho_new)) {
+      st->done = 1;
+      st->status = kPcgBreakdown;
+    } else if (init) {
+      st->rho = rho_new;
+      st->beta = 0.0;
+    } else {
+      st->beta = rho_new / st->rho;
+      st->rho = rho_new;
+    }
+  }
+}
+
+void launch_spai_finish_rho(int c, const double* Ginv, double delta, int init, DevState* st,
+                            hipStream_t s) {
+  k_spai_finish_rho<<<1, 64, 0, s>>>(c, Ginv, delta, init, st);
+  HIP_LAUNCH_CHECK();
+}
+
+// z = y - delta Y g; p = z + beta p; partials V-hat^T p and sum(p).
+template <typename T, int CM>
+__global__ __launch_bounds__(kBlock) void k_pcg_update2_learned(
+    int n, const T* __restrict__ y, T* __restrict__ p, const T* __restrict__ Y, int64_t ldv,
+    int c, const T* __restrict__ V, double delta, int init, DevState* st, double* partials,
+    unsigned* counter) {
+  if (st->done) return;
+  constexpr int NV = 1 + (CM > 0 ? CM : 0);
+  __shared__ T sg[CM > 0 ? CM : 1];
+  for (int j = threadIdx.x; j < c; j += kBlock) sg[j] = (T)st->g[j];
+  __syncthreads();
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  const T beta = init ? T(0) : (T)st->beta;
+  const T dl = (T)delta;
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    T s = T(0);
+#pragma unroll
+    for (int j = 0; j < CM; ++j)
+      if (j < c) s += Y[l + (int64_t)j * ldv] * sg[j];
+    const T z = y[l] - dl * s;
+    const T pn = init ? z : z + beta * p[l];
+    p[l] = pn;
+    acc[0] += (double)pn;
+#pragma unroll
+    for (int j = 0; j < CM; ++j)
+      if (j < c) acc[1 + j] += (double)V[l + (int64_t)j * ldv] * (double)pn;
+  }
+  const int nv = 1 + c;
+  write_partials<NV>(acc, nv, partials);
+  if (!arrive_last(counter)) return;
+  __shared__ double red[NV];
+  final_reduce(partials, nv, gridDim.x, red);
+  for (int j = threadIdx.x; j < c; j += kBlock) st->t1[j] = red[1 + j];
+  if (threadIdx.x == 0) {
+    st->sump = red[0];
+    *counter = 0u;
+  }
+}
+
+template <typename T>
+void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, int init, DevState* st,
+                              RedBuf rb, hipStream_t s) {
+  k_pcg_update1_plain<T><<<stream_grid(n), kBlock, 0, s>>>(n, x, r, p, q, init, st,
+                                                          rb.partials, rb.counters + 4);
+  HIP_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv, int c,
+                                const T* V, double delta, int init, DevState* st, RedBuf rb,
+                                hipStream_t s) {
+  const int grid = stream_grid(n);
+  unsigned* cnt = rb.counters + 5;
+  switch (pick_cm(c)) {
+    case 0:
+      k_pcg_update2_learned<T, 0><<<grid, kBlock, 0, s>>>(n, y, p, Y, ldv, c, V, delta, init,
+                                                          st, rb.partials, cnt);
+      break;
+    case 8:
+      k_pcg_update2_learned<T, 8><<<grid, kBlock, 0, s>>>(n, y, p, Y, ldv, c, V, delta, init,
+                                                          st, rb.partials, cnt);
+      break;
+    case 16:
+      k_pcg_update2_learned<T, 16><<<grid, kBlock, 0, s>>>(n, y, p, Y, ldv, c, V, delta, init,
+                                                           st, rb.partials, cnt);
+      break;
+    case 32:
+      k_pcg_update2_learned<T, 32><<<grid, kBlock, 0, s>>>(n, y, p, Y, ldv, c, V, delta, init,
+                                                           st, rb.partials, cnt);
+      break;
+    default:
+      k_pcg_update2_learned<T, 64><<<grid, kBlock, 0, s>>>(n, y, p, Y, ldv, c, V, delta, init,
+                                                           st, rb.partials, cnt);
+      break;
+  }
+  HIP_LAUNCH_CHECK();
+}
+template void launch_pcg_update1_plain<double>(int, double*, double*, const double*,
+                                               const double*, int, DevState*, RedBuf,
+                                               hipStream_t);
+template void launch_pcg_update1_plain<float>(int, float*, float*, const float*, const float*,
+                                              int, DevState*, RedBuf, hipStream_t);
+template void launch_pcg_update2_learned<double>(int, const double*, double*, const double*,
+                                                 int64_t, int, const double*, double, int,
+                                                 DevState*, RedBuf, hipStream_t);
+template void launch_pcg_update2_learned<float>(int, const float*, float*, const float*,
+                                                int64_t, int, const float*, double, int,
+                                                DevState*, RedBuf, hipStream_t);
+
+// ------------------------------------------------------------------ right-hand side, enlarge
+
+// r_in = trim(r - mean) in the inner precision (entry `trim` is 0); x = 0.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rhs_prep(int n, const double* __restrict__ r64,
+                                                     double mean, int trim, T* __restrict__ rin,
+                                                     T* __restrict__ x) {
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    rin[l] = (l == trim) ? T(0) : (T)(r64[l] - mean);
+    x[l] = T(0);
+  }
+}
+template <typename T>
+void launch_rhs_prep(int n, const double* r64, double mean, int trim, T* rin, T* x,
+                     hipStream_t s) {
+  k_rhs_prep<T><<<stream_grid(n), kBlock, 0, s>>>(n, r64, mean, trim, rin, x);
+  HIP_LAUNCH_CHECK();
+}
+template void launch_rhs_prep<double>(int, const double*, double, int, double*, double*,
+                                      hipStream_t);
+template void launch_rhs_prep<float>(int, const double*, double, int, float*, float*,
+                                     hipStream_t);
+
+// eq. (2.5): z = x - (1^T x / n) 1, in FP64 (x carries the trimmed zero in place).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sum(int n, const T* __restrict__ x,
+                                                DevState* st, double* partials,
+                                                unsigned* counter) {
+  double acc[1] = {0.0};
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
+    acc[0] += (double)x[l];
+  write_partials<1>(acc, 1, partials);
+  if (!arrive_last(counter)) return;
+  __shared__ double red[1];
+  final_reduce(partials, 1, gridDim.x, red);
+  if (threadIdx.x == 0) {
+    st->sumx = red[0];
+    *counter = 0u;
+  }
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_enlarge(int n, const T* __restrict__ x,
+                                                    double* __restrict__ z, const DevState* st) {
+  const double mean = st->sumx / (double)n;
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
+    z[l] = (double)x[l] - mean;
+}
+template <typename T>
+void launch_enlarge(int n, const T* x, double* z, DevState* st, RedBuf rb, hipStream_t s) {
+  const int grid = stream_grid(n);
+  k_sum<T><<<grid, kBlock, 0, s>>>(n, x, st, rb.partials, rb.counters + 6);
+  k_enlarge<T><<<grid, kBlock, 0, s>>>(n, x, z, st);
+  HIP_LAUNCH_CHECK();
+}
+template void launch_enlarge<double>(int, const double*, double*, DevState*, RedBuf,
+                                     hipStream_t);
+template void launch_enlarge<float>(int, const float*, double*, DevState*, RedBuf, hipStream_t);
+
+// ------------------------------------------------------------------ column dots, updates
+
+// h_j = sum_l A[l,j] w_l z_l (j < na), then B's columns, then sum(z), then z^T z.  Tiles of
+// kTile rows are staged in LDS; each wave owns a set of columns, so the per-workgroup sums
+// need no atomics.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_multidot(int n, const T* __restrict__ A,
+                                                     int64_t lda, int na,
+                                                     const T* __restrict__ B, int64_t ldb,
+                                                     int nb, const T* __restrict__ z,
+                                                     const T* __restrict__ wz, int with_sum,
+                                                     int with_self, double* h,
+                                                     double* partials, unsigned* counter) {
+  __shared__ T zt[kTile];
+  __shared__ double acc[kMaxCols];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int ncol = na + nb;
+  const int nv = ncol + with_sum + with_self;
+  for (int v = tid; v < nv; v += kBlock) acc[v] = 0.0;
+  const int ntiles = (n + kTile - 1) / kTile;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int base = tile * kTile;
+    const int len = (n - base) < kTile ? (n - base) : kTile;
+    __syncthreads();
+    for (int i = tid; i < len; i += kBlock) {
+      T zz = z[base + i];
+      if (wz) zz *= wz[base + i];
+      zt[i] = zz;
+    }
+    __syncthreads();
+    for (int j = wid; j < nv; j += 4) {
+      double s = 0.0;
+      if (j < ncol) {
+        const T* colp = (j < na) ? A + (int64_t)j * lda + base : B + (int64_t)(j - na) * ldb + base;
+        for (int i = lane; i < len; i += 64) s += (double)colp[i] * (double)zt[i];
+      } else if (with_sum && j == ncol) {
+        for (int i = lane; i < len; i += 64) s += (double)zt[i];
+      } else {
+        for (int i = lane; i < len; i += 64) s += (double)zt[i] * (double)zt[i];
+      }
+      s = wave_sum(s);
+      if (lane == 0) acc[j] += s;
+    }
+  }
+  __syncthreads();
+  for (int v = tid; v < nv; v += kBlock) partials[(size_t)v * gridDim.x + blockIdx.x] = acc[v];
+  if (!arrive_last(counter)) return;
+  __shared__ double red[kMaxCols];
+  final_reduce(partials, nv, gridDim.x, red);
+  for (int v = tid; v < nv; v += kBlock) h[v] = red[v];
+  if (tid == 0) *counter = 0u;
+}
+
+template <typename T>
+void launch_multidot(int n, const T* A, int64_t lda, int na, const T* B, int64_t ldb, int nb,
+                     const T* z, const T* wz, int with_sum, int with_self, double* h, RedBuf rb,
+                     hipStream_t s) {
+  int grid = (n + kTile - 1) / kTile;
+  if (grid > kStreamGrid) grid = kStreamGrid;
+  k_multidot<T><<<grid, kBlock, 0, s>>>(n, A, lda, na, B, ldb, nb, z, wz, with_sum, with_self,
+                                        h, rb.partials, rb.counters + 7);
+  HIP_LAUNCH_CHECK();
+}
+template void launch_multidot<double>(int, const double*, int64_t, int, const double*, int64_t,
+                                      int, const double*, const double*, int, int, double*,
+                                      RedBuf, hipStream_t);
+template void launch_multidot<float>(int, const float*, int64_t, int, const float*, int64_t, int,
+                                     const float*, const float*, int, int, double*, RedBuf,
+                                     hipStream_t);
+
+// z -= A hA + B hB (+ h_sum / n); optional ||z||^2 -> st->red[2].
+__global__ __launch_bounds__(kBlock) void k_gemv_sub(int n, const double* __restrict__ A,
+                                                     int64_t lda, int na,
+                                                     const double* __restrict__ B, int64_t ldb,
+                                                     int nb, const double* __restrict__ h,
+                                                     int with_sum, double* __restrict__ z,
+                                                     int with_norm, DevState* st,
+                                                     double* partials, unsigned* counter) {
+  __shared__ double sh[kMaxCols];
+  const int ncol = na + nb;
+  for (int v = threadIdx.x; v < ncol + with_sum; v += kBlock) sh[v] = h[v];
+  __syncthreads();
+  const double mean = with_sum ? sh[ncol] / (double)n : 0.0;
+  double acc[1] = {0.0};
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    double s = 0.0;
+    for (int j = 0; j < na; ++j) s += A[l + (int64_t)j * lda] * sh[j];
+    for (int j = 0; j < nb; ++j) s += B[l + (int64_t)j * ldb] * sh[na + j];
+    const double zl = z[l] - s - mean;
+    z[l] = zl;
+    acc[0] += zl * zl;
+  }
+  if (!with_norm) return;
+  write_partials<1>(acc, 1, partials);
+  if (!arrive_last(counter)) return;
+  __shared__ double red[1];
+  final_reduce(partials, 1, gridDim.x, red);
+  if (threadIdx.x == 0) {
+    st->red[2] = red[0];
+    *counter = 0u;
+  }
+}
+
+void launch_gemv_sub(int n, const double* A, int64_t lda, int na, const double* B, int64_t ldb,
+                     int nb, const double* h, int with_sum, double* z, int with_norm,
+                     DevState* st, RedBuf rb, hipStream_t s) {
+  k_gemv_sub<<<stream_grid(n), kBlock, 0, s>>>(n, A, lda, na, B, ldb, nb, h, with_sum, z,
+                                               with_norm, st, rb.partials, rb.counters + 8);
+  HIP_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale(int n, const double* __restrict__ z,
+                                                  double scale, double* __restrict__ u) {
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
+    u[l] = z[l] * scale;
+}
+void launch_scale(int n, const double* z, double scale, double* u, hipStream_t s) {
+  k_scale<<<stream_grid(n), kBlock, 0, s>>>(n, z, scale, u);
+  HIP_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ Ritz vectors, residuals
+
+// r = W s - theta U s; partials ||r||^2 -> st->red[0], sum(r) -> st->red[1].
+__global__ __launch_bounds__(kBlock) void k_ritz_residual(int n, const double* __restrict__ U,
+                                                          const double* __restrict__ W,
+                                                          int64_t ld, int k,
+                                                          const double* __restrict__ svec,
+                                                          double theta, double* __restrict__ r,
+                                                          DevState* st, double* partials,
+                                                          unsigned* counter) {
+  __shared__ double sh[ISIRA_MAX_BASIS];
+  for (int j = threadIdx.x; j < k; j += kBlock) sh[j] = svec[j];
+  __syncthreads();
+  double acc[2] = {0.0, 0.0};
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    double y = 0.0, ly = 0.0;
+    for (int j = 0; j < k; ++j) {
+      y += U[l + (int64_t)j * ld] * sh[j];
+      ly += W[l + (int64_t)j * ld] * sh[j];
+    }
+    const double rl = ly - theta * y;
+    r[l] = rl;
+    acc[0] += rl * rl;
+    acc[1] += rl;
+  }
+  write_partials<2>(acc, 2, partials);
+  if (!arrive_last(counter)) return;
+  __shared__ double red[2];
+  final_reduce(partials, 2, gridDim.x, red);
+  if (threadIdx.x == 0) {
+    st->red[0] = red[0];
+    st->red[1] = red[1];
+    *counter = 0u;
+  }
+}
+void launch_ritz_residual(int n, const double* U, const double* W, int64_t ld, int k,
+                          const double* svec, double theta, double* r, DevState* st, RedBuf rb,
+                          hipStream_t s) {
+  k_ritz_residual<<<stream_grid(n), kBlock, 0, s>>>(n, U, W, ld, k, svec, theta, r, st,
+                                                    rb.partials, rb.counters + 9);
+  HIP_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(kBlock) void k_ritz_vector(int n, const double* __restrict__ U,
+                                                        int64_t ld, int k,
+                                                        const double* __restrict__ svec,
+                                                        double* __restrict__ y) {
+  __shared__ double sh[ISIRA_MAX_BASIS];
+  for (int j = threadIdx.x; j < k; j += kBlock) sh[j] = svec[j];
+  __syncthreads();
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += U[l + (int64_t)j * ld] * sh[j];
+    y[l] = s;
+  }
+}
+void launch_ritz_vector(int n, const double* U, int64_t ld, int k, const double* svec,
+                        double* y, hipStream_t s) {
+  k_ritz_vector<<<stream_grid(n), kBlock, 0, s>>>(n, U, ld, k, svec, y);
+  HIP_LAUNCH_CHECK();
+}
+
+// U[:, 0:q] = U[:, 0:k] S[:, 0:q] in place (S k-by-q column-major, device).  Each
+// workgroup stages a tile of rows of U and a panel of S in LDS.
+constexpr int kTsRows = 32;
+constexpr int kTsCols = 16;
+__global__ __launch_bounds__(kBlock) void k_tsgemm_inplace(int n, double* __restrict__ U,
+                                                           int64_t ld, int k,
+                                                           const double* __restrict__ S,
+                                                           int q) {
+  __shared__ double ut[kTsRows * ISIRA_MAX_BASIS];
+  __shared__ double sp[ISIRA_MAX_BASIS * kTsCols];
+  const int tid = threadIdx.x;
+  const int rr = tid % kTsRows, cg = tid / kTsRows;  // 8 column groups
+  const int ntiles = (n + kTsRows - 1) / kTsRows;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int base = tile * kTsRows;
+    const int len = (n - base) < kTsRows ? (n - base) : kTsRows;
+    __syncthreads();
+    for (int e = tid; e < kTsRows * k; e += kBlock) {
+      const int j = e / kTsRows, i = e - j * kTsRows;
+      ut[i * k + j] = (i < len) ? U[base + i + (int64_t)j * ld] : 0.0;
+    }
+    for (int c0 = 0; c0 < q; c0 += kTsCols) {
+      const int nc = (q - c0) < kTsCols ? (q - c0) : kTsCols;
+      __syncthreads();
+      for (int e = tid; e < k * nc; e += kBlock) {
+        const int jc = e / k, i = e - jc * k;
+        sp[jc * k + i] = S[i + (int64_t)(c0 + jc) * k];
+      }
+      __syncthreads();
+      for (int jc = cg; jc < nc; jc += kBlock / kTsRows) {
+        double s = 0.0;
+        const double* urow = ut + rr * k;
+        const double* scol = sp + jc * k;
+        for (int i = 0; i < k; ++i) s += urow[i] * scol[i];
+        if (rr < len) U[base + rr + (int64_t)(c0 + jc) * ld] = s;
+      }
+    }
+  }
+}
+void launch_tsgemm_inplace(int n, double* U, int64_t ld, int k, const double* S, int q,
+                           hipStream_t s) {
+  int grid = (n + kTsRows - 1) / kTsRows;
+  if (grid > 4 * kStreamGrid) grid = 4 * kStreamGrid;
+  k_tsgemm_inplace<<<grid, kBlock, 0, s>>>(n, U, ld, k, S, q);
+  HIP_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ small elementwise helpers
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_masked_copy(int n, const double* __restrict__ src,
+                                                        int trim, T* __restrict__ dst) {
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
+    dst[l] = (l == trim) ? T(0) : (T)src[l];
+}
+template <typename T>
+void launch_masked_copy(int n, const double* src, int trim, T* dst, hipStream_t s) {
+  k_masked_copy<T><<<stream_grid(n), kBlock, 0, s>>>(n, src, trim, dst);
+  HIP_LAUNCH_CHECK();
+}
+template void launch_masked_copy<double>(int, const double*, int, double*, hipStream_t);
+template void launch_masked_copy<float>(int, const double*, int, float*, hipStream_t);
+
+// Jacobi part of Remark 3.2: M-hat_sigma^{-1} = 1 / (d - sigma), with 0 at the trimmed row.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dinv(int n, const double* __restrict__ d,
+                                                 double sigma, int trim, T* __restrict__ dinv) {
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
+    dinv[l] = (l == trim) ? T(0) : (T)(1.0 / (d[l] - sigma));
+}
+template <typename T>
+void launch_dinv(int n, const double* d, double sigma, int trim, T* dinv, hipStream_t s) {
+  k_dinv<T><<<stream_grid(n), kBlock, 0, s>>>(n, d, sigma, trim, dinv);
+  HIP_LAUNCH_CHECK();
+}
+template void launch_dinv<double>(int, const double*, double, int, double*, hipStream_t);
+template void launch_dinv<float>(int, const double*, double, int, float*, hipStream_t);
+
+// dst[l] = src[idx[l]]
+template <typename Ts, typename Td>
+__global__ __launch_bounds__(kBlock) void k_gather(int n, const Ts* __restrict__ src,
+                                                   const int32_t* __restrict__ idx,
+                                                   Td* __restrict__ dst) {
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
+    dst[l] = (Td)src[idx[l]];
+}
+template <typename Ts, typename Td>
+void launch_gather(int n, const Ts* src, const int32_t* idx, Td* dst, hipStream_t s) {
+  k_gather<Ts, Td><<<stream_grid(n), kBlock, 0, s>>>(n, src, idx, dst);
+  HIP_LAUNCH_CHECK();
+}
+template void launch_gather<double, double>(int, const double*, const int32_t*, double*,
+                                            hipStream_t);
+template void launch_gather<float, float>(int, const float*, const int32_t*, float*,
+                                          hipStream_t);
+template void launch_gather<double, float>(int, const double*, const int32_t*, float*,
+                                           hipStream_t);
+template void launch_gather<float, double>(int, const float*, const int32_t*, double*,
+                                           hipStream_t);
+
+// Replacement vectors from SplitMix64 (Steele, Lea and Flood 2014): entry with caller
+// label o of draw number `draw` is output number draw*n + o of the generator seeded `seed`,
+// mapped to [-1, 1) through its top 53 bits.
+__device__ __forceinline__ double splitmix64_uniform(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+}
+__global__ __launch_bounds__(kBlock) void k_fill_replacement(int n, uint64_t seed, uint64_t draw,
+                                                             const int32_t* __restrict__ perm,
+                                                             double* __restrict__ out) {
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
+    out[l] = splitmix64_uniform(seed, draw * (uint64_t)n + (uint64_t)perm[l]);
+}
+void launch_fill_replacement(int n, uint64_t seed, uint64_t draw, const int32_t* perm,
+                             double* out, hipStream_t s) {
+  k_fill_replacement<<<stream_grid(n), kBlock, 0, s>>>(n, seed, draw, perm, out);
+  HIP_LAUNCH_CHECK();
+}
+
+}  // namespace isira

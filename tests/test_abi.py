@@ -1,0 +1,89 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared entry point,
+the host eigensolver works, and graph validation rejects bad input before any GPU call."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1710_07080_amd as pkg
+
+    pkg.load()
+    return pkg
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "isira.h")).read()
+    return sorted(set(re.findall(r"\b(isira_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(P):
+    lib = P.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing
+    assert sorted(P.isira.EXPORTS) == names
+
+
+def test_defaults_and_strerror(P):
+    o = P.isira.default_options()
+    assert o.k0 == 4 and o.inner_rtol == 1e-4 and o.trim_index == -1 and o.check_every == 8
+    lib = P.load()
+    for code in [0, 1, -1, -2, -3, -4, -5, -6]:
+        assert lib.isira_strerror(code)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 7, 40, 120, 192])
+def test_host_symeig(P, k):
+    rng = np.random.default_rng(k)
+    H = rng.standard_normal((k, k))
+    H = H + H.T
+    theta, S = P.symeig(H)
+    lam = np.linalg.eigvalsh(H)
+    scale = max(1.0, np.abs(lam).max())
+    assert np.abs(theta - lam).max() <= 1e-13 * scale
+    assert np.abs(H @ S - S * theta).max() <= 1e-12 * scale
+    assert np.abs(S.T @ S - np.eye(k)).max() <= 1e-13
+    assert np.all(np.diff(theta) >= 0)
+
+
+def test_symeig_clustered_and_diagonal(P):
+    H = np.diag([3.0, 1.0, 2.0, 1.0, 5.0])
+    theta, S = P.symeig(H)
+    assert np.allclose(theta, [1, 1, 2, 3, 5])
+    H = np.diag(np.arange(1, 31) * 1e-3) + 1e-12 * np.ones((30, 30))
+    theta, S = P.symeig(H)
+    assert np.allclose(theta, np.linalg.eigvalsh(H), rtol=0, atol=1e-15)
+
+
+def _bad(P, n, rp, col, w=None, code=None):
+    with pytest.raises(P.IsiraError) as e:
+        P.Context(n, np.asarray(rp), np.asarray(col), w, stream=0)
+    assert e.value.code == code
+
+
+def test_create_rejects_bad_graphs(P):
+    E = P.isira
+    _bad(P, 3, [0, 1, 2, 2], [1, 0], code=E.ISIRA_E_DISCONNECTED)   # isolated vertex 2
+    _bad(P, 3, [0, 2, 3, 4], [0, 1, 0, 0], code=E.ISIRA_E_GRAPH)    # self loop
+    _bad(P, 3, [0, 1, 2, 3], [1, 0, 5], code=E.ISIRA_E_GRAPH)       # index out of range
+    _bad(P, 3, [0, 2, 3, 4], [2, 1, 0, 0], code=E.ISIRA_E_GRAPH)    # unsorted columns
+    _bad(P, 3, [0, 1, 3, 4], [1, 0, 2, 0], code=E.ISIRA_E_GRAPH)    # asymmetric pattern
+    g = gg.path_graph(5)
+    w = np.ones(g.nnz)
+    w[0] = 2.0
+    _bad(P, 5, g.row_ptr, g.col, w, code=E.ISIRA_E_GRAPH)            # asymmetric weights
+    w = np.ones(g.nnz)
+    w[3] = -1.0
+    _bad(P, 5, g.row_ptr, g.col, w, code=E.ISIRA_E_GRAPH)            # negative weight
+    # two components: 0-1 and 2-3
+    _bad(P, 4, [0, 1, 2, 3, 4], [1, 0, 3, 2], code=E.ISIRA_E_DISCONNECTED)
+    _bad(P, 2, [0, 1, 2], [1, 0], code=E.ISIRA_E_ARG)                # n too small

@@ -1,0 +1,143 @@
+"""GPU parity of the learned SPAI preconditioner: network forward (M values), loss and
+gradient of the hand-written backward kernels, the Adam step, and the learned-
+preconditioner inner solve, all against the FP64 CPU oracle."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+from oracle import isira_oracle as O
+from oracle import spai_oracle as SO
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1710_07080_amd as pkg
+
+    pkg.load()
+    return pkg
+
+
+def _params(seed, jitter=0.2):
+    rng = np.random.default_rng(seed)
+    p = SO.init_params(seed).astype(np.float64) + jitter * rng.standard_normal(SO.NPARAM)
+    p[SO.OFF["ce"][0]] = 0.8
+    return p.astype(np.float32)
+
+
+GRAPHS = {
+    "rmat12": lambda: gg.rmat(12, 8, seed=21),
+    "grid3d_w": lambda: gg.grid3d(10, 9, 8, weights=(0.5, 1.5), seed=3),
+    "hubs": lambda: gg.chung_lu(6000, 2.1, 12.0, seed=8),
+}
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_forward_matches_oracle(P, name):
+    g = GRAPHS[name]()
+    assert P.isira.spai_nparam() == SO.NPARAM
+    ctx = P.Context.from_graph(g)
+    trim = O.trim_index(O.degrees(g))
+    sigma = 0.05 if name == "grid3d_w" else 0.0
+    p = _params(1)
+    ctx.spai_install(torch.as_tensor(p, device="cuda"), sigma=sigma, trim=-1)
+    diag, offd = ctx.spai_export()
+    fw = SO.forward(g, p, sigma, trim)
+    diag = diag.cpu().numpy().astype(np.float64)
+    offd = offd.cpu().numpy().astype(np.float64)
+    assert np.allclose(diag, fw["diag"], rtol=2e-5, atol=1e-7 * np.abs(fw["diag"]).max())
+    assert np.allclose(offd, fw["offd"], rtol=2e-4, atol=1e-6 * np.abs(fw["diag"]).max())
+    assert diag[trim] == 0.0
+    # strict diagonal dominance holds for the GPU values themselves
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    keep = (rows != trim) & (g.col != trim)
+    rowsum = np.zeros(g.n)
+    np.add.at(rowsum, rows[keep], np.abs(offd[keep]))
+    mask = np.arange(g.n) != trim
+    assert np.all(rowsum[mask] < diag[mask])
+
+
+@pytest.mark.parametrize("name", ["rmat12", "grid3d_w"])
+def test_loss_and_gradient_match_oracle(P, name):
+    g = GRAPHS[name]()
+    ctx = P.Context.from_graph(g)
+    trim = O.trim_index(O.degrees(g))
+    sigma = 0.05 if name == "grid3d_w" else 0.0
+    p = _params(2)
+    S = 5
+    rng = np.random.default_rng(3)
+    R = rng.standard_normal((g.n, S)).astype(np.float32)
+    Z = rng.standard_normal((g.n, S)).astype(np.float32)
+    R[trim] = 0
+    Z[trim] = 0
+    loss, grad = ctx.spai_loss_grad(torch.as_tensor(p, device="cuda"),
+                                    torch.as_tensor(np.ascontiguousarray(R.T), device="cuda"),
+                                    torch.as_tensor(np.ascontiguousarray(Z.T), device="cuda"),
+                                    sigma=sigma)
+    Lo, go = SO.loss_grad(g, p, sigma, trim, R.astype(np.float64), Z.astype(np.float64))
+    assert loss == pytest.approx(Lo, rel=1e-5)
+    grad = grad.cpu().numpy().astype(np.float64)
+    scale = np.abs(go).max()
+    assert np.abs(grad - go).max() <= 2e-4 * scale
+    # per-block relative agreement for every parameter group
+    for k, (o, sz) in SO.OFF.items():
+        ref = go[o:o + sz]
+        if np.abs(ref).max() > 1e-3 * scale:
+            assert np.linalg.norm(grad[o:o + sz] - ref) <= 2e-3 * np.linalg.norm(ref), k
+
+
+def test_adam_step(P):
+    g = gg.path_graph(10)
+    ctx = P.Context.from_graph(g)
+    rng = np.random.default_rng(4)
+    p = rng.standard_normal(1000).astype(np.float32)
+    gr = rng.standard_normal(1000).astype(np.float32)
+    m = rng.standard_normal(1000).astype(np.float32) * 0.1
+    v = np.abs(rng.standard_normal(1000).astype(np.float32)) * 0.1
+    tp, tg, tm, tv = (torch.as_tensor(a.copy(), device="cuda") for a in (p, gr, m, v))
+    ctx.adam_step(tp, tg, tm, tv, lr=1e-2, step=3)
+    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 1e-2
+    m2 = b1 * m + (1 - b1) * gr
+    v2 = b2 * v + (1 - b2) * gr * gr
+    p2 = p - lr * (m2 / (1 - b1 ** 3)) / (np.sqrt(v2 / (1 - b2 ** 3)) + eps)
+    assert np.allclose(tp.cpu().numpy(), p2, rtol=1e-5, atol=1e-6)
+    assert np.allclose(tm.cpu().numpy(), m2, rtol=1e-6)
+    assert np.allclose(tv.cpu().numpy(), v2, rtol=1e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_learned_inner_solve(P, prec):
+    g = GRAPHS["rmat12"]()
+    ctx = P.Context.from_graph(g)
+    L = O.laplacian(g)
+    d = O.degrees(g)
+    trim = O.trim_index(d)
+    delta = O.deflation_shift(d)
+    res = O.isira(g, 4, 0.0, 1e-9, gg.start_block(g.n, 4, 3), inner_rtol=1e-8)
+    V = res.evecs
+    p = _params(5, jitter=0.1)
+    ctx.spai_install(torch.as_tensor(p, device="cuda"), sigma=0.0)
+    fw = SO.forward(g, p, 0.0, trim)
+    r = np.random.default_rng(6).standard_normal(g.n)
+    r -= r.mean()
+    rtol = 1e-10 if prec == 0 else 1e-4
+    z, its, rel = ctx.inner_solve(torch.as_tensor(r, device="cuda"),
+                                  torch.as_tensor(np.ascontiguousarray(V.T), device="cuda"),
+                                  rtol=rtol, max_it=5000, prec=prec, precond=P.isira.PC_LEARNED)
+    z = z.cpu().numpy()
+    assert rel <= rtol
+    # reference: the oracle's inner solve with the oracle's own M as preconditioner
+    keep = np.array([i for i in range(g.n) if i != trim])
+    Mh = SO.dense_M(g, fw["diag"], fw["offd"])[np.ix_(keep, keep)]
+    z_ref, its_ref, _ = O.inner_solve(L, d, r, trim, 0.0, delta, V, 1e-12, 20000,
+                                      apply_minv_hat=lambda x: Mh @ x)
+    if prec == 0:
+        assert np.linalg.norm(z - z_ref) <= 1e-7 * np.linalg.norm(z_ref)
+        assert abs(its - its_ref) <= max(3, 0.1 * its_ref)
+    else:
+        Lt = L @ z + delta * V @ (V.T @ z)
+        assert np.linalg.norm(Lt - r) <= 5e-3 * np.linalg.norm(r)

@@ -1,0 +1,79 @@
+"""Pins of the SPAI network oracle: central finite differences of its hand-written
+backward pass, the SPD construction, BF16 rounding, and the Jacobi special case."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+from oracle import spai_oracle as SO
+from oracle import isira_oracle as O
+
+
+def _samples(g, trim, S, seed):
+    rng = np.random.default_rng(seed)
+    R = rng.standard_normal((g.n, S))
+    Z = rng.standard_normal((g.n, S))
+    R[trim] = 0.0
+    Z[trim] = 0.0
+    return R, Z
+
+
+@pytest.mark.parametrize("gname", ["rand_w", "rmat", "grid"])
+def test_backward_matches_central_differences(gname):
+    g = {"rand_w": lambda: gg.random_connected(40, 70, seed=3, weights=(0.5, 1.5)),
+         "rmat": lambda: gg.rmat(7, 8, seed=4),
+         "grid": lambda: gg.grid2d(6, 5)}[gname]()
+    trim = O.trim_index(O.degrees(g))
+    sigma = 0.1 if gname == "rand_w" else 0.0
+    rng = np.random.default_rng(1)
+    p = SO.init_params(2).astype(np.float64) + 0.2 * rng.standard_normal(SO.NPARAM)
+    R, Z = _samples(g, trim, 3, 5)
+    L, grad = SO.loss_grad(g, p, sigma, trim, R, Z, round_bf16=False)
+    assert L == pytest.approx(SO.loss(g, p, sigma, trim, R, Z, round_bf16=False), rel=1e-14)
+    idx = np.unique(np.concatenate([rng.choice(SO.NPARAM, 80, replace=False),
+                                    [SO.OFF[k][0] for k in SO.OFF]]))
+    h = 1e-6
+    for i in idx:
+        pp = p.copy()
+        pm = p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (SO.loss(g, pp, sigma, trim, R, Z, False) - SO.loss(g, pm, sigma, trim, R, Z, False)) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, grad[i])
+
+
+def test_M_is_symmetric_sdd_and_spd():
+    g = gg.rmat(8, 8, seed=6)
+    trim = O.trim_index(O.degrees(g))
+    p = SO.init_params(3).astype(np.float64)
+    p[SO.OFF["ce"][0]] = 3.0  # large edge values: stress the dominance bound
+    fw = SO.forward(g, p.astype(np.float32), 0.0, trim)
+    M = SO.dense_M(g, fw["diag"], fw["offd"])
+    keep = np.array([i for i in range(g.n) if i != trim])
+    Mh = M[np.ix_(keep, keep)]
+    assert np.array_equal(Mh, Mh.T)
+    off = np.abs(Mh).sum(axis=1) - np.abs(np.diag(Mh))
+    assert np.all(np.diag(Mh) > 0) and np.all(off < np.diag(Mh))
+    assert np.linalg.eigvalsh(Mh).min() > 0
+    assert np.all(M[trim] == 0) and np.all(M[:, trim] == 0)
+
+
+def test_bf16_rounding_published_format():
+    # bfloat16 keeps 8 significant bits; ties go to the even significand
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5, 1.0 + 2 ** -7, 3.0e38], dtype=np.float32)
+    out = SO.bf16_round(vals)
+    assert list(out[:5]) == [1.0, 1.0, 1.0 + 2 ** -6, -2.5, 1.0 + 2 ** -7]
+    assert np.isfinite(out[5])
+
+
+def test_zero_network_is_jacobi():
+    g = gg.random_connected(30, 40, seed=7, weights=(0.5, 1.5))
+    trim = 4
+    P = {k: np.zeros(v) if v > 1 else 0.0 for k, (o, v) in SO.OFF.items()}
+    P = SO.unpack(np.zeros(SO.NPARAM))
+    P["bd"] = float(np.log(np.e - 1.0))
+    fw = SO.forward(g, SO.pack(P), 0.3, trim, round_bf16=False)
+    d = O.degrees(g)
+    ref = 1.0 / (d - 0.3)
+    ref[trim] = 0.0
+    assert np.allclose(fw["diag"], ref, rtol=1e-14)
+    assert np.all(fw["offd"] == 0.0)
