@@ -139,7 +139,7 @@ static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp) {
     while (G < 64 && G * 4 < cnt) G <<= 1;
     return G;
   };
-  std::vector<int32_t> srow, schunk, sslot, sbase, snch;
+  std::vector<int32_t> srow, schunk, sslot, sbase, snch, srowof;
   int units = 0;
   int row = 0;
   int nchunks_total = 0;
@@ -160,6 +160,7 @@ static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp) {
         const int slot = (int)sbase.size();
         sbase.push_back(nchunks_total);
         snch.push_back(nch);
+        srowof.push_back(r);
         for (int c = 0; c < nch; ++c) {
           srow.push_back(r);
           schunk.push_back(c);
@@ -185,6 +186,7 @@ static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp) {
   if ((rc = dalloc(&P.split_chunk, srow.size()))) return rc;
   if ((rc = dalloc(&P.split_slot, srow.size()))) return rc;
   if ((rc = dalloc(&P.split_base, sbase.size()))) return rc;
+  if ((rc = dalloc(&P.split_rowof, sbase.size()))) return rc;
   if ((rc = dalloc(&P.split_nchunk, sbase.size()))) return rc;
   if ((rc = dalloc(&P.split_cnt, sbase.size()))) return rc;
   if ((rc = dalloc(&P.split_part, (size_t)nchunks_total))) return rc;
@@ -194,6 +196,7 @@ static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp) {
     CKH(hipMemcpy(P.split_chunk, schunk.data(), srow.size() * 4, hipMemcpyHostToDevice));
     CKH(hipMemcpy(P.split_slot, sslot.data(), srow.size() * 4, hipMemcpyHostToDevice));
     CKH(hipMemcpy(P.split_base, sbase.data(), sbase.size() * 4, hipMemcpyHostToDevice));
+    CKH(hipMemcpy(P.split_rowof, srowof.data(), sbase.size() * 4, hipMemcpyHostToDevice));
     CKH(hipMemcpy(P.split_nchunk, snch.data(), sbase.size() * 4, hipMemcpyHostToDevice));
     CKH(hipMemset(P.split_cnt, 0, sbase.size() * 4));
     CKH(hipMemset(P.split_red, 0, sbase.size() * 8));
@@ -398,8 +401,7 @@ extern "C" int isira_create(isira_ctx** out, int64_t n, int64_t nnz, const int32
     if ((rc = dalloc(&ctx->w64, nnz))) return cleanup(rc);
     if ((rc = dalloc(&ctx->w32, nnz))) return cleanup(rc);
   }
-  const size_t npart = std::max((size_t)kMaxCols * kStreamGrid, (size_t)4 * kSpmvGrid);
-  if ((rc = dalloc(&ctx->rb.partials, npart))) return cleanup(rc);
+  if ((rc = dalloc(&ctx->rb.partials, kPartialsElems))) return cleanup(rc);
   if ((rc = dalloc(&ctx->rb.counters, 64))) return cleanup(rc);
   if ((rc = dalloc(&ctx->st, 1))) return cleanup(rc);
   if ((rc = dalloc(&ctx->hbuf, kMaxCols))) return cleanup(rc);
@@ -450,6 +452,7 @@ extern "C" void isira_destroy(isira_ctx* c) {
   dfree(c->d_perm); dfree(c->d_iperm); dfree(c->d_emap);
   dfree(c->plan.split_row); dfree(c->plan.split_chunk); dfree(c->plan.split_slot);
   dfree(c->plan.split_base); dfree(c->plan.split_nchunk); dfree(c->plan.split_cnt);
+  dfree(c->plan.split_rowof);
   dfree(c->plan.split_part); dfree(c->plan.split_red);
   dfree(c->rb.partials); dfree(c->rb.counters); dfree(c->st); dfree(c->hbuf); dfree(c->scal4);
   dfree(c->svec); dfree(c->Sdev); dfree(c->Ginv);
@@ -1043,15 +1046,16 @@ extern "C" int isira_time_spmv(isira_ctx* c, int32_t prec, int32_t reps, double*
   SpmvArgs<float> a32{};
   a32.rp = c->rp; a32.col = c->col; a32.vals = c->w32; a32.x = c->x32; a32.y = c->y32;
   a32.diag = c->deg32; a32.n = n; a32.trim = -1;
-  for (int w = 0; w < 3; ++w) {
-    if (prec == ISIRA_FP64) spmv64(c, c->x64, c->y64, nullptr, 0, nullptr, 0.0, 0, 0.0);
-    else launch_spmv<float>(c->plan, valmode32(c), a32, c->rb, s);
-  }
+  SpmvArgs<double> a64{};
+  a64.rp = c->rp; a64.col = c->col; a64.vals = c->w64; a64.x = c->x64; a64.y = c->y64;
+  a64.diag = c->deg; a64.n = n; a64.trim = -1;
+  auto launch = [&]() {
+    if (prec == ISIRA_FP64) launch_spmv_probe<double>(c->plan, valmode64(c), a64, c->rb.partials, s);
+    else launch_spmv_probe<float>(c->plan, valmode32(c), a32, c->rb.partials, s);
+  };
+  for (int w = 0; w < 3; ++w) launch();
   CKH(hipEventRecord(e0, s));
-  for (int r = 0; r < reps; ++r) {
-    if (prec == ISIRA_FP64) spmv64(c, c->x64, c->y64, nullptr, 0, nullptr, 0.0, 0, 0.0);
-    else launch_spmv<float>(c->plan, valmode32(c), a32, c->rb, s);
-  }
+  for (int r = 0; r < reps; ++r) launch();
   CKH(hipEventRecord(e1, s));
   CKH(hipEventSynchronize(e1));
   float ms = 0;

@@ -11,7 +11,7 @@
 namespace isira {
 
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
-constexpr int kStreamGrid = 1024;      // max workgroups of grid-stride streaming kernels
+constexpr int kStreamGrid = 512;       // max workgroups of grid-stride streaming kernels
 constexpr int kSpmvGrid = 2048;        // max workgroups of the persistent SpMV grid
 constexpr int kSplitChunk = 4096;      // nnz per chunk of a split (very long) row
 constexpr int kBlockRowMin = 1024;     // rows longer than this get a whole workgroup
@@ -19,6 +19,15 @@ constexpr int kMaxSegs = 16;           // SpMV segments (row-length classes)
 constexpr int kMaxC = ISIRA_MAX_K;     // deflation columns in the inner solve
 constexpr int kTile = 512;             // rows per tile of the column-dot kernels
 constexpr int kMaxCols = 2 * ISIRA_MAX_BASIS + 2;  // columns of one multi-dot
+// Values x workgroups of the largest reduction in the learned-preconditioner backward pass.
+constexpr int kSpaiRedValues = 600;
+constexpr int kSpaiRedGrid = 512;
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+// Capacity (doubles) of the shared partials buffer: every reducing kernel writes at most
+// values x workgroups of it, each checked against this bound at compile time.
+constexpr size_t kPartialsElems =
+    cmax(cmax((size_t)kMaxCols * kStreamGrid, (size_t)4 * kSpmvGrid),
+         (size_t)kSpaiRedValues * kSpaiRedGrid);
 
 // One row-length class of the SpMV: rows [row_begin, row_end) of the relabelled graph.
 // lanes in 1..64: `lanes` lanes per row, 256/lanes rows per unit; 256: one workgroup per
@@ -45,10 +54,12 @@ struct DevState {
 
 enum PcgStatus { kPcgOk = 0, kPcgCapped = 1, kPcgBreakdown = 2 };
 
-// Reduction scratch shared by kernels on one stream (kernels run one after another).
+// Reduction scratch shared by kernels on one stream (kernels run one after another): each
+// reducing kernel writes one partial per workgroup and value, and a finishing dispatch
+// sums them in a fixed order.
 struct RedBuf {
-  double* partials;   // kMaxCols * kSpmvGrid doubles
-  unsigned* counters; // 64 counters, zeroed at creation and reset by each last workgroup
+  double* partials;   // max(kMaxCols * kStreamGrid, 4 * kSpmvGrid) doubles
+  unsigned* counters; // 64 counters (setup kernels only), zeroed at creation
 };
 
 // SpMV execution plan (device arrays for split rows).
@@ -56,6 +67,7 @@ struct SpmvPlan {
   SpmvSegs segs;
   int32_t grid = 0;
   int32_t n_split_units = 0, n_split_rows = 0;
+  int32_t* split_rowof = nullptr;  // per split row slot: the row
   int32_t* split_row = nullptr;    // per split unit: row
   int32_t* split_chunk = nullptr;  // per split unit: chunk index within the row
   int32_t* split_slot = nullptr;   // per split unit: slot of its row (0..n_split_rows-1)
@@ -103,6 +115,10 @@ void launch_argmax_degree(const double* d, const int32_t* perm, int n, DevState*
 template <typename T>
 void launch_spmv(const SpmvPlan& plan, int valmode, const SpmvArgs<T>& a, RedBuf rb,
                  hipStream_t s);
+// the same product under a separate kernel symbol, for bandwidth measurement (red = 0)
+template <typename T>
+void launch_spmv_probe(const SpmvPlan& plan, int valmode, const SpmvArgs<T>& a, double* partials,
+                       hipStream_t s);
 
 template <typename T>
 void launch_pcg_update1(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const T* V,

@@ -79,6 +79,10 @@ __device__ void write_partials(const double (&acc)[NV], int nv, double* partials
     partials[(size_t)v * gridDim.x + blockIdx.x] = (sh[0][v] + sh[1][v]) + (sh[2][v] + sh[3][v]);
 }
 
+static_assert((size_t)(2 + kMaxC) * kStreamGrid <= kPartialsElems, "PCG partials");
+static_assert((size_t)kMaxCols * kStreamGrid <= kPartialsElems, "multi-dot partials");
+static_assert((size_t)kSpmvGrid <= kPartialsElems, "SpMV partials");
+
 static inline int stream_grid(int n) {
   int g = (n + kBlock - 1) / kBlock;
   return g < 1 ? 1 : (g > kStreamGrid ? kStreamGrid : g);
@@ -209,6 +213,7 @@ void launch_signed_gather(int n, const double* v, const int32_t* perm, const int
 // ------------------------------------------------------------------ sparse product
 
 struct SplitInfo {
+  const int32_t* rowof;  // per slot: the split row
   const int32_t* row;
   const int32_t* chunk;
   const int32_t* slot;
@@ -278,7 +283,9 @@ __device__ __forceinline__ double finish_row(const SpmvArgs<T>& a, int row, T ns
   return 0.0;
 }
 
-template <typename T, int VM>
+// TAG only separates the symbol of the bandwidth probe (isira_time_spmv) from the solver's
+// launches in profiler summaries; the code is identical.
+template <typename T, int VM, int TAG = 0>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs<T> a, SpmvSegs segs, SplitInfo sp,
                                                  double* partials, unsigned* counter) {
   if (a.check_done && a.st->done) return;
@@ -325,29 +332,40 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs<T> a, SpmvSegs segs, S
       __syncthreads();
       if ((tid & 63) == 0) shT[tid >> 6] = s;
       __syncthreads();
-      if (tid == 0) {
-        sp.part[sp.base[slot] + ch] = (double)((shT[0] + shT[1]) + (shT[2] + shT[3]));
-        __threadfence();
-        const unsigned prev = atomicAdd(&sp.cnt[slot], 1u);
-        if (prev == (unsigned)(sp.nchunk[slot] - 1)) {
-          __threadfence();
-          double tot = 0.0;
-          const int nb = sp.nchunk[slot], pb = sp.base[slot];
-          for (int k = 0; k < nb; ++k) tot += sp.part[pb + k];
-          sp.red[slot] = finish_row<VM, T>(a, row, (T)tot, sh_t, shift_add);
-          sp.cnt[slot] = 0u;
-        }
-      }
+      if (tid == 0) sp.part[sp.base[slot] + ch] = (double)((shT[0] + shT[1]) + (shT[2] + shT[3]));
+      (void)row;
     }
   }
   if (a.red == 0) return;
   const double bs = block_sum1(acc, sh4);
   if (tid == 0) partials[blockIdx.x] = bs;
-  if (!arrive_last(counter)) return;
-  __shared__ double sh_out[1];
-  final_reduce(partials, 1, gridDim.x, sh_out);
+}
+
+// Second dispatch of the sparse product: finishes the split rows from their chunk sums
+// (fixed chunk order) and reduces the per-workgroup partials plus the split rows'
+// contributions (fixed order).  One workgroup.
+template <typename T, int VM>
+__global__ __launch_bounds__(kBlock) void k_spmv_fin(SpmvArgs<T> a, SplitInfo sp, int nblk,
+                                                     const double* partials) {
+  if (a.check_done && a.st->done) return;
+  __shared__ double sh_t[kMaxC];
+  __shared__ double sh_red[1];
+  const int tid = threadIdx.x;
+  const double* tv = a.tvec ? a.tvec : (a.st ? a.st->t1 : nullptr);
+  for (int j = tid; j < a.c; j += kBlock) sh_t[j] = tv[j];
+  const T shift_add = (a.sig_over_n != 0.0) ? (T)(a.sig_over_n * a.st->sump) : T(0);
+  __syncthreads();
+  for (int slot = tid; slot < sp.nslots; slot += kBlock) {
+    double tot = 0.0;
+    const int nb = sp.nchunk[slot], pb = sp.base[slot];
+    for (int k = 0; k < nb; ++k) tot += sp.part[pb + k];
+    sp.red[slot] = finish_row<VM, T>(a, sp.rowof[slot], (T)tot, sh_t, shift_add);
+  }
+  if (a.red == 0) return;
+  __syncthreads();
+  final_reduce(partials, 1, nblk, sh_red);
   if (tid == 0) {
-    double tot = sh_out[0];
+    double tot = sh_red[0];
     for (int k = 0; k < sp.nslots; ++k) tot += sp.red[k];
     DevState* st = a.st;
     if (a.red == 1) {
@@ -363,33 +381,47 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs<T> a, SpmvSegs segs, S
     } else {
       st->red[1] = tot;
     }
-    *counter = 0u;
   }
+}
+
+static SplitInfo split_info(const SpmvPlan& plan) {
+  return SplitInfo{plan.split_rowof, plan.split_row, plan.split_chunk, plan.split_slot,
+                   plan.split_base, plan.split_nchunk, plan.split_cnt, plan.split_part,
+                   plan.split_red, plan.n_split_rows};
+}
+
+template <typename T, int VM, int TAG>
+static void spmv_dispatch(const SpmvPlan& plan, const SpmvArgs<T>& a, double* partials,
+                          hipStream_t s) {
+  const SplitInfo sp = split_info(plan);
+  k_spmv<T, VM, TAG><<<plan.grid, kBlock, 0, s>>>(a, plan.segs, sp, partials, nullptr);
+  if (plan.n_split_rows > 0 || a.red != 0)
+    k_spmv_fin<T, VM><<<1, kBlock, 0, s>>>(a, sp, plan.grid, partials);
 }
 
 template <typename T>
 void launch_spmv(const SpmvPlan& plan, int valmode, const SpmvArgs<T>& a, RedBuf rb,
                  hipStream_t s) {
-  SplitInfo sp{plan.split_row, plan.split_chunk, plan.split_slot, plan.split_base,
-               plan.split_nchunk, plan.split_cnt, plan.split_part, plan.split_red,
-               plan.n_split_rows};
-  unsigned* cnt = rb.counters + 1;
   switch (valmode) {
-    case kUnitNeg:
-      k_spmv<T, kUnitNeg><<<plan.grid, kBlock, 0, s>>>(a, plan.segs, sp, rb.partials, cnt);
-      break;
-    case kF32Neg:
-      k_spmv<T, kF32Neg><<<plan.grid, kBlock, 0, s>>>(a, plan.segs, sp, rb.partials, cnt);
-      break;
-    case kF64Neg:
-      k_spmv<T, kF64Neg><<<plan.grid, kBlock, 0, s>>>(a, plan.segs, sp, rb.partials, cnt);
-      break;
-    default:
-      k_spmv<T, kF32Pos><<<plan.grid, kBlock, 0, s>>>(a, plan.segs, sp, rb.partials, cnt);
-      break;
+    case kUnitNeg: spmv_dispatch<T, kUnitNeg, 0>(plan, a, rb.partials, s); break;
+    case kF32Neg: spmv_dispatch<T, kF32Neg, 0>(plan, a, rb.partials, s); break;
+    case kF64Neg: spmv_dispatch<T, kF64Neg, 0>(plan, a, rb.partials, s); break;
+    default: spmv_dispatch<T, kF32Pos, 0>(plan, a, rb.partials, s); break;
   }
   HIP_LAUNCH_CHECK();
 }
+template <typename T>
+void launch_spmv_probe(const SpmvPlan& plan, int valmode, const SpmvArgs<T>& a, double* partials,
+                       hipStream_t s) {
+  if (valmode == kUnitNeg) spmv_dispatch<T, kUnitNeg, 1>(plan, a, partials, s);
+  else if (valmode == kF64Neg) spmv_dispatch<T, kF64Neg, 1>(plan, a, partials, s);
+  else spmv_dispatch<T, kF32Neg, 1>(plan, a, partials, s);
+  HIP_LAUNCH_CHECK();
+}
+template void launch_spmv_probe<double>(const SpmvPlan&, int, const SpmvArgs<double>&, double*,
+                                        hipStream_t);
+template void launch_spmv_probe<float>(const SpmvPlan&, int, const SpmvArgs<float>&, double*,
+                                       hipStream_t);
 template void launch_spmv<double>(const SpmvPlan&, int, const SpmvArgs<double>&, RedBuf,
                                   hipStream_t);
 template void launch_spmv<float>(const SpmvPlan&, int, const SpmvArgs<float>&, RedBuf,
@@ -430,11 +462,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update1(int n, T* __restrict__ x
     for (int j = 0; j < CM; ++j)
       if (j < c) acc[2 + j] += (double)V[l + (int64_t)j * ldv] * (double)u;
   }
-  const int nv = 2 + c;
-  write_partials<NV>(acc, nv, partials);
-  if (!arrive_last(counter)) return;
-  __shared__ double red[NV];
-  final_reduce(partials, nv, gridDim.x, red);
+  write_partials<NV>(acc, 2 + c, partials);
+}
+
+// Reduces the partials of k_pcg_update1 (one workgroup), forms g = G^-1 t2 and
+// rho = r^T M^-1 r - delta t2^T g, tests convergence and sets beta.
+__global__ __launch_bounds__(kBlock) void k_pcg_fin1(int c, int nblk, const double* partials,
+                                                     const double* Ginv, double delta, int init,
+                                                     DevState* st) {
+  if (st->done) return;
+  __shared__ double red[2 + kMaxC];
+  final_reduce(partials, 2 + c, nblk, red);
   // g = Ginv t2 (c x c, column-major)
   for (int j = threadIdx.x; j < c; j += kBlock) {
     double gj = 0.0;
@@ -478,7 +516,6 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update1(int n, T* __restrict__ x
         st->done = 1;
       }
     }
-    *counter = 0u;
   }
 }
 
@@ -520,16 +557,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update2(int n, const T* __restri
     for (int j = 0; j < CM; ++j)
       if (j < c) acc[1 + j] += (double)vreg[j] * (double)pn;
   }
-  const int nv = 1 + c;
-  write_partials<NV>(acc, nv, partials);
-  if (!arrive_last(counter)) return;
-  __shared__ double red[NV];
-  final_reduce(partials, nv, gridDim.x, red);
+  write_partials<NV>(acc, 1 + c, partials);
+}
+
+// Reduces the partials of the p-update (one workgroup): t1 = V-hat^T p, sum(p).
+__global__ __launch_bounds__(kBlock) void k_pcg_fin2(int c, int nblk, const double* partials,
+                                                     DevState* st) {
+  if (st->done) return;
+  __shared__ double red[1 + kMaxC];
+  final_reduce(partials, 1 + c, nblk, red);
   for (int j = threadIdx.x; j < c; j += kBlock) st->t1[j] = red[1 + j];
-  if (threadIdx.x == 0) {
-    st->sump = red[0];
-    *counter = 0u;
-  }
+  if (threadIdx.x == 0) st->sump = red[0];
 }
 
 static inline int pick_cm(int c) {
@@ -568,6 +606,7 @@ void launch_pcg_update1(int n, T* x, T* r, const T* p, const T* q, const T* dinv
                                                    init, st, rb.partials, cnt);
       break;
   }
+  k_pcg_fin1<<<1, kBlock, 0, s>>>(c, grid, rb.partials, Ginv, delta, init, st);
   HIP_LAUNCH_CHECK();
 }
 
@@ -598,6 +637,7 @@ void launch_pcg_update2(int n, const T* r, T* p, const T* dinv, const T* V, int6
                                                    rb.partials, cnt);
       break;
   }
+  k_pcg_fin2<<<1, kBlock, 0, s>>>(c, grid, rb.partials, st);
   HIP_LAUNCH_CHECK();
 }
 template void launch_pcg_update1<double>(int, double*, double*, const double*, const double*,
@@ -637,9 +677,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update1_plain(int n, T* __restri
     acc[0] += (double)rl * (double)rl;
   }
   write_partials<1>(acc, 1, partials);
-  if (!arrive_last(counter)) return;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pcg_fin1_plain(int nblk, const double* partials,
+                                                           int init, DevState* st) {
+  if (st->done) return;
   __shared__ double red[1];
-  final_reduce(partials, 1, gridDim.x, red);
+  final_reduce(partials, 1, nblk, red);
   if (threadIdx.x == 0) {
     const double rr = red[0];
     st->rr = rr;
@@ -660,7 +704,6 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update1_plain(int n, T* __restri
         st->status = kPcgBreakdown;
       }
     }
-    *counter = 0u;
   }
 }
 
@@ -727,16 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update2_learned(
     for (int j = 0; j < CM; ++j)
       if (j < c) acc[1 + j] += (double)V[l + (int64_t)j * ldv] * (double)pn;
   }
-  const int nv = 1 + c;
-  write_partials<NV>(acc, nv, partials);
-  if (!arrive_last(counter)) return;
-  __shared__ double red[NV];
-  final_reduce(partials, nv, gridDim.x, red);
-  for (int j = threadIdx.x; j < c; j += kBlock) st->t1[j] = red[1 + j];
-  if (threadIdx.x == 0) {
-    st->sump = red[0];
-    *counter = 0u;
-  }
+  write_partials<NV>(acc, 1 + c, partials);
 }
 
 template <typename T>
@@ -744,6 +778,7 @@ void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, int ini
                               RedBuf rb, hipStream_t s) {
   k_pcg_update1_plain<T><<<stream_grid(n), kBlock, 0, s>>>(n, x, r, p, q, init, st,
                                                           rb.partials, rb.counters + 4);
+  k_pcg_fin1_plain<<<1, kBlock, 0, s>>>(stream_grid(n), rb.partials, init, st);
   HIP_LAUNCH_CHECK();
 }
 template <typename T>
@@ -774,6 +809,7 @@ void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv
                                                            st, rb.partials, cnt);
       break;
   }
+  k_pcg_fin2<<<1, kBlock, 0, s>>>(c, grid, rb.partials, st);
   HIP_LAUNCH_CHECK();
 }
 template void launch_pcg_update1_plain<double>(int, double*, double*, const double*,
@@ -820,13 +856,12 @@ __global__ __launch_bounds__(kBlock) void k_sum(int n, const T* __restrict__ x,
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
     acc[0] += (double)x[l];
   write_partials<1>(acc, 1, partials);
-  if (!arrive_last(counter)) return;
+}
+__global__ __launch_bounds__(kBlock) void k_sum_fin(int nblk, const double* partials,
+                                                    DevState* st) {
   __shared__ double red[1];
-  final_reduce(partials, 1, gridDim.x, red);
-  if (threadIdx.x == 0) {
-    st->sumx = red[0];
-    *counter = 0u;
-  }
+  final_reduce(partials, 1, nblk, red);
+  if (threadIdx.x == 0) st->sumx = red[0];
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_enlarge(int n, const T* __restrict__ x,
@@ -839,6 +874,7 @@ template <typename T>
 void launch_enlarge(int n, const T* x, double* z, DevState* st, RedBuf rb, hipStream_t s) {
   const int grid = stream_grid(n);
   k_sum<T><<<grid, kBlock, 0, s>>>(n, x, st, rb.partials, rb.counters + 6);
+  k_sum_fin<<<1, kBlock, 0, s>>>(grid, rb.partials, st);
   k_enlarge<T><<<grid, kBlock, 0, s>>>(n, x, z, st);
   HIP_LAUNCH_CHECK();
 }
@@ -892,11 +928,17 @@ __global__ __launch_bounds__(kBlock) void k_multidot(int n, const T* __restrict_
   }
   __syncthreads();
   for (int v = tid; v < nv; v += kBlock) partials[(size_t)v * gridDim.x + blockIdx.x] = acc[v];
-  if (!arrive_last(counter)) return;
-  __shared__ double red[kMaxCols];
-  final_reduce(partials, nv, gridDim.x, red);
-  for (int v = tid; v < nv; v += kBlock) h[v] = red[v];
-  if (tid == 0) *counter = 0u;
+}
+
+// h[v] = sum over workgroups of partials[v * nblk + b]; one wave per value, fixed order.
+__global__ __launch_bounds__(64) void k_values_fin(int nv, int nblk, const double* partials,
+                                                   double* h) {
+  const int v = blockIdx.x;
+  if (v >= nv) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) s += partials[(size_t)v * nblk + b];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) h[v] = s;
 }
 
 template <typename T>
@@ -907,6 +949,8 @@ void launch_multidot(int n, const T* A, int64_t lda, int na, const T* B, int64_t
   if (grid > kStreamGrid) grid = kStreamGrid;
   k_multidot<T><<<grid, kBlock, 0, s>>>(n, A, lda, na, B, ldb, nb, z, wz, with_sum, with_self,
                                         h, rb.partials, rb.counters + 7);
+  const int nv = na + nb + with_sum + with_self;
+  k_values_fin<<<nv, 64, 0, s>>>(nv, grid, rb.partials, h);
   HIP_LAUNCH_CHECK();
 }
 template void launch_multidot<double>(int, const double*, int64_t, int, const double*, int64_t,
@@ -940,13 +984,6 @@ __global__ __launch_bounds__(kBlock) void k_gemv_sub(int n, const double* __rest
   }
   if (!with_norm) return;
   write_partials<1>(acc, 1, partials);
-  if (!arrive_last(counter)) return;
-  __shared__ double red[1];
-  final_reduce(partials, 1, gridDim.x, red);
-  if (threadIdx.x == 0) {
-    st->red[2] = red[0];
-    *counter = 0u;
-  }
 }
 
 void launch_gemv_sub(int n, const double* A, int64_t lda, int na, const double* B, int64_t ldb,
@@ -954,6 +991,7 @@ void launch_gemv_sub(int n, const double* A, int64_t lda, int na, const double* 
                      DevState* st, RedBuf rb, hipStream_t s) {
   k_gemv_sub<<<stream_grid(n), kBlock, 0, s>>>(n, A, lda, na, B, ldb, nb, h, with_sum, z,
                                                with_norm, st, rb.partials, rb.counters + 8);
+  if (with_norm) k_values_fin<<<1, 64, 0, s>>>(1, stream_grid(n), rb.partials, st->red + 2);
   HIP_LAUNCH_CHECK();
 }
 
@@ -993,20 +1031,13 @@ __global__ __launch_bounds__(kBlock) void k_ritz_residual(int n, const double* _
     acc[1] += rl;
   }
   write_partials<2>(acc, 2, partials);
-  if (!arrive_last(counter)) return;
-  __shared__ double red[2];
-  final_reduce(partials, 2, gridDim.x, red);
-  if (threadIdx.x == 0) {
-    st->red[0] = red[0];
-    st->red[1] = red[1];
-    *counter = 0u;
-  }
 }
 void launch_ritz_residual(int n, const double* U, const double* W, int64_t ld, int k,
                           const double* svec, double theta, double* r, DevState* st, RedBuf rb,
                           hipStream_t s) {
   k_ritz_residual<<<stream_grid(n), kBlock, 0, s>>>(n, U, W, ld, k, svec, theta, r, st,
                                                     rb.partials, rb.counters + 9);
+  k_values_fin<<<2, 64, 0, s>>>(2, stream_grid(n), rb.partials, st->red);
   HIP_LAUNCH_CHECK();
 }
 

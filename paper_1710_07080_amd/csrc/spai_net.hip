@@ -31,6 +31,8 @@ constexpr int NV_VERT = obd + 1;      // gradients reduced over vertices: params
 constexpr int NV_EDGE = NP - oWe;     // gradients reduced over edges:    params [oWe, NP)
 constexpr float kEps = 0.05f;
 static_assert(NV_VERT == oWe, "layout");
+static_assert(NV_EDGE <= kSpaiRedValues && NV_VERT <= kSpaiRedValues && 64 <= kSpaiRedValues,
+              "gradient reductions must fit the partials buffer");
 
 __device__ __forceinline__ float bf16_round(float x) {
   unsigned u = __float_as_uint(x);
@@ -733,7 +735,9 @@ int loss_grad(SpaiWork& w, const int32_t* rp, const int32_t* col, const void* wt
   if (S < 1 || S > 64) return -2;
   if (forward(w, rp, col, wts, wdt, deg, n, nnz, sigma, trim, params, s)) return -1;
   const size_t nS = (size_t)n * S;
-  const size_t need = 4 * nS + (size_t)n * (7 * H + 2) + (size_t)nnz * (2 * H + 1) + 2 * 66;
+  // 4 sample blocks, 6 per-vertex H-vectors + 2 scalars, per-entry dpre/u/dg, then 16-byte
+  // aligned doubles zz[64] and the loss (65 doubles = 130 floats) with generous slack
+  const size_t need = 4 * nS + (size_t)n * (6 * H + 2) + (size_t)nnz * (2 * H + 1) + 512;
   float* base = scratch(w, need);
   if (!base) return -1;
   float* Rt = base;
@@ -761,9 +765,9 @@ int loss_grad(SpaiWork& w, const int32_t* rp, const int32_t* col, const void* wt
   while (Sp < S) Sp <<= 1;
   k_apply_multi<<<grid_for(n, kBlock / Sp, 8192), kBlock, 0, s>>>(n, S, Sp, rp, col, w.diag32,
                                                                   w.offd, trim, Rt, Yt);
-  k_sample_norms<<<grid_for(n, kBlock / 64, 512), kBlock, 0, s>>>(n, S, Zt, rb.partials,
+  k_sample_norms<<<grid_for(n, kBlock / 64, kSpaiRedGrid), kBlock, 0, s>>>(n, S, Zt, rb.partials,
                                                                  rb.counters + 20, zz);
-  k_loss_grad_y<<<grid_for((int64_t)nS, kBlock, 512), kBlock, 0, s>>>(n, S, Yt, Zt, zz, Gt,
+  k_loss_grad_y<<<grid_for((int64_t)nS, kBlock, kSpaiRedGrid), kBlock, 0, s>>>(n, S, Yt, Zt, zz, Gt,
                                                                       rb.partials,
                                                                       rb.counters + 21, dloss);
   const int gw = grid_for(n, kBlock / 64, 8192);
@@ -774,10 +778,10 @@ int loss_grad(SpaiWork& w, const int32_t* rp, const int32_t* col, const void* wt
                                            params, ds, dh, da);
   k_neighbour_mean<<<grid_for(n, kBlock / H, 8192), kBlock, 0, s>>>(n, rp, col, da, dagg, 1);
   k_vertex_backward2<<<gv, kBlock, 0, s>>>(n, dh, dagg, w.h, w.t1, params, dpre2, dpre1);
-  k_vertex_param_grad<<<grid_for(n, kRT, 512), kBlock, 0, s>>>(n, w.feat, w.t1, w.h, w.agg, ds,
+  k_vertex_param_grad<<<grid_for(n, kRT, kSpaiRedGrid), kBlock, 0, s>>>(n, w.feat, w.t1, w.h, w.agg, ds,
                                                                dpre1, dpre2, rb.partials,
                                                                rb.counters + 22, grad);
-  k_edge_param_grad<<<grid_for(nnz, kRT, 512), kBlock, 0, s>>>(nnz, w.rowidx, col, wts, wdt, deg,
+  k_edge_param_grad<<<grid_for(nnz, kRT, kSpaiRedGrid), kBlock, 0, s>>>(nnz, w.rowidx, col, wts, wdt, deg,
                                                                w.h, dpre_e, u_e, dg_e, rb.partials,
                                                                rb.counters + 23, grad);
   if (hipMemcpyAsync(loss_host, dloss, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)

@@ -104,9 +104,10 @@ def test_adam_step(P):
     m2 = b1 * m + (1 - b1) * gr
     v2 = b2 * v + (1 - b2) * gr * gr
     p2 = p - lr * (m2 / (1 - b1 ** 3)) / (np.sqrt(v2 / (1 - b2 ** 3)) + eps)
+    # float32 update formulas; the GPU may contract multiply-adds (one rounding fewer)
     assert np.allclose(tp.cpu().numpy(), p2, rtol=1e-5, atol=1e-6)
-    assert np.allclose(tm.cpu().numpy(), m2, rtol=1e-6)
-    assert np.allclose(tv.cpu().numpy(), v2, rtol=1e-6)
+    assert np.allclose(tm.cpu().numpy(), m2, rtol=1e-5, atol=1e-7)
+    assert np.allclose(tv.cpu().numpy(), v2, rtol=1e-5, atol=1e-8)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
