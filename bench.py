@@ -165,6 +165,8 @@ def main():
         "max_resid": float(np.max(res)),
         "outer_total": st["outer_total"],
         "inner_total": st["inner_total"],
+        "phases_ms": {k: round(st[k], 2) for k in ("ms_total", "ms_inner", "ms_ortho", "ms_rr_host",
+                                                  "ms_residual", "ms_restart")},
         "wall_s_per_step": wall / args.steps,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

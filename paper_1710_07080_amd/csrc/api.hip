@@ -128,78 +128,68 @@ struct isira_ctx {
   spai::SpaiWork spw;
 };
 
-static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp) {
+// SpMV work units from the relabelled CSR (rows by decreasing length): rows longer than
+// the unit size are cut into chunks; the remaining rows are packed greedily, in order, into
+// stream units of at most unit-size nonzeros and a row limit.  A stream unit sums each row
+// with G lanes, G the smallest power of two >= (longest row) / 8, capped at 64.  Graphs
+// whose gathers concentrate on the highest-degree labels use the hub-cached shape.
+static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp,
+                      const std::vector<int32_t>& col) {
   const int n = (int)ctx->n;
   SpmvPlan& P = ctx->plan;
-  P.segs.nseg = 0;
-  auto lanes_for = [](int cnt) {
-    if (cnt > kSplitChunk) return -1;
-    if (cnt > kBlockRowMin) return kBlock;
-    int G = 1;
-    while (G < 64 && G * 4 < cnt) G <<= 1;
-    return G;
-  };
-  std::vector<int32_t> srow, schunk, sslot, sbase, snch, srowof;
-  int units = 0;
+  // power-law test: share of the gathers that hit the first kHubX64 labels (the
+  // highest-degree vertices after relabelling)
+  int64_t hits = 0;
+  for (size_t j = 0; j < col.size(); ++j) hits += col[j] < kHubX64;
+  P.hub = (n > 4 * kHubX64 && (double)hits >= 0.25 * (double)col.size()) ? 1 : 0;
+  const int unnz = P.hub ? kHubUnitNnz : kUnitNnz;
+  const int urows = P.hub ? kHubUnitRows : kUnitRows;
+  std::vector<int4> units;
+  std::vector<int32_t> rowof, base, nch;
+  int nchunks = 0;
   int row = 0;
-  int nchunks_total = 0;
-  while (row < n) {
-    const int G = lanes_for(rp[row + 1] - rp[row]);
-    int end = row;
-    while (end < n && lanes_for(rp[end + 1] - rp[end]) == G) ++end;
-    if (P.segs.nseg >= kMaxSegs) return fail(ISIRA_E_STATE, "too many SpMV segments");
-    SpmvSeg& sg = P.segs.s[P.segs.nseg++];
-    sg.row_begin = row;
-    sg.row_end = end;
-    sg.lanes = G;
-    sg.unit_begin = units;
-    if (G == -1) {
-      for (int r = row; r < end; ++r) {
-        const int cnt = rp[r + 1] - rp[r];
-        const int nch = (cnt + kSplitChunk - 1) / kSplitChunk;
-        const int slot = (int)sbase.size();
-        sbase.push_back(nchunks_total);
-        snch.push_back(nch);
-        srowof.push_back(r);
-        for (int c = 0; c < nch; ++c) {
-          srow.push_back(r);
-          schunk.push_back(c);
-          sslot.push_back(slot);
-        }
-        nchunks_total += nch;
-        units += nch;
-      }
-    } else if (G == kBlock) {
-      units += end - row;
-    } else {
-      const int R = kBlock / G;
-      units += (end - row + R - 1) / R;
+  while (row < n && rp[row + 1] - rp[row] > unnz) {
+    const int len = rp[row + 1] - rp[row];
+    const int nc = (len + unnz - 1) / unnz;
+    rowof.push_back(row);
+    base.push_back(nchunks);
+    nch.push_back(nc);
+    for (int c = 0; c < nc; ++c) {
+      const int j0 = rp[row] + c * unnz;
+      const int j1 = std::min(rp[row + 1], j0 + unnz);
+      units.push_back(make_int4(row, j0, j1, nchunks + c));
     }
-    row = end;
+    nchunks += nc;
+    ++row;
   }
-  P.segs.n_units = units;
-  P.grid = std::max(1, std::min(units, kSpmvGrid));
-  P.n_split_units = (int)srow.size();
-  P.n_split_rows = (int)sbase.size();
+  while (row < n) {
+    const int r0 = row;
+    const int lmax = rp[row + 1] - rp[row];
+    int nnz = 0;
+    while (row < n && row - r0 < urows && nnz + (rp[row + 1] - rp[row]) <= unnz) {
+      nnz += rp[row + 1] - rp[row];
+      ++row;
+    }
+    int G = 1;
+    while (G < 64 && G * 8 < lmax) G <<= 1;
+    units.push_back(make_int4(r0, row, G, -1));
+  }
+  P.n_units = (int)units.size();
+  P.grid = std::max(1, std::min(P.n_units, P.hub ? kHubGrid : kSpmvGrid));
+  P.n_split_units = nchunks;
+  P.n_split_rows = (int)rowof.size();
   int rc;
-  if ((rc = dalloc(&P.split_row, srow.size()))) return rc;
-  if ((rc = dalloc(&P.split_chunk, srow.size()))) return rc;
-  if ((rc = dalloc(&P.split_slot, srow.size()))) return rc;
-  if ((rc = dalloc(&P.split_base, sbase.size()))) return rc;
-  if ((rc = dalloc(&P.split_rowof, sbase.size()))) return rc;
-  if ((rc = dalloc(&P.split_nchunk, sbase.size()))) return rc;
-  if ((rc = dalloc(&P.split_cnt, sbase.size()))) return rc;
-  if ((rc = dalloc(&P.split_part, (size_t)nchunks_total))) return rc;
-  if ((rc = dalloc(&P.split_red, sbase.size()))) return rc;
-  if (!srow.empty()) {
-    CKH(hipMemcpy(P.split_row, srow.data(), srow.size() * 4, hipMemcpyHostToDevice));
-    CKH(hipMemcpy(P.split_chunk, schunk.data(), srow.size() * 4, hipMemcpyHostToDevice));
-    CKH(hipMemcpy(P.split_slot, sslot.data(), srow.size() * 4, hipMemcpyHostToDevice));
-    CKH(hipMemcpy(P.split_base, sbase.data(), sbase.size() * 4, hipMemcpyHostToDevice));
-    CKH(hipMemcpy(P.split_rowof, srowof.data(), sbase.size() * 4, hipMemcpyHostToDevice));
-    CKH(hipMemcpy(P.split_nchunk, snch.data(), sbase.size() * 4, hipMemcpyHostToDevice));
-    CKH(hipMemset(P.split_cnt, 0, sbase.size() * 4));
-    CKH(hipMemset(P.split_red, 0, sbase.size() * 8));
+  if ((rc = dalloc(&P.units, units.size()))) return rc;
+  if ((rc = dalloc(&P.split_rowof, rowof.size()))) return rc;
+  if ((rc = dalloc(&P.split_base, rowof.size()))) return rc;
+  if ((rc = dalloc(&P.split_nchunk, rowof.size()))) return rc;
+  if ((rc = dalloc(&P.split_part, (size_t)nchunks))) return rc;
+  if ((rc = dalloc(&P.split_red, rowof.size()))) return rc;
+  CKH(hipMemcpy(P.units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice));
+  if (!rowof.empty()) {
+    CKH(hipMemcpy(P.split_rowof, rowof.data(), rowof.size() * 4, hipMemcpyHostToDevice));
+    CKH(hipMemcpy(P.split_base, base.data(), base.size() * 4, hipMemcpyHostToDevice));
+    CKH(hipMemcpy(P.split_nchunk, nch.data(), nch.size() * 4, hipMemcpyHostToDevice));
   }
   return ISIRA_OK;
 }
@@ -427,7 +417,7 @@ extern "C" int isira_create(isira_ctx** out, int64_t n, int64_t nnz, const int32
       hipMemsetAsync(ctx->st, 0, sizeof(DevState), s) ||
       hipMemsetAsync(ctx->deg, 0, ctx->ld * 8, s) || hipMemsetAsync(ctx->deg32, 0, ctx->ld * 4, s))
     return cleanup(fail(ISIRA_E_HIP, "memset failed"));
-  if ((rc = build_plan(ctx, rp2))) return cleanup(rc);
+  if ((rc = build_plan(ctx, rp2, col2))) return cleanup(rc);
   // degrees, trim index (Remark 4.1(i)) and delta (Remark 4.1(ii)) on the GPU
   launch_degree(ctx->rp, w_dtype == ISIRA_W_NONE ? nullptr : (w_dtype == ISIRA_W_F32 ? (const void*)ctx->w32 : (const void*)ctx->w64),
                 w_dtype == ISIRA_W_NONE ? ISIRA_W_NONE : (w_dtype == ISIRA_W_F32 ? ISIRA_W_F32 : ISIRA_W_F64),
@@ -450,8 +440,7 @@ extern "C" void isira_destroy(isira_ctx* c) {
   free_workspace(c);
   dfree(c->rp); dfree(c->col); dfree(c->w64); dfree(c->w32); dfree(c->deg); dfree(c->deg32);
   dfree(c->d_perm); dfree(c->d_iperm); dfree(c->d_emap);
-  dfree(c->plan.split_row); dfree(c->plan.split_chunk); dfree(c->plan.split_slot);
-  dfree(c->plan.split_base); dfree(c->plan.split_nchunk); dfree(c->plan.split_cnt);
+  dfree(c->plan.units); dfree(c->plan.split_base); dfree(c->plan.split_nchunk);
   dfree(c->plan.split_rowof);
   dfree(c->plan.split_part); dfree(c->plan.split_red);
   dfree(c->rb.partials); dfree(c->rb.counters); dfree(c->st); dfree(c->hbuf); dfree(c->scal4);
@@ -471,7 +460,7 @@ extern "C" int isira_get_info(const isira_ctx* c, isira_info* info) {
   info->min_degree = c->min_deg;
   info->delta_default = 2.0 * c->max_deg;
   info->norm1 = 2.0 * c->max_deg;
-  info->n_spmv_units = c->plan.segs.n_units;
+  info->n_spmv_units = c->plan.n_units;
   info->n_spmv_blocks = c->plan.grid;
   info->n_split_rows = c->plan.n_split_rows;
   info->has_learned = c->has_learned ? 1 : 0;

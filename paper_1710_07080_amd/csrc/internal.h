@@ -12,10 +12,16 @@ namespace isira {
 
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 constexpr int kStreamGrid = 512;       // max workgroups of grid-stride streaming kernels
-constexpr int kSpmvGrid = 2048;        // max workgroups of the persistent SpMV grid
-constexpr int kSplitChunk = 4096;      // nnz per chunk of a split (very long) row
-constexpr int kBlockRowMin = 1024;     // rows longer than this get a whole workgroup
-constexpr int kMaxSegs = 16;           // SpMV segments (row-length classes)
+constexpr int kSpmvGrid = 2048;       // max workgroups of the persistent SpMV grid
+constexpr int kUnitNnz = 2048;        // nonzeros per SpMV unit (stream unit or long-row chunk)
+constexpr int kUnitRows = 512;        // rows per stream unit at most
+// hub-cached shape for power-law graphs (one 1024-thread workgroup per CU)
+constexpr int kHubThreads = 1024;
+constexpr int kHubUnitNnz = 8192;
+constexpr int kHubUnitRows = 2048;
+constexpr int kHubX64 = 10240;        // FP64 x entries staged in LDS (80 KB)
+constexpr int kHubX32 = 24576;        // FP32 x entries staged in LDS (96 KB)
+constexpr int kHubGrid = 256;
 constexpr int kMaxC = ISIRA_MAX_K;     // deflation columns in the inner solve
 constexpr int kTile = 512;             // rows per tile of the column-dot kernels
 constexpr int kMaxCols = 2 * ISIRA_MAX_BASIS + 2;  // columns of one multi-dot
@@ -29,19 +35,12 @@ constexpr size_t kPartialsElems =
     cmax(cmax((size_t)kMaxCols * kStreamGrid, (size_t)4 * kSpmvGrid),
          (size_t)kSpaiRedValues * kSpaiRedGrid);
 
-// One row-length class of the SpMV: rows [row_begin, row_end) of the relabelled graph.
-// lanes in 1..64: `lanes` lanes per row, 256/lanes rows per unit; 256: one workgroup per
-// row; -1: split rows (units are chunks of kSplitChunk nonzeros).
-struct SpmvSeg {
-  int32_t row_begin, row_end, lanes, unit_begin;
-};
-
-struct SpmvSegs {
-  SpmvSeg s[kMaxSegs];
-  int32_t nseg;
-  int32_t n_units;
-};
-
+// SpMV work units (int4, device), built on the host from the relabelled CSR:
+//   stream unit  {r0, r1, G, -1}: rows [r0, r1) with at most kUnitNnz nonzeros and
+//                kUnitRows rows; their products are staged in LDS and each row is summed
+//                by G lanes;
+//   chunk unit   {row, j0, j1, p}: nonzeros [j0, j1) of a row longer than kUnitNnz, whose
+//                sum goes to split_part[p] and is finished by the second dispatch.
 // Scalars of the inner PCG and of the outer reductions, living in device memory.
 struct DevState {
   double alpha, beta, rho, pq, rr, rr0, rmr, thresh2, rtol2, sump, sumx;
@@ -64,16 +63,14 @@ struct RedBuf {
 
 // SpMV execution plan (device arrays for split rows).
 struct SpmvPlan {
-  SpmvSegs segs;
+  int hub = 0;  // 1: hub-cached shape
+  int4* units = nullptr;
+  int32_t n_units = 0;
   int32_t grid = 0;
   int32_t n_split_units = 0, n_split_rows = 0;
   int32_t* split_rowof = nullptr;  // per split row slot: the row
-  int32_t* split_row = nullptr;    // per split unit: row
-  int32_t* split_chunk = nullptr;  // per split unit: chunk index within the row
-  int32_t* split_slot = nullptr;   // per split unit: slot of its row (0..n_split_rows-1)
   int32_t* split_base = nullptr;   // per split row slot: first chunk partial index
   int32_t* split_nchunk = nullptr; // per split row slot: number of chunks
-  unsigned* split_cnt = nullptr;   // per split row slot: arrival counter
   double* split_part = nullptr;    // per chunk partial neighbour sums
   double* split_red = nullptr;     // per split row slot: reduction contribution
 };

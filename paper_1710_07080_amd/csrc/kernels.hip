@@ -51,16 +51,42 @@ __device__ __forceinline__ bool arrive_last(unsigned* counter) {
   return last;
 }
 
-// Last workgroup: out[v] = sum over workgroups of partials[v * nblk + b] (fixed order).
+// Finishing dispatch: out[v] = sum over workgroups of partials[v * nblk + b], one wave per
+// value (round-robin over the waves of the workgroup); each lane sums b = lane, lane + 64,
+// ... in increasing order, then the wave sums its lanes: a fixed order.
+constexpr int kFin = 1024;  // threads of the finishing dispatches
 __device__ void final_reduce(const double* partials, int nv, int nblk, double* out) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int v = wid; v < nv; v += 4) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int v = wid; v < nv; v += nw) {
+    const double* pv = partials + (size_t)v * nblk;
     double s = 0.0;
-    for (int b = lane; b < nblk; b += 64) s += partials[(size_t)v * nblk + b];
+    int b = lane;
+    for (; b + 7 * 64 < nblk; b += 8 * 64) {
+      double t[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) t[i] = pv[b + i * 64];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s += t[i];
+    }
+    for (; b < nblk; b += 64) s += pv[b];
     s = wave_sum(s);
     if (lane == 0) out[v] = s;
   }
   __syncthreads();
+}
+
+// Sum one double over a workgroup of up to 1024 threads; valid in thread 0.
+__device__ __forceinline__ double block_sum_any(double v) {
+  __shared__ double sh[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < nw; ++w) s += sh[w];
+  return s;
 }
 
 template <int NV>
@@ -214,14 +240,10 @@ void launch_signed_gather(int n, const double* v, const int32_t* perm, const int
 
 struct SplitInfo {
   const int32_t* rowof;  // per slot: the split row
-  const int32_t* row;
-  const int32_t* chunk;
-  const int32_t* slot;
-  const int32_t* base;
-  const int32_t* nchunk;
-  unsigned* cnt;
-  double* part;
-  double* red;
+  const int32_t* base;   // per slot: first chunk partial
+  const int32_t* nchunk; // per slot: number of chunks
+  double* part;          // per chunk partial sums
+  double* red;           // per slot: reduction contribution (scratch)
   int32_t nslots;
 };
 
@@ -234,24 +256,6 @@ __device__ __forceinline__ T edge_val(const void* vals, int j) {
   } else {
     return (T)((const float*)vals)[j];
   }
-}
-
-template <int VM, typename T>
-__device__ __forceinline__ T row_gather(const SpmvArgs<T>& a, int b, int e, int start,
-                                        int stride) {
-  T s = T(0);
-  const T* __restrict__ x = a.x;
-  const int32_t* __restrict__ col = a.col;
-  int j = b + start;
-  // two independent chains for memory-level parallelism
-  T s2 = T(0);
-  for (; j + stride < e; j += 2 * stride) {
-    const int c0 = col[j], c1 = col[j + stride];
-    s += edge_val<VM, T>(a.vals, j) * x[c0];
-    s2 += edge_val<VM, T>(a.vals, j + stride) * x[c1];
-  }
-  if (j < e) s += edge_val<VM, T>(a.vals, j) * x[col[j]];
-  return s + s2;
 }
 
 // Finish row `row` given the neighbour sum; returns this row's reduction contribution.
@@ -283,90 +287,126 @@ __device__ __forceinline__ double finish_row(const SpmvArgs<T>& a, int row, T ns
   return 0.0;
 }
 
-// TAG only separates the symbol of the bandwidth probe (isira_time_spmv) from the solver's
-// launches in profiler summaries; the code is identical.
-template <typename T, int VM, int TAG = 0>
-__global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs<T> a, SpmvSegs segs, SplitInfo sp,
-                                                 double* partials, unsigned* counter) {
+// Sparse product over work units (persistent grid, units taken round-robin).  A stream unit
+// loads all its column indices (and row pointers) in one coalesced batch, then all its x
+// gathers in a second batch, staging the products in LDS; each row is then summed from
+// LDS by G lanes and finished.  A chunk unit of a long row sums its nonzeros into one
+// partial.  Two shapes: 256 threads / 2048-nonzero units (8 workgroups per CU), and, for
+// power-law graphs, 1024 threads / 8192-nonzero units with x of the HUB highest-degree
+// columns (the first HUB labels after relabelling) staged once per workgroup in LDS, so
+// that those gathers never reach L2.  TAG only separates the symbol of the bandwidth probe
+// (isira_time_spmv) from the solver's launches in profiler summaries.
+template <typename T, int VM, int TAG, int NT, int UNNZ, int UROWS, int HUB>
+__global__ __launch_bounds__(NT) void k_spmv(SpmvArgs<T> a, const int4* __restrict__ units,
+                                             int n_units, double* partials,
+                                             double* __restrict__ chunk_part) {
   if (a.check_done && a.st->done) return;
+  constexpr int PT = UNNZ / NT;
+  __shared__ T prod[UNNZ];
+  __shared__ int srp[UROWS + 1];
+  __shared__ T xs[HUB > 0 ? HUB : 1];
   __shared__ double sh_t[kMaxC];
-  __shared__ double sh4[4];
-  __shared__ T shT[4];
+  __shared__ T shT[NT / 64];
   const int tid = threadIdx.x;
   const double* tv = a.tvec ? a.tvec : (a.st ? a.st->t1 : nullptr);
-  for (int j = tid; j < a.c; j += kBlock) sh_t[j] = tv[j];
+  for (int j = tid; j < a.c; j += NT) sh_t[j] = tv[j];
   const T shift_add = (a.sig_over_n != 0.0) ? (T)(a.sig_over_n * a.st->sump) : T(0);
+  const T* __restrict__ x = a.x;
+  const int32_t* __restrict__ col = a.col;
+  if constexpr (HUB > 0) {
+    const int hn = a.n < HUB ? a.n : HUB;
+    for (int i = tid; i < hn; i += NT) xs[i] = x[i];
+  }
   __syncthreads();
   double acc = 0.0;
-  for (int u = blockIdx.x; u < segs.n_units; u += gridDim.x) {
-    int si = 0;
-    while (si + 1 < segs.nseg && u >= segs.s[si + 1].unit_begin) ++si;
-    const SpmvSeg sg = segs.s[si];
-    if (sg.lanes > 0 && sg.lanes <= 64) {
-      const int lanes = sg.lanes;
-      const int R = kBlock / lanes;
-      const int grp = tid / lanes, gl = tid - grp * lanes;
-      const int row = sg.row_begin + (u - sg.unit_begin) * R + grp;
-      T s = T(0);
-      if (row < sg.row_end) s = row_gather<VM, T>(a, a.rp[row], a.rp[row + 1], gl, lanes);
-      s = group_sum(s, lanes);
-      if (gl == 0 && row < sg.row_end) acc += finish_row<VM, T>(a, row, s, sh_t, shift_add);
-    } else if (sg.lanes == kBlock) {
-      const int row = sg.row_begin + (u - sg.unit_begin);
-      T s = row_gather<VM, T>(a, a.rp[row], a.rp[row + 1], tid, kBlock);
-      s = wave_sum(s);
-      __syncthreads();
-      if ((tid & 63) == 0) shT[tid >> 6] = s;
-      __syncthreads();
-      if (tid == 0) acc += finish_row<VM, T>(a, row, (shT[0] + shT[1]) + (shT[2] + shT[3]), sh_t,
-                                             shift_add);
+  for (int u = blockIdx.x; u < n_units; u += gridDim.x) {
+    const int4 un = units[u];
+    int j0, j1;
+    if (un.w < 0) {
+      j0 = a.rp[un.x];
+      j1 = a.rp[un.y];
     } else {
-      // split row: one chunk of kSplitChunk nonzeros
-      const int su = u - sg.unit_begin;
-      const int row = sp.row[su], ch = sp.chunk[su], slot = sp.slot[su];
-      const int b = a.rp[row] + ch * kSplitChunk;
-      int e = b + kSplitChunk;
-      if (e > a.rp[row + 1]) e = a.rp[row + 1];
-      T s = row_gather<VM, T>(a, b, e, tid, kBlock);
-      s = wave_sum(s);
+      j0 = un.y;
+      j1 = un.z;
+    }
+    int ci[PT];
+    T v[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int e = j0 + tid + k * NT;
+      ci[k] = (e < j1) ? col[e] : -1;
+      v[k] = (e < j1) ? edge_val<VM, T>(a.vals, e) : T(0);
+    }
+    // x gathers; the hub shape reads the staged labels from LDS
+    auto gx = [&](int c) -> T {
+      if constexpr (HUB > 0) {
+        return c < HUB ? xs[c] : x[c];
+      } else {
+        return x[c];
+      }
+    };
+    if (un.w < 0) {
+      const int nr = un.y - un.x;
+      for (int t = tid; t <= nr; t += NT) srp[t] = a.rp[un.x + t] - j0;
+#pragma unroll
+      for (int k = 0; k < PT; ++k)
+        if (ci[k] >= 0) prod[tid + k * NT] = v[k] * gx(ci[k]);
       __syncthreads();
+      const int G = un.z;
+      const int R = NT / G, grp = tid / G, gl = tid - grp * G;
+      for (int rr = grp; rr < nr; rr += R) {
+        T s = T(0);
+        const int e = srp[rr + 1];
+        for (int j = srp[rr] + gl; j < e; j += G) s += prod[j];
+        s = group_sum(s, G);
+        if (gl == 0) acc += finish_row<VM, T>(a, un.x + rr, s, sh_t, shift_add);
+      }
+      __syncthreads();
+    } else {
+      T s = T(0);
+#pragma unroll
+      for (int k = 0; k < PT; ++k)
+        if (ci[k] >= 0) s += v[k] * gx(ci[k]);
+      s = wave_sum(s);
       if ((tid & 63) == 0) shT[tid >> 6] = s;
       __syncthreads();
-      if (tid == 0) sp.part[sp.base[slot] + ch] = (double)((shT[0] + shT[1]) + (shT[2] + shT[3]));
-      (void)row;
+      if (tid == 0) {
+        T t = T(0);
+        for (int w = 0; w < NT / 64; ++w) t += shT[w];
+        chunk_part[un.w] = (double)t;
+      }
+      __syncthreads();
     }
   }
   if (a.red == 0) return;
-  const double bs = block_sum1(acc, sh4);
+  const double bs = block_sum_any(acc);
   if (tid == 0) partials[blockIdx.x] = bs;
 }
 
-// Second dispatch of the sparse product: finishes the split rows from their chunk sums
-// (fixed chunk order) and reduces the per-workgroup partials plus the split rows'
-// contributions (fixed order).  One workgroup.
+// Second dispatch of the sparse product (one workgroup): finishes the split rows from
+// their chunk sums (fixed chunk order) and reduces the per-workgroup partials plus the
+// split rows' contributions in a fixed order.
 template <typename T, int VM>
-__global__ __launch_bounds__(kBlock) void k_spmv_fin(SpmvArgs<T> a, SplitInfo sp, int nblk,
-                                                     const double* partials) {
+__global__ __launch_bounds__(kFin) void k_spmv_fin(SpmvArgs<T> a, SplitInfo sp, int nblk,
+                                                   const double* partials) {
   if (a.check_done && a.st->done) return;
   __shared__ double sh_t[kMaxC];
-  __shared__ double sh_red[1];
   const int tid = threadIdx.x;
   const double* tv = a.tvec ? a.tvec : (a.st ? a.st->t1 : nullptr);
-  for (int j = tid; j < a.c; j += kBlock) sh_t[j] = tv[j];
+  for (int j = tid; j < a.c; j += blockDim.x) sh_t[j] = tv[j];
   const T shift_add = (a.sig_over_n != 0.0) ? (T)(a.sig_over_n * a.st->sump) : T(0);
   __syncthreads();
-  for (int slot = tid; slot < sp.nslots; slot += kBlock) {
+  double acc = 0.0;
+  for (int slot = tid; slot < sp.nslots; slot += blockDim.x) {
     double tot = 0.0;
     const int nb = sp.nchunk[slot], pb = sp.base[slot];
     for (int k = 0; k < nb; ++k) tot += sp.part[pb + k];
-    sp.red[slot] = finish_row<VM, T>(a, sp.rowof[slot], (T)tot, sh_t, shift_add);
+    acc += finish_row<VM, T>(a, sp.rowof[slot], (T)tot, sh_t, shift_add);
   }
   if (a.red == 0) return;
-  __syncthreads();
-  final_reduce(partials, 1, nblk, sh_red);
+  for (int b = tid; b < nblk; b += blockDim.x) acc += partials[b];
+  const double tot = block_sum_any(acc);
   if (tid == 0) {
-    double tot = sh_red[0];
-    for (int k = 0; k < sp.nslots; ++k) tot += sp.red[k];
     DevState* st = a.st;
     if (a.red == 1) {
       st->pq = tot;
@@ -385,8 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_fin(SpmvArgs<T> a, SplitInfo sp
 }
 
 static SplitInfo split_info(const SpmvPlan& plan) {
-  return SplitInfo{plan.split_rowof, plan.split_row, plan.split_chunk, plan.split_slot,
-                   plan.split_base, plan.split_nchunk, plan.split_cnt, plan.split_part,
+  return SplitInfo{plan.split_rowof, plan.split_base, plan.split_nchunk, plan.split_part,
                    plan.split_red, plan.n_split_rows};
 }
 
@@ -394,9 +433,17 @@ template <typename T, int VM, int TAG>
 static void spmv_dispatch(const SpmvPlan& plan, const SpmvArgs<T>& a, double* partials,
                           hipStream_t s) {
   const SplitInfo sp = split_info(plan);
-  k_spmv<T, VM, TAG><<<plan.grid, kBlock, 0, s>>>(a, plan.segs, sp, partials, nullptr);
+  if (plan.hub) {
+    constexpr int HUB = sizeof(T) == 8 ? kHubX64 : kHubX32;
+    k_spmv<T, VM, TAG, kHubThreads, kHubUnitNnz, kHubUnitRows, HUB>
+        <<<plan.grid, kHubThreads, 0, s>>>(a, plan.units, plan.n_units, partials,
+                                           plan.split_part);
+  } else {
+    k_spmv<T, VM, TAG, kBlock, kUnitNnz, kUnitRows, 0>
+        <<<plan.grid, kBlock, 0, s>>>(a, plan.units, plan.n_units, partials, plan.split_part);
+  }
   if (plan.n_split_rows > 0 || a.red != 0)
-    k_spmv_fin<T, VM><<<1, kBlock, 0, s>>>(a, sp, plan.grid, partials);
+    k_spmv_fin<T, VM><<<1, kFin, 0, s>>>(a, sp, plan.grid, partials);
 }
 
 template <typename T>
@@ -410,6 +457,7 @@ void launch_spmv(const SpmvPlan& plan, int valmode, const SpmvArgs<T>& a, RedBuf
   }
   HIP_LAUNCH_CHECK();
 }
+
 template <typename T>
 void launch_spmv_probe(const SpmvPlan& plan, int valmode, const SpmvArgs<T>& a, double* partials,
                        hipStream_t s) {
@@ -467,23 +515,25 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update1(int n, T* __restrict__ x
 
 // Reduces the partials of k_pcg_update1 (one workgroup), forms g = G^-1 t2 and
 // rho = r^T M^-1 r - delta t2^T g, tests convergence and sets beta.
-__global__ __launch_bounds__(kBlock) void k_pcg_fin1(int c, int nblk, const double* partials,
+__global__ __launch_bounds__(kFin) void k_pcg_fin1(int c, int nblk, const double* partials,
                                                      const double* Ginv, double delta, int init,
                                                      DevState* st) {
   if (st->done) return;
   __shared__ double red[2 + kMaxC];
+  __shared__ double gsh[kMaxC];
   final_reduce(partials, 2 + c, nblk, red);
   // g = Ginv t2 (c x c, column-major)
-  for (int j = threadIdx.x; j < c; j += kBlock) {
+  for (int j = threadIdx.x; j < c; j += blockDim.x) {
     double gj = 0.0;
     for (int i = 0; i < c; ++i) gj += Ginv[j + i * c] * red[2 + i];
+    gsh[j] = gj;
     st->g[j] = gj;
     st->t2[j] = red[2 + j];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     double tg = 0.0;
-    for (int j = 0; j < c; ++j) tg += red[2 + j] * st->g[j];
+    for (int j = 0; j < c; ++j) tg += red[2 + j] * gsh[j];
     const double rr = red[0];
     const double rho_new = red[1] - delta * tg;
     st->rr = rr;
@@ -561,12 +611,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update2(int n, const T* __restri
 }
 
 // Reduces the partials of the p-update (one workgroup): t1 = V-hat^T p, sum(p).
-__global__ __launch_bounds__(kBlock) void k_pcg_fin2(int c, int nblk, const double* partials,
+__global__ __launch_bounds__(kFin) void k_pcg_fin2(int c, int nblk, const double* partials,
                                                      DevState* st) {
   if (st->done) return;
   __shared__ double red[1 + kMaxC];
   final_reduce(partials, 1 + c, nblk, red);
-  for (int j = threadIdx.x; j < c; j += kBlock) st->t1[j] = red[1 + j];
+  for (int j = threadIdx.x; j < c; j += blockDim.x) st->t1[j] = red[1 + j];
   if (threadIdx.x == 0) st->sump = red[0];
 }
 
@@ -606,7 +656,7 @@ void launch_pcg_update1(int n, T* x, T* r, const T* p, const T* q, const T* dinv
                                                    init, st, rb.partials, cnt);
       break;
   }
-  k_pcg_fin1<<<1, kBlock, 0, s>>>(c, grid, rb.partials, Ginv, delta, init, st);
+  k_pcg_fin1<<<1, kFin, 0, s>>>(c, grid, rb.partials, Ginv, delta, init, st);
   HIP_LAUNCH_CHECK();
 }
 
@@ -637,7 +687,7 @@ void launch_pcg_update2(int n, const T* r, T* p, const T* dinv, const T* V, int6
                                                    rb.partials, cnt);
       break;
   }
-  k_pcg_fin2<<<1, kBlock, 0, s>>>(c, grid, rb.partials, st);
+  k_pcg_fin2<<<1, kFin, 0, s>>>(c, grid, rb.partials, st);
   HIP_LAUNCH_CHECK();
 }
 template void launch_pcg_update1<double>(int, double*, double*, const double*, const double*,
@@ -679,7 +729,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update1_plain(int n, T* __restri
   write_partials<1>(acc, 1, partials);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_fin1_plain(int nblk, const double* partials,
+__global__ __launch_bounds__(kFin) void k_pcg_fin1_plain(int nblk, const double* partials,
                                                            int init, DevState* st) {
   if (st->done) return;
   __shared__ double red[1];
@@ -778,7 +828,7 @@ void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, int ini
                               RedBuf rb, hipStream_t s) {
   k_pcg_update1_plain<T><<<stream_grid(n), kBlock, 0, s>>>(n, x, r, p, q, init, st,
                                                           rb.partials, rb.counters + 4);
-  k_pcg_fin1_plain<<<1, kBlock, 0, s>>>(stream_grid(n), rb.partials, init, st);
+  k_pcg_fin1_plain<<<1, kFin, 0, s>>>(stream_grid(n), rb.partials, init, st);
   HIP_LAUNCH_CHECK();
 }
 template <typename T>
@@ -809,7 +859,7 @@ void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv
                                                            st, rb.partials, cnt);
       break;
   }
-  k_pcg_fin2<<<1, kBlock, 0, s>>>(c, grid, rb.partials, st);
+  k_pcg_fin2<<<1, kFin, 0, s>>>(c, grid, rb.partials, st);
   HIP_LAUNCH_CHECK();
 }
 template void launch_pcg_update1_plain<double>(int, double*, double*, const double*,
@@ -857,7 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_sum(int n, const T* __restrict__ x,
     acc[0] += (double)x[l];
   write_partials<1>(acc, 1, partials);
 }
-__global__ __launch_bounds__(kBlock) void k_sum_fin(int nblk, const double* partials,
+__global__ __launch_bounds__(kFin) void k_sum_fin(int nblk, const double* partials,
                                                     DevState* st) {
   __shared__ double red[1];
   final_reduce(partials, 1, nblk, red);
@@ -874,7 +924,7 @@ template <typename T>
 void launch_enlarge(int n, const T* x, double* z, DevState* st, RedBuf rb, hipStream_t s) {
   const int grid = stream_grid(n);
   k_sum<T><<<grid, kBlock, 0, s>>>(n, x, st, rb.partials, rb.counters + 6);
-  k_sum_fin<<<1, kBlock, 0, s>>>(grid, rb.partials, st);
+  k_sum_fin<<<1, kFin, 0, s>>>(grid, rb.partials, st);
   k_enlarge<T><<<grid, kBlock, 0, s>>>(n, x, z, st);
   HIP_LAUNCH_CHECK();
 }
@@ -912,7 +962,34 @@ __global__ __launch_bounds__(kBlock) void k_multidot(int n, const T* __restrict_
       zt[i] = zz;
     }
     __syncthreads();
-    for (int j = wid; j < nv; j += 4) {
+    // columns j = wid + 4 i; four of them in flight per wave
+    int j = wid;
+    for (; j + 12 < ncol; j += 16) {
+      const T* c0 = (j < na) ? A + (int64_t)j * lda + base : B + (int64_t)(j - na) * ldb + base;
+      const int j1 = j + 4, j2 = j + 8, j3 = j + 12;
+      const T* c1 = (j1 < na) ? A + (int64_t)j1 * lda + base : B + (int64_t)(j1 - na) * ldb + base;
+      const T* c2 = (j2 < na) ? A + (int64_t)j2 * lda + base : B + (int64_t)(j2 - na) * ldb + base;
+      const T* c3 = (j3 < na) ? A + (int64_t)j3 * lda + base : B + (int64_t)(j3 - na) * ldb + base;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int i = lane; i < len; i += 64) {
+        const double zz = (double)zt[i];
+        s0 += (double)c0[i] * zz;
+        s1 += (double)c1[i] * zz;
+        s2 += (double)c2[i] * zz;
+        s3 += (double)c3[i] * zz;
+      }
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      s3 = wave_sum(s3);
+      if (lane == 0) {
+        acc[j] += s0;
+        acc[j1] += s1;
+        acc[j2] += s2;
+        acc[j3] += s3;
+      }
+    }
+    for (; j < nv; j += 4) {
       double s = 0.0;
       if (j < ncol) {
         const T* colp = (j < na) ? A + (int64_t)j * lda + base : B + (int64_t)(j - na) * ldb + base;

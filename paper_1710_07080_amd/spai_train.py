@@ -143,6 +143,41 @@ def mean_loss(sets: List[PairSet], params, batch: int = 32) -> float:
     return tot / max(1, cnt)
 
 
+def evaluate(g, params, k: int = 20, sigma: float = 0.0, tol: float = 1e-8, seed: int = 1,
+             inner_rtol: float = 1e-4, repeats: int = 1) -> dict:
+    """Time to k pairs on one graph: plain FP64 (Jacobi), FP32 inner (Jacobi) and FP32 inner
+    with the learned preconditioner; every variant must reach the residual tolerance."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+
+    ctx = I.Context.from_graph(g)
+    u0 = gg.start_block(g.n, 4, seed)
+    out = {"n": g.n, "nnz": g.nnz}
+    ref = None
+    t = time.perf_counter()
+    ctx.spai_install(params, sigma=sigma)
+    torch.cuda.synchronize()
+    out["install_s"] = time.perf_counter() - t
+    for name, prec, pc in [("fp64_jacobi", I.FP64, I.PC_JACOBI), ("fp32_jacobi", I.FP32, I.PC_JACOBI),
+                           ("fp32_learned", I.FP32, I.PC_LEARNED), ("fp64_learned", I.FP64, I.PC_LEARNED)]:
+        best = None
+        for _ in range(repeats):
+            ev, X, res, st = ctx.solve(k, sigma, tol, u0=u0, inner_prec=prec, precond=pc,
+                                       inner_rtol=inner_rtol)
+            best = st if best is None or st["ms_total"] < best["ms_total"] else best
+        ev = np.sort(ev)
+        row = {"s": best["ms_total"] / 1e3, "converged": best["n_converged"], "outer": best["outer_total"],
+               "inner": best["inner_total"], "max_resid": float(np.max(res)) if len(res) else None}
+        if ref is None:
+            ref = ev
+        elif len(ev) == len(ref):
+            row["max_rel_eval_diff_vs_fp64_jacobi"] = float(np.max(np.abs(ev - ref) / ref))
+        out[name] = row
+    return out
+
+
 def save(params, path: str = DEFAULT_WEIGHTS):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     np.save(path, params.detach().cpu().numpy().astype(np.float32), allow_pickle=False)
@@ -158,8 +193,10 @@ def load(path: str = DEFAULT_WEIGHTS):
 
 
 def main(argv: Optional[list] = None):
-    """Train on seeded R-MAT graphs (scale 16 + seed mod 3, edge factor 8) and save."""
+    """Train on seeded R-MAT graphs (scale 16 + seed mod 3, edge factor 8), save the weights,
+    and optionally evaluate them on held-out R-MAT graphs."""
     import argparse
+    import json
 
     import graphgen as gg
 
@@ -171,6 +208,7 @@ def main(argv: Optional[list] = None):
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--k", type=int, default=20)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--eval", default="", help="comma list of held-out graphs: rmatS[:EF[:seed]]")
     args = ap.parse_args(argv)
     I.load()
     sets = []
@@ -188,6 +226,15 @@ def main(argv: Optional[list] = None):
     print(f"[spai] trained {args.steps} steps in {lg.seconds:.1f} s; loss {l0:.4f} -> {l1:.4f}", flush=True)
     save(p, args.out)
     print(f"[spai] saved {args.out}", flush=True)
+    for spec in [x for x in args.eval.split(",") if x]:
+        parts = spec[4:].split(":")
+        scale = int(parts[0])
+        ef = int(parts[1]) if len(parts) > 1 else 8
+        seed = int(parts[2]) if len(parts) > 2 else 4000
+        g = gg.rmat(scale, ef, seed=seed)
+        res = evaluate(g, p, k=args.k)
+        res["graph"] = spec
+        print("[spai-eval] " + json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

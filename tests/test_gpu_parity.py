@@ -53,6 +53,9 @@ GRAPHS = {
     "hubs": _hub_graph,
     "star": lambda: gg.star_graph(5000),
     "path": lambda: gg.path_graph(1001),
+    # n > 4 * 10240 with hub-concentrated gathers: the hub-cached SpMV shape
+    "rmat17": lambda: gg.rmat(17, 8, seed=13),
+    "chunglu": lambda: gg.chung_lu(120000, 2.1, 12.0, seed=14),
 }
 
 
@@ -76,7 +79,7 @@ def test_laplacian_apply_fp64(P, name):
     assert inf["delta_default"] == pytest.approx(O.deflation_shift(O.degrees(g)), rel=4e-16 * g.counts().max())
 
 
-@pytest.mark.parametrize("name", ["grid3d_w", "rmat14", "hubs"])
+@pytest.mark.parametrize("name", ["grid3d_w", "rmat14", "hubs", "rmat17", "chunglu"])
 def test_laplacian_apply_fp32(P, name):
     g = GRAPHS[name]()
     ctx = P.Context.from_graph(g)
@@ -96,7 +99,8 @@ def test_laplacian_apply_fp32(P, name):
     dict(g="rmat14", c=5, sigma=0.0, trim=None),
     dict(g="rmat14", c=2, sigma="half", trim=17),
     dict(g="hubs", c=9, sigma="half", trim=None),
-], ids=["grid64", "grid3d_c3", "rmat14_c5", "rmat14_shift_trim17", "hubs_c9_shift"])
+    dict(g="rmat17", c=6, sigma=0.0, trim=None),
+], ids=["grid64", "grid3d_c3", "rmat14_c5", "rmat14_shift_trim17", "hubs_c9_shift", "rmat17_c6"])
 def test_inner_solve_fp64(P, case):
     g = GRAPHS[case["g"]]()
     ctx = P.Context.from_graph(g)
