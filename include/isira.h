@@ -65,7 +65,7 @@ typedef struct {
   int32_t m;            /* maximal search-space dimension (Algorithm 3.2); default 2*q */
   int32_t q;            /* restart size; default k + 10 */
   int32_t k0;           /* start-block columns; default 4 */
-  double inner_rtol;    /* inner PCG stop: ||r_hat - K_hat z|| <= inner_rtol ||r_hat||; default 1e-4 */
+  double inner_rtol;    /* inner PCG stop: ||r_hat - K_hat z|| <= inner_rtol ||r_hat||; default 1e-1 */
   int32_t max_inner;    /* PCG iteration cap per inner solve; default 1000 */
   int32_t max_outer;    /* cap on outer iterations of the whole solve; default 20000 */
   int32_t inner_prec;   /* ISIRA_FP64 (default) or ISIRA_FP32 */

@@ -103,7 +103,9 @@ struct isira_ctx {
   DevState* st = nullptr;
   DevState* st_host = nullptr;  // pinned
   double* hbuf = nullptr;       // device kMaxCols
-  double* hbuf_host = nullptr;  // pinned kMaxCols
+  double* hbuf_host = nullptr;  // pinned 2 * kMaxCols (second half: CGS2 first-pass values)
+  unsigned char* up_host = nullptr;  // pinned upload ring for small host-to-device copies
+  size_t up_off = 0;                 // next free byte; reset whenever the stream is idle
   double* scal4 = nullptr;      // device 4
   int trim_default = 0;         // internal index
   int64_t trim_label = 0;
@@ -157,7 +159,7 @@ static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp,
     for (int c = 0; c < nc; ++c) {
       const int j0 = rp[row] + c * unnz;
       const int j1 = std::min(rp[row + 1], j0 + unnz);
-      units.push_back(make_int4(row, j0, j1, nchunks + c));
+      units.push_back(make_int4(row, j0, j1, -(nchunks + c + 1)));
     }
     nchunks += nc;
     ++row;
@@ -172,7 +174,7 @@ static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp,
     }
     int G = 1;
     while (G < 64 && G * 8 < lmax) G <<= 1;
-    units.push_back(make_int4(r0, row, G, -1));
+    units.push_back(make_int4(r0, rp[r0], rp[row], ((row - r0) << 8) | G));
   }
   P.n_units = (int)units.size();
   P.grid = std::max(1, std::min(P.n_units, P.hub ? kHubGrid : kSpmvGrid));
@@ -230,7 +232,7 @@ extern "C" int isira_default_options(isira_options* o) {
   o->m = 0;
   o->q = 0;
   o->k0 = 4;
-  o->inner_rtol = 1e-4;
+  o->inner_rtol = 1e-1;
   o->max_inner = 1000;
   o->max_outer = 20000;
   o->inner_prec = ISIRA_FP64;
@@ -400,7 +402,8 @@ extern "C" int isira_create(isira_ctx** out, int64_t n, int64_t nnz, const int32
   if ((rc = dalloc(&ctx->Sdev, (size_t)ISIRA_MAX_BASIS * ISIRA_MAX_BASIS))) return cleanup(rc);
   if ((rc = dalloc(&ctx->Ginv, (size_t)kMaxC * kMaxC))) return cleanup(rc);
   if (hipHostMalloc((void**)&ctx->st_host, sizeof(DevState)) != hipSuccess ||
-      hipHostMalloc((void**)&ctx->hbuf_host, kMaxCols * sizeof(double)) != hipSuccess)
+      hipHostMalloc((void**)&ctx->hbuf_host, 2 * kMaxCols * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->up_host, kUploadRing) != hipSuccess)
     return cleanup(fail(ISIRA_E_HIP, "hipHostMalloc failed"));
   hipStream_t s = ctx->stream;
   auto up = [&](void* dst, const void* src, size_t bytes) {
@@ -448,6 +451,7 @@ extern "C" void isira_destroy(isira_ctx* c) {
   spai::free_work(c->spw);
   if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->hbuf_host) (void)hipHostFree(c->hbuf_host);
+  if (c->up_host) (void)hipHostFree(c->up_host);
   delete c;
 }
 
@@ -497,15 +501,47 @@ void spmv64(isira_ctx* c, const double* x, double* y, const double* V, int nv,
   launch_spmv<double>(c->plan, valmode64(c), a, c->rb, c->stream);
 }
 
-int sync_state(isira_ctx* c) {
-  CKH(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+// Waits for the stream; afterwards the upload ring is free again.
+int stream_sync(isira_ctx* c) {
   CKH(hipStreamSynchronize(c->stream));
+  c->up_off = 0;
   return ISIRA_OK;
 }
 
-int read_h(isira_ctx* c, int count) {
-  CKH(hipMemcpyAsync(c->hbuf_host, c->hbuf, count * sizeof(double), hipMemcpyDeviceToHost,
+#define SYNC_OR_RETURN(c)           \
+  do {                              \
+    const int rc_ = stream_sync(c); \
+    if (rc_) return rc_;            \
+  } while (0)
+
+int sync_state(isira_ctx* c) {
+  CKH(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+  return stream_sync(c);
+}
+
+// Queues a copy of hbuf[0:count) into hbuf_host[off:off+count) (read after a sync).
+int read_h(isira_ctx* c, int count, int off = 0) {
+  CKH(hipMemcpyAsync(c->hbuf_host + off, c->hbuf, count * sizeof(double), hipMemcpyDeviceToHost,
                      c->stream));
+  return ISIRA_OK;
+}
+
+// Host-to-device copy of a small host array through the pinned ring, so that the copy is
+// queued on the stream like a kernel instead of stalling the host; the ring is reused only
+// after the stream has drained.
+int upload(isira_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (bytes > kUploadRing) {
+    CKH(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    return stream_sync(c);
+  }
+  if (c->up_off + bytes > kUploadRing) {
+    int rc = stream_sync(c);
+    if (rc) return rc;
+  }
+  unsigned char* h = c->up_host + c->up_off;
+  std::memcpy(h, src, bytes);
+  CKH(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, c->stream));
+  c->up_off += (bytes + 255) & ~(size_t)255;
   return ISIRA_OK;
 }
 
@@ -551,76 +587,97 @@ struct InnerCfg {
 };
 
 // Solve the trimmed shifted deflated system (2.15) for right-hand side r64 (internal order,
-// FP64, mean `mean` removed here) with c deflation columns already in Vin/Y and Ginv.
-// The solution (still trimmed, inner precision) is left in x32/x64.
+// FP64) with c deflation columns already in Vin/Y and Ginv.  The mean removed from r64 is
+// `mean`, or (when mean_sum is given) the device value *mean_sum / n.  inner_pcg_start only
+// queues the set-up and the first batch of iterations; inner_pcg_finish waits and queues
+// further batches until the device-side test has stopped the iteration.  The solution
+// (still trimmed, inner precision) is left in x32/x64.
 template <typename T>
-int inner_pcg(isira_ctx* c, const InnerCfg& cfg, const double* r64, double mean, int nc,
-              int* iters, int* status, double* relres) {
-  const int n = (int)c->n;
+struct PcgBufs {
   T *x, *r, *p, *q, *dinv, *y;
   const T *V, *Y;
+};
+template <typename T>
+PcgBufs<T> pcg_bufs(isira_ctx* c) {
   if constexpr (sizeof(T) == 8) {
-    x = c->x64; r = c->ri64; p = c->p64; q = c->q64; dinv = c->dinv64; y = c->y64;
-    V = c->Vin64; Y = c->Y64;
+    return PcgBufs<T>{c->x64, c->ri64, c->p64, c->q64, c->dinv64, c->y64, c->Vin64, c->Y64};
   } else {
-    x = c->x32; r = c->ri32; p = c->p32; q = c->q32; dinv = c->dinv32; y = c->y32;
-    V = c->Vin32; Y = c->Y32;
+    return PcgBufs<T>{c->x32, c->ri32, c->p32, c->q32, c->dinv32, c->y32, c->Vin32, c->Y32};
   }
+}
+
+template <typename T>
+void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
+  const int n = (int)c->n;
+  const PcgBufs<T> b = pcg_bufs<T>(c);
   hipStream_t s = c->stream;
-  DevState init{};
-  init.rtol2 = cfg.rtol * cfg.rtol;
-  init.maxit = cfg.maxit;
-  CKH(hipMemcpyAsync(c->st, &init, sizeof(DevState), hipMemcpyHostToDevice, s));
-  launch_rhs_prep<T>(n, r64, mean, cfg.trim, r, x, s);
   const bool learned = cfg.precond == ISIRA_PC_LEARNED;
   const int vm = sizeof(T) == 8 ? valmode64(c) : valmode32(c);
   SpmvArgs<T> a{};
   a.rp = c->rp;
   a.col = c->col;
   a.vals = sizeof(T) == 8 ? (const void*)c->w64 : (const void*)c->w32;
-  a.x = p;
-  a.y = q;
+  a.x = b.p;
+  a.y = b.q;
   a.diag = sizeof(T) == 8 ? (const T*)c->deg : (const T*)c->deg32;
   a.n = n;
   a.trim = cfg.trim;
   a.sigma = cfg.sigma;
   a.sig_over_n = cfg.sigma / (double)n;
-  a.V = V;
+  // the deflation term delta V-hat (V-hat^T p) of the operator is applied by the residual
+  // update (which reads V-hat anyway) and folded into p^T q by the product's reduction
+  a.V = nullptr;
   a.ldv = c->ld;
-  a.c = nc;
+  a.c = 0;
   a.tvec = nullptr;
   a.delta = cfg.delta;
   a.red = 1;
   a.st = c->st;
   a.check_done = 1;
-  // learned variant: y = M r with the dots V-hat^T y and r^T y, then eq. (3.5)
-  auto precond_apply = [&](int initflag) {
-    spai::apply<T>(c->spw, c->plan, c->rp, c->col, r, y, n, cfg.trim, V, c->ld, nc, c->st,
-                   c->rb, s);
-    launch_spai_finish_rho(nc, c->Ginv, cfg.delta, initflag, c->st, s);
-    launch_pcg_update2_learned<T>(n, y, p, Y, c->ld, nc, V, cfg.delta, initflag, c->st, c->rb, s);
-  };
-  if (learned) {
-    launch_pcg_update1_plain<T>(n, x, r, p, q, 1, c->st, c->rb, s);
-    precond_apply(1);
-  } else {
-    launch_pcg_update1<T>(n, x, r, p, q, dinv, V, c->ld, nc, c->Ginv, cfg.delta, 1, c->st, c->rb, s);
-    launch_pcg_update2<T>(n, r, p, dinv, V, c->ld, nc, cfg.delta, 1, c->st, c->rb, s);
+  a.fold_c = nc;
+  // one iteration: [product] then the residual update and the preconditioned direction;
+  // the first call (init) has no product and starts from x = 0, r = rhs
+  for (int it = 0; it < iters; ++it) {
+    const int first = init && it == 0;
+    if (!first) launch_spmv<T>(c->plan, vm, a, c->rb, s);
+    if (learned) {
+      // y = M r with the dots V-hat^T y and r^T y, then eq. (3.5)
+      launch_pcg_update1_plain<T>(n, b.x, b.r, b.p, b.q, b.V, c->ld, nc, cfg.delta, first,
+                                  c->st, c->rb, s);
+      spai::apply<T>(c->spw, c->plan, c->rp, c->col, b.r, b.y, n, cfg.trim, b.V, c->ld, nc,
+                     c->st, c->rb, s);
+      launch_spai_finish_rho(nc, c->Ginv, cfg.delta, first, c->st, s);
+      launch_pcg_update2_learned<T>(n, b.y, b.p, b.Y, c->ld, nc, b.V, cfg.delta, first, c->st,
+                                    c->rb, s);
+    } else {
+      launch_pcg_update1<T>(n, b.x, b.r, b.p, b.q, b.dinv, b.V, c->ld, nc, c->Ginv, cfg.delta,
+                            first, c->st, c->rb, s);
+      launch_pcg_update2<T>(n, b.r, b.p, b.dinv, b.V, c->ld, nc, cfg.delta, first, c->st,
+                            c->rb, s);
+    }
   }
+}
+
+template <typename T>
+void inner_pcg_start(isira_ctx* c, const InnerCfg& cfg, const double* r64, double mean,
+                     const double* mean_sum, int nc) {
+  const int n = (int)c->n;
+  const PcgBufs<T> b = pcg_bufs<T>(c);
+  launch_pcg_reset(c->st, cfg.rtol * cfg.rtol, cfg.maxit, c->stream);
+  launch_rhs_prep<T>(n, r64, mean, mean_sum, 1.0 / (double)n, cfg.trim, b.r, b.x, c->stream);
+  pcg_batch<T>(c, cfg, nc, 1 + cfg.check_every, 1);
+}
+
+// `synced`: st_host already holds the state after the queued batch (no wait needed first).
+template <typename T>
+int inner_pcg_finish(isira_ctx* c, const InnerCfg& cfg, int nc, bool synced, int* iters,
+                     int* status, double* relres) {
   int rc;
   for (;;) {
-    for (int b = 0; b < cfg.check_every; ++b) {
-      launch_spmv<T>(c->plan, vm, a, c->rb, s);
-      if (learned) {
-        launch_pcg_update1_plain<T>(n, x, r, p, q, 0, c->st, c->rb, s);
-        precond_apply(0);
-      } else {
-        launch_pcg_update1<T>(n, x, r, p, q, dinv, V, c->ld, nc, c->Ginv, cfg.delta, 0, c->st, c->rb, s);
-        launch_pcg_update2<T>(n, r, p, dinv, V, c->ld, nc, cfg.delta, 0, c->st, c->rb, s);
-      }
-    }
-    if ((rc = sync_state(c))) return rc;
+    if (!synced && (rc = sync_state(c))) return rc;
+    synced = false;
     if (c->st_host->done) break;
+    pcg_batch<T>(c, cfg, nc, cfg.check_every, 0);
   }
   *iters = c->st_host->it;
   *status = c->st_host->status;
@@ -628,26 +685,42 @@ int inner_pcg(isira_ctx* c, const InnerCfg& cfg, const double* r64, double mean,
   return ISIRA_OK;
 }
 
-// Classical Gram-Schmidt twice against [U(:,0:nu) Vout(:,0:nv) 1/sqrt(n)] in place on z;
-// norms[0] = ||z|| before, norms[1] = after.
-int cgs2(isira_ctx* c, const double* U, int nu, const double* V, int nv, double* z,
-         double* norms) {
+template <typename T>
+int inner_pcg(isira_ctx* c, const InnerCfg& cfg, const double* r64, double mean, int nc,
+              int* iters, int* status, double* relres) {
+  inner_pcg_start<T>(c, cfg, r64, mean, nullptr, nc);
+  return inner_pcg_finish<T>(c, cfg, nc, false, iters, status, relres);
+}
+
+// Classical Gram-Schmidt twice against [U(:,0:nu) Vout(:,0:nv) 1/sqrt(n)] in place on z.
+// cgs2_queue only queues the work: ||z||^2 before the second pass goes to
+// hbuf_host[kMaxCols + nc + 1] and after it to st->red[2], both valid after the next sync.
+int cgs2_queue(isira_ctx* c, const double* U, int nu, const double* V, int nv, double* z) {
   const int n = (int)c->n;
   hipStream_t s = c->stream;
   const int nc = nu + nv;
   launch_multidot<double>(n, U, c->ld, nu, V, c->ld, nv, z, nullptr, 1, 1, c->hbuf, c->rb, s);
   int rc;
-  if ((rc = read_h(c, nc + 2))) return rc;  // async; read after the stream sync below
+  if ((rc = read_h(c, nc + 2, kMaxCols))) return rc;
   launch_gemv_sub(n, U, c->ld, nu, V, c->ld, nv, c->hbuf, 1, z, 0, c->st, c->rb, s);
-  // the second pass reuses hbuf only after the copy above was queued (stream order)
-  double before2;
-  CKH(hipStreamSynchronize(s));
-  before2 = c->hbuf_host[nc + 1];
+  // the second pass overwrites hbuf only after the copy above (stream order)
   launch_multidot<double>(n, U, c->ld, nu, V, c->ld, nv, z, nullptr, 1, 0, c->hbuf, c->rb, s);
   launch_gemv_sub(n, U, c->ld, nu, V, c->ld, nv, c->hbuf, 1, z, 1, c->st, c->rb, s);
-  if ((rc = sync_state(c))) return rc;
-  norms[0] = std::sqrt(std::max(0.0, before2));
+  return ISIRA_OK;
+}
+
+// norms[0] = ||z|| before the second pass, norms[1] = after (after sync_state).
+void cgs2_norms(const isira_ctx* c, int nc, double* norms) {
+  norms[0] = std::sqrt(std::max(0.0, c->hbuf_host[kMaxCols + nc + 1]));
   norms[1] = std::sqrt(std::max(0.0, c->st_host->red[2]));
+}
+
+int cgs2(isira_ctx* c, const double* U, int nu, const double* V, int nv, double* z,
+         double* norms) {
+  int rc;
+  if ((rc = cgs2_queue(c, U, nu, V, nv, z))) return rc;
+  if ((rc = sync_state(c))) return rc;
+  cgs2_norms(c, nu + nv, norms);
   return ISIRA_OK;
 }
 
@@ -693,7 +766,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
   cfg.precond = opt.precond;
   cfg.sigma = sigma;
   cfg.delta = delta;
-  cfg.rtol = opt.inner_rtol > 0 ? opt.inner_rtol : 1e-4;
+  cfg.rtol = opt.inner_rtol > 0 ? opt.inner_rtol : 1e-1;
   cfg.trim = trim;
   cfg.maxit = opt.max_inner > 0 ? opt.max_inner : 1000;
   cfg.check_every = opt.check_every > 0 ? opt.check_every : 8;
@@ -739,7 +812,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
   for (int j = 0; j < kk; ++j) {
     launch_multidot<double>(n, c->U, ld, kk, nullptr, ld, 0, c->W + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
     if ((rc = read_h(c, kk))) return rc;
-    CKH(hipStreamSynchronize(s));
+    SYNC_OR_RETURN(c);
     for (int i = 0; i < kk; ++i) H[i + (size_t)j * m] = c->hbuf_host[i];
   }
   for (int i = 0; i < kk; ++i)
@@ -777,7 +850,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     }
     int r2 = read_h(c, cc);
     if (r2) return r2;
-    CKH(hipStreamSynchronize(s));
+    SYNC_OR_RETURN(c);
     for (int i = 0; i < cc; ++i) {
       Cmat[i + (size_t)cnew * kMaxC] = c->hbuf_host[i];
       Cmat[cnew + (size_t)i * kMaxC] = c->hbuf_host[i];
@@ -787,39 +860,49 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
       for (int i = 0; i < cc; ++i)
         G[i + (size_t)j * cc] = (i == j ? 1.0 : 0.0) + delta * Cmat[i + (size_t)j * kMaxC];
     if (!spd_inverse(cc, G, Gi)) return fail(ISIRA_E_PRECOND, "SMW capacitance matrix not positive definite");
-    CKH(hipMemcpyAsync(c->Ginv, Gi.data(), Gi.size() * 8, hipMemcpyHostToDevice, s));
-    CKH(hipStreamSynchronize(s));
-    return ISIRA_OK;
+    return upload(c, c->Ginv, Gi.data(), Gi.size() * 8);
   };
 
   auto expand_with = [&](double* z) -> int {
-    // orthonormalize z against [U V 1] and append u, w = (L + delta V V^T) u, H column
+    // orthonormalize z against [U V 1] and append u, w = (L + delta V V^T) u and the new
+    // column of H.  Everything is queued behind one wait; on a CGS2 breakdown (rare) the
+    // queued results are discarded and a replacement vector is expanded instead.
     double nrm[2];
     int r2;
     double t0 = now_ms();
-    if ((r2 = cgs2(c, c->U, kk, c->Vout, nconv, z, nrm))) return r2;
-    while (!(nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0)) {
-      S.breakdowns++;
-      launch_fill_replacement(n, opt.seed, draws++, c->d_perm, z, s);
-      if ((r2 = cgs2(c, c->U, kk, c->Vout, nconv, z, nrm))) return r2;
-    }
     double* u = c->U + (size_t)kk * ld;
     double* w = c->W + (size_t)kk * ld;
-    launch_scale(n, z, 1.0 / nrm[1], u, s);
-    S.ms_ortho += now_ms() - t0;
-    if (nconv > 0)
-      launch_multidot<double>(n, c->Vout, ld, nconv, nullptr, ld, 0, u, nullptr, 0, 0, c->hbuf, c->rb, s);
-    spmv64(c, u, w, c->Vout, nconv, c->hbuf, delta, 0, 0.0);
-    S.spmv_total++;
-    launch_multidot<double>(n, c->U, ld, kk + 1, nullptr, ld, 0, w, nullptr, 0, 0, c->hbuf, c->rb, s);
-    if ((r2 = read_h(c, kk + 1))) return r2;
-    CKH(hipStreamSynchronize(s));
+    for (;;) {
+      if ((r2 = cgs2_queue(c, c->U, kk, c->Vout, nconv, z))) return r2;
+      launch_scale_dev(n, z, c->st->red + 2, u, s);
+      if (nconv > 0)
+        launch_multidot<double>(n, c->Vout, ld, nconv, nullptr, ld, 0, u, nullptr, 0, 0, c->hbuf, c->rb, s);
+      spmv64(c, u, w, c->Vout, nconv, c->hbuf, delta, 0, 0.0);
+      launch_multidot<double>(n, c->U, ld, kk + 1, nullptr, ld, 0, w, nullptr, 0, 0, c->hbuf, c->rb, s);
+      if ((r2 = read_h(c, kk + 1))) return r2;
+      if ((r2 = sync_state(c))) return r2;
+      S.spmv_total++;
+      cgs2_norms(c, kk + nconv, nrm);
+      if (nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0) break;
+      S.breakdowns++;
+      launch_fill_replacement(n, opt.seed, draws++, c->d_perm, z, s);
+    }
     for (int i = 0; i <= kk; ++i) {
       H[i + (size_t)kk * m] = c->hbuf_host[i];
       H[kk + (size_t)i * m] = c->hbuf_host[i];
     }
     kk += 1;
+    S.ms_ortho += now_ms() - t0;
     return ISIRA_OK;
+  };
+
+  auto start_inner = [&]() {
+    // the right-hand side is the Ritz residual in r64; its sum is st->red[1]
+    if (cfg.prec == ISIRA_FP64) {
+      inner_pcg_start<double>(c, cfg, c->r64, 0.0, c->st->red + 1, nconv);
+    } else {
+      inner_pcg_start<float>(c, cfg, c->r64, 0.0, c->st->red + 1, nconv);
+    }
   };
 
   while (nconv < k) {
@@ -839,13 +922,14 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     if ((rc = isira_symeig(kk, Hk.data(), theta.data(), Sm.data())))
       return fail(rc, "Rayleigh-Ritz eigensolver did not converge");
     S.ms_rr_host += now_ms() - t0;
-    // ---- Ritz residual r = W s1 - theta1 U s1
+    // ---- Ritz residual r = W s1 - theta1 U s1.  The inner solve for it is queued at once,
+    // behind the same wait: when the pair turns out converged that work is simply dropped.
     t0 = now_ms();
-    CKH(hipMemcpyAsync(c->svec, Sm.data(), kk * 8, hipMemcpyHostToDevice, s));
+    if ((rc = upload(c, c->svec, Sm.data(), kk * 8))) return rc;
     launch_ritz_residual(n, c->U, c->W, ld, kk, c->svec, theta[0], c->r64, c->st, c->rb, s);
+    start_inner();
     if ((rc = sync_state(c))) return rc;
     const double rn = std::sqrt(std::max(0.0, c->st_host->red[0]));
-    const double rsum = c->st_host->red[1];
     S.ms_residual += now_ms() - t0;
     if (rn < tol) {
       // fresh FP64 residual of the Ritz pair before locking
@@ -872,10 +956,11 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
         // eigenvector purging: U <- U S(:, 2:k), W <- W S(:, 2:k), H <- diag(theta_2..)
         t0 = now_ms();
         if (kk > 1) {
+          // S(:, 2:kk) row by row for the tall-skinny product
           Spack.assign((size_t)kk * (kk - 1), 0.0);
           for (int j = 1; j < kk; ++j)
-            for (int i = 0; i < kk; ++i) Spack[i + (size_t)(j - 1) * kk] = Sm[i + (size_t)j * kk];
-          CKH(hipMemcpyAsync(c->Sdev, Spack.data(), Spack.size() * 8, hipMemcpyHostToDevice, s));
+            for (int i = 0; i < kk; ++i) Spack[(size_t)i * (kk - 1) + (j - 1)] = Sm[i + (size_t)j * kk];
+          if ((rc = upload(c, c->Sdev, Spack.data(), Spack.size() * 8))) return rc;
           launch_tsgemm_inplace(n, c->U, ld, kk, c->Sdev, kk - 1, s);
           launch_tsgemm_inplace(n, c->W, ld, kk, c->Sdev, kk - 1, s);
         }
@@ -904,7 +989,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
       for (int j = 0; j < kk; ++j) {
         launch_multidot<double>(n, c->U, ld, kk, nullptr, ld, 0, c->W + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
         if ((rc = read_h(c, kk))) return rc;
-        CKH(hipStreamSynchronize(s));
+        if ((rc = stream_sync(c))) return rc;
         for (int i = 0; i < kk; ++i) H[i + (size_t)j * m] = c->hbuf_host[i];
       }
       for (int i = 0; i < kk; ++i)
@@ -916,9 +1001,13 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     }
     if (kk == m) {
       // subspace restart: U <- U S(:, 1:q), W <- W S(:, 1:q), H <- diag(theta_1..theta_q)
+      // (the queued inner solve reads neither U nor W)
       t0 = now_ms();
       S.restarts++;
-      CKH(hipMemcpyAsync(c->Sdev, Sm.data(), (size_t)kk * q * 8, hipMemcpyHostToDevice, s));
+      Spack.assign((size_t)kk * q, 0.0);
+      for (int j = 0; j < q; ++j)
+        for (int i = 0; i < kk; ++i) Spack[(size_t)i * q + j] = Sm[i + (size_t)j * kk];
+      if ((rc = upload(c, c->Sdev, Spack.data(), Spack.size() * 8))) return rc;
       launch_tsgemm_inplace(n, c->U, ld, kk, c->Sdev, q, s);
       launch_tsgemm_inplace(n, c->W, ld, kk, c->Sdev, q, s);
       std::fill(H.begin(), H.end(), 0.0);
@@ -930,11 +1019,10 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     t0 = now_ms();
     int its = 0, status = 0;
     double rel = 0.0;
-    const double mean = rsum / (double)n;
     if (cfg.prec == ISIRA_FP64) {
-      rc = inner_pcg<double>(c, cfg, c->r64, mean, nconv, &its, &status, &rel);
+      rc = inner_pcg_finish<double>(c, cfg, nconv, true, &its, &status, &rel);
     } else {
-      rc = inner_pcg<float>(c, cfg, c->r64, mean, nconv, &its, &status, &rel);
+      rc = inner_pcg_finish<float>(c, cfg, nconv, true, &its, &status, &rel);
     }
     if (rc) return rc;
     if (status == kPcgBreakdown) S.inner_fallbacks++;
@@ -976,7 +1064,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     double* v = c->Vout + (size_t)j * ld;
     launch_signed_gather(n, v, c->d_perm, c->d_iperm, evecs + (size_t)j * n, c->scal4, c->rb, s);
   }
-  CKH(hipStreamSynchronize(s));
+  SYNC_OR_RETURN(c);
   S.n_converged = nconv;
   S.outer_total = outer;
   S.ms_total = now_ms() - t_start;
@@ -996,7 +1084,7 @@ extern "C" int isira_laplacian_apply(isira_ctx* c, const double* x, double* y) {
   launch_gather<double, double>(n, x, c->d_perm, c->x64, c->stream);
   spmv64(c, c->x64, c->y64, nullptr, 0, nullptr, 0.0, 0, 0.0);
   launch_gather<double, double>(n, c->y64, c->d_iperm, y, c->stream);
-  CKH(hipStreamSynchronize(c->stream));
+  SYNC_OR_RETURN(c);
   return ISIRA_OK;
 }
 
@@ -1017,7 +1105,7 @@ extern "C" int isira_laplacian_apply_f32(isira_ctx* c, const float* x, float* y)
   a.trim = -1;
   launch_spmv<float>(c->plan, valmode32(c), a, c->rb, c->stream);
   launch_gather<float, float>(n, c->y32, c->d_iperm, y, c->stream);
-  CKH(hipStreamSynchronize(c->stream));
+  SYNC_OR_RETURN(c);
   return ISIRA_OK;
 }
 
@@ -1106,7 +1194,7 @@ extern "C" int isira_inner_solve(isira_ctx* c, const double* r, const double* V,
       launch_multidot<float>(n, c->Vin32, ld, nc, nullptr, ld, 0, c->Vin32 + (size_t)j * ld, c->dinv32, 0, 0, c->hbuf, c->rb, s);
     }
     if ((rc = read_h(c, nc))) return rc;
-    CKH(hipStreamSynchronize(s));
+    SYNC_OR_RETURN(c);
     for (int i = 0; i < nc; ++i) Cm[i + (size_t)j * nc] = c->hbuf_host[i];
   }
   if (nc > 0) {
@@ -1115,7 +1203,7 @@ extern "C" int isira_inner_solve(isira_ctx* c, const double* r, const double* V,
       for (int i = 0; i < nc; ++i)
         G[i + (size_t)j * nc] = (i == j ? 1.0 : 0.0) + cfg.delta * 0.5 * (Cm[i + (size_t)j * nc] + Cm[j + (size_t)i * nc]);
     if (!spd_inverse(nc, G, Gi)) return fail(ISIRA_E_PRECOND, "SMW capacitance matrix not positive definite");
-    CKH(hipMemcpyAsync(c->Ginv, Gi.data(), Gi.size() * 8, hipMemcpyHostToDevice, s));
+    if ((rc = upload(c, c->Ginv, Gi.data(), Gi.size() * 8))) return rc;
   }
   CKH(hipMemcpyAsync(c->tmp64, r, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
   launch_gather<double, double>(n, c->tmp64, c->d_perm, c->r64, s);
@@ -1127,7 +1215,7 @@ extern "C" int isira_inner_solve(isira_ctx* c, const double* r, const double* V,
   if (prec == ISIRA_FP64) launch_enlarge<double>(n, c->x64, c->z64, c->st, c->rb, s);
   else launch_enlarge<float>(n, c->x32, c->z64, c->st, c->rb, s);
   launch_gather<double, double>(n, c->z64, c->d_iperm, z, s);
-  CKH(hipStreamSynchronize(s));
+  SYNC_OR_RETURN(c);
   if (iters) *iters = its;
   if (relres) *relres = rel;
   return ISIRA_OK;
@@ -1147,7 +1235,7 @@ extern "C" int isira_orthonormalize(isira_ctx* c, const double* Q, int32_t ncols
   if ((rc = cgs2(c, c->U, ncols, c->Vout, 0, c->z64, norms))) return rc;
   launch_scale(n, c->z64, norms[1] > 0 ? 1.0 / norms[1] : 0.0, c->tmp64, s);
   launch_gather<double, double>(n, c->tmp64, c->d_iperm, u, s);
-  CKH(hipStreamSynchronize(s));
+  SYNC_OR_RETURN(c);
   return ISIRA_OK;
 }
 
@@ -1171,7 +1259,7 @@ extern "C" int isira_spai_install(isira_ctx* c, const float* params, double sigm
   if (spai::forward(c->spw, c->rp, c->col, wts, wdt, c->deg, (int)c->n, c->nnz, sigma, t, params,
                     c->stream))
     return fail(ISIRA_E_HIP, "SPAI forward failed");
-  CKH(hipStreamSynchronize(c->stream));
+  SYNC_OR_RETURN(c);
   c->has_learned = true;
   c->spai_sigma = sigma;
   c->spai_trim = t;
@@ -1183,7 +1271,7 @@ extern "C" int isira_spai_export(isira_ctx* c, float* diag, float* offd) {
   if (!c->has_learned) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
   launch_gather<float, float>((int)c->n, c->spw.diag32, c->d_iperm, diag, c->stream);
   spai::scatter_offd(c->nnz, c->spw.offd, c->d_emap, offd, c->stream);
-  CKH(hipStreamSynchronize(c->stream));
+  SYNC_OR_RETURN(c);
   return ISIRA_OK;
 }
 
@@ -1209,7 +1297,7 @@ extern "C" int isira_adam_step(isira_ctx* c, float* param, const float* grad, fl
                                int32_t step) {
   if (!c || !param || !grad || !m || !v || count < 1 || step < 1) return fail(ISIRA_E_ARG, "bad argument");
   spai::adam(param, grad, m, v, count, lr, beta1, beta2, eps, step, c->stream);
-  CKH(hipStreamSynchronize(c->stream));
+  SYNC_OR_RETURN(c);
   return ISIRA_OK;
 }
 

@@ -25,6 +25,7 @@ constexpr int kHubGrid = 256;
 constexpr int kMaxC = ISIRA_MAX_K;     // deflation columns in the inner solve
 constexpr int kTile = 512;             // rows per tile of the column-dot kernels
 constexpr int kMaxCols = 2 * ISIRA_MAX_BASIS + 2;  // columns of one multi-dot
+constexpr size_t kUploadRing = 1 << 20;            // pinned bytes for small uploads
 // Values x workgroups of the largest reduction in the learned-preconditioner backward pass.
 constexpr int kSpaiRedValues = 600;
 constexpr int kSpaiRedGrid = 512;
@@ -36,11 +37,13 @@ constexpr size_t kPartialsElems =
          (size_t)kSpaiRedValues * kSpaiRedGrid);
 
 // SpMV work units (int4, device), built on the host from the relabelled CSR:
-//   stream unit  {r0, r1, G, -1}: rows [r0, r1) with at most kUnitNnz nonzeros and
-//                kUnitRows rows; their products are staged in LDS and each row is summed
-//                by G lanes;
-//   chunk unit   {row, j0, j1, p}: nonzeros [j0, j1) of a row longer than kUnitNnz, whose
-//                sum goes to split_part[p] and is finished by the second dispatch.
+//   stream unit  {r0, j0, j1, rows << 8 | G}: rows [r0, r0 + rows) holding nonzeros
+//                [j0, j1) (at most the unit size); their products are staged in LDS and
+//                each row is summed by G lanes;
+//   chunk unit   {row, j0, j1, -(p + 1)}: nonzeros [j0, j1) of a row longer than the unit
+//                size, whose sum goes to split_part[p] and is finished by the second
+//                dispatch.
+
 // Scalars of the inner PCG and of the outer reductions, living in device memory.
 struct DevState {
   double alpha, beta, rho, pq, rr, rr0, rmr, thresh2, rtol2, sump, sumx;
@@ -101,6 +104,8 @@ struct SpmvArgs {
   double theta;
   DevState* st;
   int32_t check_done;  // return at once when st->done
+  int32_t fold_c;      // red 1 only: p^T q also gets delta * ||st->t1(0:fold_c)||^2, the
+                       // deflation term of the operator applied by the residual update
 };
 
 // ---- launchers (kernels.hip) ----
@@ -127,8 +132,9 @@ void launch_pcg_update2(int n, const T* r, T* p, const T* dinv, const T* V, int6
 // learned preconditioner variants: update1 without the Jacobi dots; apply y = M r with
 // the SMW dots; update2 with z = y - delta Y g.
 template <typename T>
-void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, int init,
-                              DevState* st, RedBuf rb, hipStream_t s);
+void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, const T* V,
+                              int64_t ldv, int c, double delta, int init, DevState* st,
+                              RedBuf rb, hipStream_t s);
 template <typename T>
 void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv, int c,
                                 const T* V, double delta, int init, DevState* st, RedBuf rb,
@@ -137,8 +143,8 @@ void launch_spai_finish_rho(int c, const double* Ginv, double delta, int init, D
                             hipStream_t s);
 
 template <typename T>
-void launch_rhs_prep(int n, const double* r64, double mean, int trim, T* rin, T* x,
-                     hipStream_t s);
+void launch_rhs_prep(int n, const double* r64, double mean, const double* mean_sum,
+                     double inv_n, int trim, T* rin, T* x, hipStream_t s);
 template <typename T>
 void launch_enlarge(int n, const T* x, double* z, DevState* st, RedBuf rb, hipStream_t s);
 
@@ -153,6 +159,8 @@ void launch_gemv_sub(int n, const double* A, int64_t lda, int na, const double* 
                      int64_t ldb, int nb, const double* h, int with_sum, double* z,
                      int with_norm, DevState* st, RedBuf rb, hipStream_t s);
 void launch_scale(int n, const double* z, double scale, double* u, hipStream_t s);
+void launch_scale_dev(int n, const double* z, const double* nrm2, double* u, hipStream_t s);
+void launch_pcg_reset(DevState* st, double rtol2, int maxit, hipStream_t s);
 void launch_ritz_residual(int n, const double* U, const double* W, int64_t ld, int k,
                           const double* svec, double theta, double* r, DevState* st, RedBuf rb,
                           hipStream_t s);

@@ -258,12 +258,12 @@ __device__ __forceinline__ T edge_val(const void* vals, int j) {
   }
 }
 
-// Finish row `row` given the neighbour sum; returns this row's reduction contribution.
+// Finish row `row` given the neighbour sum and the row's own x and diagonal entries;
+// returns this row's reduction contribution.
 template <int VM, typename T>
-__device__ __forceinline__ double finish_row(const SpmvArgs<T>& a, int row, T nsum,
-                                             const double* sh_t, T shift_add) {
-  const T xl = a.x[row];
-  T y = a.diag[row] * xl;
+__device__ __forceinline__ double finish_row_xd(const SpmvArgs<T>& a, int row, T nsum, T xl,
+                                                T dl, const double* sh_t, T shift_add) {
+  T y = dl * xl;
   if constexpr (VM == kF32Pos) {
     y += nsum;
   } else {
@@ -285,6 +285,12 @@ __device__ __forceinline__ double finish_row(const SpmvArgs<T>& a, int row, T ns
   }
   if (a.red == 1 || a.red == 3) return (double)xl * (double)y;
   return 0.0;
+}
+
+template <int VM, typename T>
+__device__ __forceinline__ double finish_row(const SpmvArgs<T>& a, int row, T nsum,
+                                             const double* sh_t, T shift_add) {
+  return finish_row_xd<VM, T>(a, row, nsum, a.x[row], a.diag[row], sh_t, shift_add);
 }
 
 // Sparse product over work units (persistent grid, units taken round-robin).  A stream unit
@@ -318,48 +324,88 @@ __global__ __launch_bounds__(NT) void k_spmv(SpmvArgs<T> a, const int4* __restri
     for (int i = tid; i < hn; i += NT) xs[i] = x[i];
   }
   __syncthreads();
-  double acc = 0.0;
-  for (int u = blockIdx.x; u < n_units; u += gridDim.x) {
-    const int4 un = units[u];
-    int j0, j1;
-    if (un.w < 0) {
-      j0 = a.rp[un.x];
-      j1 = a.rp[un.y];
+  // x gathers; the hub shape reads the staged labels from LDS
+  auto gx = [&](int c) -> T {
+    if constexpr (HUB > 0) {
+      return c < HUB ? xs[c] : x[c];
     } else {
-      j0 = un.y;
-      j1 = un.z;
+      return x[c];
     }
-    int ci[PT];
-    T v[PT];
+  };
+  double acc = 0.0;
+  // Software pipeline: unit descriptors are read two units ahead and the column indices
+  // and values of the next unit are loaded while the current unit is gathered and reduced.
+  const int G0 = gridDim.x;
+  int u = blockIdx.x;
+  // descriptors kept as plain scalars: int4 copies of HIP's vector type go through scratch
+  struct Desc {
+    int x, y, z, w;
+  };
+  auto ld_desc = [&](int i) -> Desc {
+    if (i < n_units) {
+      const int4 t = units[i];
+      return Desc{t.x, t.y, t.z, t.w};
+    }
+    return Desc{0, 0, 0, 0};
+  };
+  Desc dcur = ld_desc(u);
+  Desc dnxt = ld_desc(u + G0);
+  int ci[PT];
+  T v[PT];
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    const int e = dcur.y + tid + k * NT;
+    const bool in = u < n_units && e < dcur.z;
+    ci[k] = in ? col[e] : -1;
+    v[k] = in ? edge_val<VM, T>(a.vals, e) : T(0);
+  }
+  for (; u < n_units; u += G0) {
+    const Desc un = dcur;  // {r0 | row, j0, j1, (rows << 8 | G) | -(chunk + 1)}
+    const Desc dnn = ld_desc(u + 2 * G0);
+    // dnxt is all zero past the last unit, so every lane of the prefetch is out of range.
+    // Only the hub shape prefetches a unit ahead: it runs one workgroup per CU, so the
+    // registers are free; the stream shape keeps its occupancy instead.
+    constexpr bool PIPE = HUB > 0;
+    int cn[PT];
+    T vn[PT];
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
-      const int e = j0 + tid + k * NT;
-      ci[k] = (e < j1) ? col[e] : -1;
-      v[k] = (e < j1) ? edge_val<VM, T>(a.vals, e) : T(0);
+      const int e = dnxt.y + tid + k * NT;
+      const bool in = PIPE && e < dnxt.z;
+      cn[k] = in ? col[e] : -1;
+      vn[k] = in ? edge_val<VM, T>(a.vals, e) : T(0);
     }
-    // x gathers; the hub shape reads the staged labels from LDS
-    auto gx = [&](int c) -> T {
-      if constexpr (HUB > 0) {
-        return c < HUB ? xs[c] : x[c];
-      } else {
-        return x[c];
+    const int j0 = un.y;
+    if (un.w >= 0) {
+      const int r0 = un.x, nr = un.w >> 8, G = un.w & 255;
+      const int R = NT / G, grp = tid / G, gl = tid - grp * G;
+      for (int t = tid; t <= nr; t += NT) srp[t] = a.rp[r0 + t] - j0;
+      // the first two rows of each group: own x and diagonal entries, loaded early
+      T xl0 = T(0), dl0 = T(0), xl1 = T(0), dl1 = T(0);
+      if (gl == 0 && grp < nr) {
+        xl0 = x[r0 + grp];
+        dl0 = a.diag[r0 + grp];
+        if (grp + R < nr) {
+          xl1 = x[r0 + grp + R];
+          dl1 = a.diag[r0 + grp + R];
+        }
       }
-    };
-    if (un.w < 0) {
-      const int nr = un.y - un.x;
-      for (int t = tid; t <= nr; t += NT) srp[t] = a.rp[un.x + t] - j0;
 #pragma unroll
       for (int k = 0; k < PT; ++k)
         if (ci[k] >= 0) prod[tid + k * NT] = v[k] * gx(ci[k]);
       __syncthreads();
-      const int G = un.z;
-      const int R = NT / G, grp = tid / G, gl = tid - grp * G;
-      for (int rr = grp; rr < nr; rr += R) {
+      int it = 0;
+      for (int rr = grp; rr < nr; rr += R, ++it) {
         T s = T(0);
         const int e = srp[rr + 1];
         for (int j = srp[rr] + gl; j < e; j += G) s += prod[j];
         s = group_sum(s, G);
-        if (gl == 0) acc += finish_row<VM, T>(a, un.x + rr, s, sh_t, shift_add);
+        if (gl == 0) {
+          const int row = r0 + rr;
+          if (it == 0) acc += finish_row_xd<VM, T>(a, row, s, xl0, dl0, sh_t, shift_add);
+          else if (it == 1) acc += finish_row_xd<VM, T>(a, row, s, xl1, dl1, sh_t, shift_add);
+          else acc += finish_row<VM, T>(a, row, s, sh_t, shift_add);
+        }
       }
       __syncthreads();
     } else {
@@ -373,9 +419,23 @@ __global__ __launch_bounds__(NT) void k_spmv(SpmvArgs<T> a, const int4* __restri
       if (tid == 0) {
         T t = T(0);
         for (int w = 0; w < NT / 64; ++w) t += shT[w];
-        chunk_part[un.w] = (double)t;
+        chunk_part[-un.w - 1] = (double)t;
       }
       __syncthreads();
+    }
+    dcur = dnxt;
+    dnxt = dnn;
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      if constexpr (PIPE) {
+        ci[k] = cn[k];
+        v[k] = vn[k];
+      } else {
+        const int e = dcur.y + tid + k * NT;
+        const bool in = e < dcur.z;
+        ci[k] = in ? col[e] : -1;
+        v[k] = in ? edge_val<VM, T>(a.vals, e) : T(0);
+      }
     }
   }
   if (a.red == 0) return;
@@ -409,9 +469,15 @@ __global__ __launch_bounds__(kFin) void k_spmv_fin(SpmvArgs<T> a, SplitInfo sp, 
   if (tid == 0) {
     DevState* st = a.st;
     if (a.red == 1) {
-      st->pq = tot;
-      const double alpha = st->rho / tot;
-      if (!(tot > 0.0) || !isfinite(alpha)) {
+      double pq = tot;
+      if (a.fold_c > 0) {
+        double tt = 0.0;
+        for (int j = 0; j < a.fold_c; ++j) tt += st->t1[j] * st->t1[j];
+        pq += a.delta * tt;
+      }
+      st->pq = pq;
+      const double alpha = st->rho / pq;
+      if (!(pq > 0.0) || !isfinite(alpha)) {
         st->done = 1;
         st->status = kPcgBreakdown;
       }
@@ -477,9 +543,10 @@ template void launch_spmv<float>(const SpmvPlan&, int, const SpmvArgs<float>&, R
 
 // ------------------------------------------------------------------ PCG updates
 
-// x += alpha p; r -= alpha q; partials ||r||^2, r^T M^-1 r, V-hat^T (M^-1 r).  The last
-// workgroup forms g = G^-1 t2 and rho = r^T z (eq. (3.5) makes r^T z = r^T M^-1 r -
-// delta t2^T g), tests convergence and sets beta.
+// x += alpha p; r -= alpha (q + delta V-hat t1) with q the product without the deflation
+// term and t1 = V-hat^T p, so that V-hat is read once per iteration; partials ||r||^2,
+// r^T D^-1 r and V-hat^T (D^-1 r).  The finishing dispatch forms g = G^-1 t2 and rho = r^T z
+// (eq. (3.5) makes r^T z = r^T D^-1 r - delta t2^T g), tests convergence and sets beta.
 template <typename T, int CM>
 __global__ __launch_bounds__(kBlock) void k_pcg_update1(int n, T* __restrict__ x,
                                                         T* __restrict__ r,
@@ -492,15 +559,31 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update1(int n, T* __restrict__ x
                                                         double* partials, unsigned* counter) {
   if (st->done) return;
   constexpr int NV = 2 + (CM > 0 ? CM : 0);
+  __shared__ T st1[CM > 0 ? CM : 1];
+  if constexpr (CM > 0) {
+    for (int j = threadIdx.x; j < c; j += kBlock) st1[j] = init ? T(0) : (T)st->t1[j];
+    __syncthreads();
+  }
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   const T alpha = init ? T(0) : (T)st->alpha;
+  const T dl = (T)delta;
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    T vreg[CM > 0 ? CM : 1];
+    T vt = T(0);
+#pragma unroll
+    for (int j = 0; j < CM; ++j) {
+      vreg[j] = T(0);
+      if (j < c) {
+        vreg[j] = V[l + (int64_t)j * ldv];
+        vt += vreg[j] * st1[j];
+      }
+    }
     T rl = r[l];
     if (!init) {
       x[l] += alpha * p[l];
-      rl -= alpha * q[l];
+      rl -= alpha * (q[l] + dl * vt);
       r[l] = rl;
     }
     const T u = dinv[l] * rl;
@@ -508,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update1(int n, T* __restrict__ x
     acc[1] += (double)rl * (double)u;
 #pragma unroll
     for (int j = 0; j < CM; ++j)
-      if (j < c) acc[2 + j] += (double)V[l + (int64_t)j * ldv] * (double)u;
+      if (j < c) acc[2 + j] += (double)vreg[j] * (double)u;
   }
   write_partials<NV>(acc, 2 + c, partials);
 }
@@ -706,22 +789,31 @@ template void launch_pcg_update2<float>(int, const float*, float*, const float*,
 
 // ---- learned preconditioner variants ----
 
-// x += alpha p; r -= alpha q; partial ||r||^2; the last workgroup tests convergence.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_update1_plain(int n, T* __restrict__ x,
-                                                              T* __restrict__ r,
-                                                              const T* __restrict__ p,
-                                                              const T* __restrict__ q, int init,
-                                                              DevState* st, double* partials,
-                                                              unsigned* counter) {
+// x += alpha p; r -= alpha (q + delta V-hat t1) (q without the deflation term, t1 =
+// V-hat^T p); partial ||r||^2; the finishing dispatch tests convergence.
+template <typename T, int CM>
+__global__ __launch_bounds__(kBlock) void k_pcg_update1_plain(
+    int n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+    const T* __restrict__ q, const T* __restrict__ V, int64_t ldv, int c, double delta,
+    int init, DevState* st, double* partials) {
   if (st->done) return;
+  __shared__ T st1[CM > 0 ? CM : 1];
+  if constexpr (CM > 0) {
+    for (int j = threadIdx.x; j < c; j += kBlock) st1[j] = (T)st->t1[j];
+    __syncthreads();
+  }
   double acc[1] = {0.0};
   const T alpha = init ? T(0) : (T)st->alpha;
+  const T dl = (T)delta;
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
     T rl = r[l];
     if (!init) {
+      T vt = T(0);
+#pragma unroll
+      for (int j = 0; j < CM; ++j)
+        if (j < c) vt += V[l + (int64_t)j * ldv] * st1[j];
       x[l] += alpha * p[l];
-      rl -= alpha * q[l];
+      rl -= alpha * (q[l] + dl * vt);
       r[l] = rl;
     }
     acc[0] += (double)rl * (double)rl;
@@ -824,11 +916,33 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update2_learned(
 }
 
 template <typename T>
-void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, int init, DevState* st,
+void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, const T* V,
+                              int64_t ldv, int c, double delta, int init, DevState* st,
                               RedBuf rb, hipStream_t s) {
-  k_pcg_update1_plain<T><<<stream_grid(n), kBlock, 0, s>>>(n, x, r, p, q, init, st,
-                                                          rb.partials, rb.counters + 4);
-  k_pcg_fin1_plain<<<1, kFin, 0, s>>>(stream_grid(n), rb.partials, init, st);
+  const int grid = stream_grid(n);
+  switch (pick_cm(c)) {
+    case 0:
+      k_pcg_update1_plain<T, 0><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, init,
+                                                        st, rb.partials);
+      break;
+    case 8:
+      k_pcg_update1_plain<T, 8><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, init,
+                                                        st, rb.partials);
+      break;
+    case 16:
+      k_pcg_update1_plain<T, 16><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, init,
+                                                         st, rb.partials);
+      break;
+    case 32:
+      k_pcg_update1_plain<T, 32><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, init,
+                                                         st, rb.partials);
+      break;
+    default:
+      k_pcg_update1_plain<T, 64><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, init,
+                                                         st, rb.partials);
+      break;
+  }
+  k_pcg_fin1_plain<<<1, kFin, 0, s>>>(grid, rb.partials, init, st);
   HIP_LAUNCH_CHECK();
 }
 template <typename T>
@@ -863,10 +977,11 @@ void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv
   HIP_LAUNCH_CHECK();
 }
 template void launch_pcg_update1_plain<double>(int, double*, double*, const double*,
-                                               const double*, int, DevState*, RedBuf,
-                                               hipStream_t);
+                                               const double*, const double*, int64_t, int,
+                                               double, int, DevState*, RedBuf, hipStream_t);
 template void launch_pcg_update1_plain<float>(int, float*, float*, const float*, const float*,
-                                              int, DevState*, RedBuf, hipStream_t);
+                                              const float*, int64_t, int, double, int,
+                                              DevState*, RedBuf, hipStream_t);
 template void launch_pcg_update2_learned<double>(int, const double*, double*, const double*,
                                                  int64_t, int, const double*, double, int,
                                                  DevState*, RedBuf, hipStream_t);
@@ -876,26 +991,54 @@ template void launch_pcg_update2_learned<float>(int, const float*, float*, const
 
 // ------------------------------------------------------------------ right-hand side, enlarge
 
-// r_in = trim(r - mean) in the inner precision (entry `trim` is 0); x = 0.
+// r_in = trim(r - mean) in the inner precision (entry `trim` is 0); x = 0.  The mean is
+// `mean`, or *mean_sum * inv_n when mean_sum is given (a sum left on the device).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rhs_prep(int n, const double* __restrict__ r64,
-                                                     double mean, int trim, T* __restrict__ rin,
-                                                     T* __restrict__ x) {
+                                                     double mean, const double* mean_sum,
+                                                     double inv_n, int trim,
+                                                     T* __restrict__ rin, T* __restrict__ x) {
+  const double mu = mean_sum ? *mean_sum * inv_n : mean;
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
-    rin[l] = (l == trim) ? T(0) : (T)(r64[l] - mean);
+    rin[l] = (l == trim) ? T(0) : (T)(r64[l] - mu);
     x[l] = T(0);
   }
 }
 template <typename T>
-void launch_rhs_prep(int n, const double* r64, double mean, int trim, T* rin, T* x,
-                     hipStream_t s) {
-  k_rhs_prep<T><<<stream_grid(n), kBlock, 0, s>>>(n, r64, mean, trim, rin, x);
+void launch_rhs_prep(int n, const double* r64, double mean, const double* mean_sum,
+                     double inv_n, int trim, T* rin, T* x, hipStream_t s) {
+  k_rhs_prep<T><<<stream_grid(n), kBlock, 0, s>>>(n, r64, mean, mean_sum, inv_n, trim, rin, x);
   HIP_LAUNCH_CHECK();
 }
-template void launch_rhs_prep<double>(int, const double*, double, int, double*, double*,
-                                      hipStream_t);
-template void launch_rhs_prep<float>(int, const double*, double, int, float*, float*,
-                                     hipStream_t);
+template void launch_rhs_prep<double>(int, const double*, double, const double*, double, int,
+                                      double*, double*, hipStream_t);
+template void launch_rhs_prep<float>(int, const double*, double, const double*, double, int,
+                                     float*, float*, hipStream_t);
+
+// Resets the inner-iteration fields of the device state (the generic outputs red[] are
+// kept: they may hold the Ritz residual the right-hand side is built from).
+__global__ void k_pcg_reset(DevState* st, double rtol2, int maxit) {
+  const int t = threadIdx.x;
+  for (int j = t; j < kMaxC; j += blockDim.x) {
+    st->t1[j] = 0.0;
+    st->g[j] = 0.0;
+  }
+  for (int j = t; j < kMaxC + 1; j += blockDim.x) st->t2[j] = 0.0;
+  if (t == 0) {
+    st->alpha = st->beta = st->rho = st->pq = st->rr = st->rr0 = st->rmr = 0.0;
+    st->thresh2 = 0.0;
+    st->rtol2 = rtol2;
+    st->sump = st->sumx = 0.0;
+    st->it = 0;
+    st->done = 0;
+    st->status = 0;
+    st->maxit = maxit;
+  }
+}
+void launch_pcg_reset(DevState* st, double rtol2, int maxit, hipStream_t s) {
+  k_pcg_reset<<<1, 64, 0, s>>>(st, rtol2, maxit);
+  HIP_LAUNCH_CHECK();
+}
 
 // eq. (2.5): z = x - (1^T x / n) 1, in FP64 (x carries the trimmed zero in place).
 template <typename T>
@@ -1082,6 +1225,20 @@ void launch_scale(int n, const double* z, double scale, double* u, hipStream_t s
   HIP_LAUNCH_CHECK();
 }
 
+// u = z / sqrt(*nrm2) with the squared norm left on the device (u = 0 when it is not > 0).
+__global__ __launch_bounds__(kBlock) void k_scale_dev(int n, const double* __restrict__ z,
+                                                      const double* nrm2,
+                                                      double* __restrict__ u) {
+  const double v = *nrm2;
+  const double sc = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
+    u[l] = z[l] * sc;
+}
+void launch_scale_dev(int n, const double* z, const double* nrm2, double* u, hipStream_t s) {
+  k_scale_dev<<<stream_grid(n), kBlock, 0, s>>>(n, z, nrm2, u);
+  HIP_LAUNCH_CHECK();
+}
+
 // ------------------------------------------------------------------ Ritz vectors, residuals
 
 // r = W s - theta U s; partials ||r||^2 -> st->red[0], sum(r) -> st->red[1].
@@ -1137,50 +1294,81 @@ void launch_ritz_vector(int n, const double* U, int64_t ld, int k, const double*
   HIP_LAUNCH_CHECK();
 }
 
-// U[:, 0:q] = U[:, 0:k] S[:, 0:q] in place (S k-by-q column-major, device).  Each
-// workgroup stages a tile of rows of U and a panel of S in LDS.
-constexpr int kTsRows = 32;
-constexpr int kTsCols = 16;
+// U[:, 0:q] = U[:, 0:k] S in place, with S (k x q) stored row by row (St[i * q + j] = S(i, j)).
+// Each workgroup stages a tile of 64 rows of U column-major in LDS (lane = row: conflict-free);
+// each wave then forms eight output columns at a time.  The wave index is made provably
+// uniform, so the eight entries S(i, j0:j0+8) of a row of S are one scalar load and every
+// LDS read feeds eight FMAs.  All reads of a tile precede its writes, so the update is in place.
+constexpr int kTsRows = 64;
+constexpr int kTsCw = 8;
 __global__ __launch_bounds__(kBlock) void k_tsgemm_inplace(int n, double* __restrict__ U,
                                                            int64_t ld, int k,
-                                                           const double* __restrict__ S,
+                                                           const double* __restrict__ St,
                                                            int q) {
-  __shared__ double ut[kTsRows * ISIRA_MAX_BASIS];
-  __shared__ double sp[ISIRA_MAX_BASIS * kTsCols];
-  const int tid = threadIdx.x;
-  const int rr = tid % kTsRows, cg = tid / kTsRows;  // 8 column groups
+  extern __shared__ double ut[];  // k * kTsRows
+  const int r = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ntiles = (n + kTsRows - 1) / kTsRows;
+  const int ngroups = (q + kTsCw - 1) / kTsCw;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int base = tile * kTsRows;
-    const int len = (n - base) < kTsRows ? (n - base) : kTsRows;
+    const bool ok = base + r < n;
     __syncthreads();
-    for (int e = tid; e < kTsRows * k; e += kBlock) {
-      const int j = e / kTsRows, i = e - j * kTsRows;
-      ut[i * k + j] = (i < len) ? U[base + i + (int64_t)j * ld] : 0.0;
-    }
-    for (int c0 = 0; c0 < q; c0 += kTsCols) {
-      const int nc = (q - c0) < kTsCols ? (q - c0) : kTsCols;
-      __syncthreads();
-      for (int e = tid; e < k * nc; e += kBlock) {
-        const int jc = e / k, i = e - jc * k;
-        sp[jc * k + i] = S[i + (int64_t)(c0 + jc) * k];
+    // eight columns in flight per wave
+    for (int i0 = w; i0 < k; i0 += 32) {
+      double t[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int i = i0 + 4 * b;
+        t[b] = (ok && i < k) ? U[base + r + (int64_t)i * ld] : 0.0;
       }
-      __syncthreads();
-      for (int jc = cg; jc < nc; jc += kBlock / kTsRows) {
-        double s = 0.0;
-        const double* urow = ut + rr * k;
-        const double* scol = sp + jc * k;
-        for (int i = 0; i < k; ++i) s += urow[i] * scol[i];
-        if (rr < len) U[base + rr + (int64_t)(c0 + jc) * ld] = s;
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        if (i0 + 4 * b < k) ut[(i0 + 4 * b) * kTsRows + r] = t[b];
+    }
+    __syncthreads();
+    for (int g = w; g < ngroups; g += 4) {
+      const int j0 = g * kTsCw;
+      double a[kTsCw];
+#pragma unroll
+      for (int jj = 0; jj < kTsCw; ++jj) a[jj] = 0.0;
+      if (j0 + kTsCw <= q) {
+#pragma unroll 4
+        for (int i = 0; i < k; ++i) {
+          const double u = ut[i * kTsRows + r];
+          const double* sr = St + (int64_t)i * q + j0;
+#pragma unroll
+          for (int jj = 0; jj < kTsCw; ++jj) a[jj] += u * sr[jj];
+        }
+      } else {
+        const int nj = q - j0;
+        for (int i = 0; i < k; ++i) {
+          const double u = ut[i * kTsRows + r];
+          const double* sr = St + (int64_t)i * q + j0;
+#pragma unroll
+          for (int jj = 0; jj < kTsCw; ++jj)
+            if (jj < nj) a[jj] += u * sr[jj];
+        }
+      }
+      if (ok) {
+#pragma unroll
+        for (int jj = 0; jj < kTsCw; ++jj)
+          if (j0 + jj < q) U[base + r + (int64_t)(j0 + jj) * ld] = a[jj];
       }
     }
   }
 }
-void launch_tsgemm_inplace(int n, double* U, int64_t ld, int k, const double* S, int q,
+void launch_tsgemm_inplace(int n, double* U, int64_t ld, int k, const double* St, int q,
                            hipStream_t s) {
   int grid = (n + kTsRows - 1) / kTsRows;
-  if (grid > 4 * kStreamGrid) grid = 4 * kStreamGrid;
-  k_tsgemm_inplace<<<grid, kBlock, 0, s>>>(n, U, ld, k, S, q);
+  if (grid > 2048) grid = 2048;
+  static bool lds_raised = false;  // k <= 192 needs up to 96 KB of dynamic LDS
+  if (!lds_raised) {
+    (void)hipFuncSetAttribute((const void*)k_tsgemm_inplace,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              ISIRA_MAX_BASIS * kTsRows * (int)sizeof(double));
+    lds_raised = true;
+  }
+  k_tsgemm_inplace<<<grid, kBlock, (size_t)k * kTsRows * sizeof(double), s>>>(n, U, ld, k, St, q);
   HIP_LAUNCH_CHECK();
 }
 

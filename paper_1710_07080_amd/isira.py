@@ -101,6 +101,11 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} not found: build it with paper_1710_07080_amd/build.py "
                           "(or __graft_entry__.build())")
+    # torch's HIP runtime must be the one in the process before the library binds to it:
+    # device memory and streams come from torch, and a second runtime loaded first may not
+    # see the device
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double

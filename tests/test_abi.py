@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(P):
 
 def test_defaults_and_strerror(P):
     o = P.isira.default_options()
-    assert o.k0 == 4 and o.inner_rtol == 1e-4 and o.trim_index == -1 and o.check_every == 8
+    assert o.k0 == 4 and o.inner_rtol == 1e-1 and o.trim_index == -1 and o.check_every == 8
     lib = P.load()
     for code in [0, 1, -1, -2, -3, -4, -5, -6]:
         assert lib.isira_strerror(code)
