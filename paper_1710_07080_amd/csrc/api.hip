@@ -146,19 +146,20 @@ static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp,
   P.hub = (n > 4 * kHubX64 && (double)hits >= 0.25 * (double)col.size()) ? 1 : 0;
   const int unnz = P.hub ? kHubUnitNnz : kUnitNnz;
   const int urows = P.hub ? kHubUnitRows : kUnitRows;
+  const int chunk = unnz;  // nonzeros per piece of a long row
   std::vector<int4> units;
   std::vector<int32_t> rowof, base, nch;
   int nchunks = 0;
   int row = 0;
   while (row < n && rp[row + 1] - rp[row] > unnz) {
     const int len = rp[row + 1] - rp[row];
-    const int nc = (len + unnz - 1) / unnz;
+    const int nc = (len + chunk - 1) / chunk;
     rowof.push_back(row);
     base.push_back(nchunks);
     nch.push_back(nc);
     for (int c = 0; c < nc; ++c) {
-      const int j0 = rp[row] + c * unnz;
-      const int j1 = std::min(rp[row + 1], j0 + unnz);
+      const int j0 = rp[row] + c * chunk;
+      const int j1 = std::min(rp[row + 1], j0 + chunk);
       units.push_back(make_int4(row, j0, j1, -(nchunks + c + 1)));
     }
     nchunks += nc;
@@ -212,10 +213,17 @@ static int ensure_workspace(isira_ctx* c, int m, int kmax) {
   if ((rc = dalloc(&c->U, ld * m))) return rc;
   if ((rc = dalloc(&c->W, ld * m))) return rc;
   if ((rc = dalloc(&c->Vout, ld * kmax))) return rc;
-  if ((rc = dalloc(&c->Vin64, ld * kmax))) return rc;
-  if ((rc = dalloc(&c->Y64, ld * kmax))) return rc;
-  if ((rc = dalloc(&c->Vin32, ld * kmax))) return rc;
-  if ((rc = dalloc(&c->Y32, ld * kmax))) return rc;
+  // deflation blocks of the inner solve: whole column groups, zeroed once (the kernels read
+  // the padding columns and weight them by 0, which needs finite values)
+  const size_t kpad = (size_t)std::max(pick_cm(kmax), 4);
+  if ((rc = dalloc(&c->Vin64, ld * kpad))) return rc;
+  if ((rc = dalloc(&c->Y64, ld * kpad))) return rc;
+  if ((rc = dalloc(&c->Vin32, ld * kpad))) return rc;
+  if ((rc = dalloc(&c->Y32, ld * kpad))) return rc;
+  CKH(hipMemset(c->Vin64, 0, ld * kpad * sizeof(double)));
+  CKH(hipMemset(c->Y64, 0, ld * kpad * sizeof(double)));
+  CKH(hipMemset(c->Vin32, 0, ld * kpad * sizeof(float)));
+  CKH(hipMemset(c->Y32, 0, ld * kpad * sizeof(float)));
   for (double** p : {&c->r64, &c->z64, &c->tmp64, &c->x64, &c->ri64, &c->p64, &c->q64,
                      &c->dinv64, &c->y64})
     if ((rc = dalloc(p, ld))) return rc;
@@ -623,9 +631,10 @@ void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
   a.n = n;
   a.trim = cfg.trim;
   a.sigma = cfg.sigma;
-  a.sig_over_n = cfg.sigma / (double)n;
-  // the deflation term delta V-hat (V-hat^T p) of the operator is applied by the residual
-  // update (which reads V-hat anyway) and folded into p^T q by the product's reduction
+  // the deflation term delta V-hat (V-hat^T p) and the rank-one term (sigma/n) 1-hat 1-hat^T p
+  // of the operator are applied by the residual update (which reads V-hat anyway) and folded
+  // into p^T q by the product's finishing dispatch, which also reduces the p-update's sums
+  a.sig_over_n = 0.0;
   a.V = nullptr;
   a.ldv = c->ld;
   a.c = 0;
@@ -635,6 +644,10 @@ void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
   a.st = c->st;
   a.check_done = 1;
   a.fold_c = nc;
+  a.fold_nblk = stream_grid(n);
+  a.fold_partials = c->rb.partials;
+  a.fold_sig_over_n = cfg.sigma / (double)n;
+  const double sig_over_n = cfg.sigma / (double)n;
   // one iteration: [product] then the residual update and the preconditioned direction;
   // the first call (init) has no product and starts from x = 0, r = rhs
   for (int it = 0; it < iters; ++it) {
@@ -642,8 +655,8 @@ void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
     if (!first) launch_spmv<T>(c->plan, vm, a, c->rb, s);
     if (learned) {
       // y = M r with the dots V-hat^T y and r^T y, then eq. (3.5)
-      launch_pcg_update1_plain<T>(n, b.x, b.r, b.p, b.q, b.V, c->ld, nc, cfg.delta, first,
-                                  c->st, c->rb, s);
+      launch_pcg_update1_plain<T>(n, b.x, b.r, b.p, b.q, b.V, c->ld, nc, cfg.delta, cfg.trim,
+                                  sig_over_n, first, c->st, c->rb, s);
       spai::apply<T>(c->spw, c->plan, c->rp, c->col, b.r, b.y, n, cfg.trim, b.V, c->ld, nc,
                      c->st, c->rb, s);
       launch_spai_finish_rho(nc, c->Ginv, cfg.delta, first, c->st, s);
@@ -651,7 +664,7 @@ void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
                                     c->rb, s);
     } else {
       launch_pcg_update1<T>(n, b.x, b.r, b.p, b.q, b.dinv, b.V, c->ld, nc, c->Ginv, cfg.delta,
-                            first, c->st, c->rb, s);
+                            cfg.trim, sig_over_n, first, c->st, c->rb, s);
       launch_pcg_update2<T>(n, b.r, b.p, b.dinv, b.V, c->ld, nc, cfg.delta, first, c->st,
                             c->rb, s);
     }

@@ -11,15 +11,19 @@
 namespace isira {
 
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
-constexpr int kStreamGrid = 512;       // max workgroups of grid-stride streaming kernels
+#ifndef ISIRA_STREAM_GRID
+#define ISIRA_STREAM_GRID 1024
+#endif
+// max workgroups of grid-stride streaming kernels (compile-time tunable)
+constexpr int kStreamGrid = ISIRA_STREAM_GRID;
 constexpr int kSpmvGrid = 2048;       // max workgroups of the persistent SpMV grid
 constexpr int kUnitNnz = 2048;        // nonzeros per SpMV unit (stream unit or long-row chunk)
-constexpr int kUnitRows = 512;        // rows per stream unit at most
+constexpr int kUnitRows = 256;        // rows per stream unit at most
 // hub-cached shape for power-law graphs (one 1024-thread workgroup per CU)
 constexpr int kHubThreads = 1024;
 constexpr int kHubUnitNnz = 8192;
 constexpr int kHubUnitRows = 2048;
-constexpr int kHubX64 = 10240;        // FP64 x entries staged in LDS (80 KB)
+constexpr int kHubX64 = 8192;         // FP64 x entries staged in LDS (64 KB)
 constexpr int kHubX32 = 24576;        // FP32 x entries staged in LDS (96 KB)
 constexpr int kHubGrid = 256;
 constexpr int kMaxC = ISIRA_MAX_K;     // deflation columns in the inner solve
@@ -30,10 +34,27 @@ constexpr size_t kUploadRing = 1 << 20;            // pinned bytes for small upl
 constexpr int kSpaiRedValues = 600;
 constexpr int kSpaiRedGrid = 512;
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+// workgroups of a grid-stride streaming kernel over n rows (one partial per workgroup)
+inline int stream_grid(int n) {
+  int g = (n + kBlock - 1) / kBlock;
+  return g < 1 ? 1 : (g > kStreamGrid ? kStreamGrid : g);
+}
+
+// The PCG kernels process the c deflation columns in whole groups: c rounded up to the next
+// of these sizes.  The columns past c are allocated, finite (zeroed once) and weighted by 0.
+inline int pick_cm(int c) {
+  if (c <= 0) return 0;
+  if (c <= 24) return (c + 3) / 4 * 4;
+  if (c <= 48) return (c + 7) / 8 * 8;
+  return 64;
+}
+
 // Capacity (doubles) of the shared partials buffer: every reducing kernel writes at most
-// values x workgroups of it, each checked against this bound at compile time.
+// values x workgroups of it, each checked against this bound at compile time.  The
+// product's own partials sit after the p-update's, which its finishing dispatch reads.
+constexpr size_t kSpmvPartOff = (size_t)(1 + kMaxC) * kStreamGrid;
 constexpr size_t kPartialsElems =
-    cmax(cmax((size_t)kMaxCols * kStreamGrid, (size_t)4 * kSpmvGrid),
+    cmax(cmax((size_t)kMaxCols * kStreamGrid, kSpmvPartOff + (size_t)4 * kSpmvGrid),
          (size_t)kSpaiRedValues * kSpaiRedGrid);
 
 // SpMV work units (int4, device), built on the host from the relabelled CSR:
@@ -104,8 +125,15 @@ struct SpmvArgs {
   double theta;
   DevState* st;
   int32_t check_done;  // return at once when st->done
-  int32_t fold_c;      // red 1 only: p^T q also gets delta * ||st->t1(0:fold_c)||^2, the
-                       // deflation term of the operator applied by the residual update
+  // PCG product (red 1) only: the deflation term delta V-hat (V-hat^T p) and the rank-one
+  // term (sigma/n) 1-hat (1-hat^T p) of the operator are applied by the residual update;
+  // the finishing dispatch first reduces the partials of the p-update (fold_nblk workgroups:
+  // sum(p), then V-hat^T p) into st->sump, st->t1, and folds delta ||t1||^2 and
+  // fold_sig_over_n * sump^2 into p^T q.
+  int32_t fold_c;
+  int32_t fold_nblk;
+  const double* fold_partials;
+  double fold_sig_over_n;
 };
 
 // ---- launchers (kernels.hip) ----
@@ -124,8 +152,8 @@ void launch_spmv_probe(const SpmvPlan& plan, int valmode, const SpmvArgs<T>& a, 
 
 template <typename T>
 void launch_pcg_update1(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const T* V,
-                        int64_t ldv, int c, const double* Ginv, double delta, int init,
-                        DevState* st, RedBuf rb, hipStream_t s);
+                        int64_t ldv, int c, const double* Ginv, double delta, int trim,
+                        double sig_over_n, int init, DevState* st, RedBuf rb, hipStream_t s);
 template <typename T>
 void launch_pcg_update2(int n, const T* r, T* p, const T* dinv, const T* V, int64_t ldv,
                         int c, double delta, int init, DevState* st, RedBuf rb, hipStream_t s);
@@ -133,8 +161,8 @@ void launch_pcg_update2(int n, const T* r, T* p, const T* dinv, const T* V, int6
 // the SMW dots; update2 with z = y - delta Y g.
 template <typename T>
 void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, const T* V,
-                              int64_t ldv, int c, double delta, int init, DevState* st,
-                              RedBuf rb, hipStream_t s);
+                              int64_t ldv, int c, double delta, int trim, double sig_over_n,
+                              int init, DevState* st, RedBuf rb, hipStream_t s);
 template <typename T>
 void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv, int c,
                                 const T* V, double delta, int init, DevState* st, RedBuf rb,

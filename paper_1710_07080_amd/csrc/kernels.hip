@@ -109,10 +109,7 @@ static_assert((size_t)(2 + kMaxC) * kStreamGrid <= kPartialsElems, "PCG partials
 static_assert((size_t)kMaxCols * kStreamGrid <= kPartialsElems, "multi-dot partials");
 static_assert((size_t)kSpmvGrid <= kPartialsElems, "SpMV partials");
 
-static inline int stream_grid(int n) {
-  int g = (n + kBlock - 1) / kBlock;
-  return g < 1 ? 1 : (g > kStreamGrid ? kStreamGrid : g);
-}
+
 
 #define HIP_LAUNCH_CHECK() (void)hipGetLastError()
 
@@ -272,9 +269,20 @@ __device__ __forceinline__ double finish_row_xd(const SpmvArgs<T>& a, int row, T
   if (a.sigma != 0.0) y -= (T)a.sigma * xl;
   y += shift_add;
   if (a.c > 0) {
+    // four columns in flight (the last group re-reads column c-1 with weight 0)
     T s = T(0);
     const T* __restrict__ V = a.V + row;
-    for (int j = 0; j < a.c; ++j) s += V[(int64_t)j * a.ldv] * (T)sh_t[j];
+    for (int j0 = 0; j0 < a.c; j0 += 4) {
+      T v4[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = j0 + i < a.c ? j0 + i : a.c - 1;
+        v4[i] = V[(int64_t)j * a.ldv];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (j0 + i < a.c) s += v4[i] * (T)sh_t[j0 + i];
+    }
     y += (T)a.delta * s;
   }
   if (row == a.trim) y = T(0);
@@ -293,23 +301,63 @@ __device__ __forceinline__ double finish_row(const SpmvArgs<T>& a, int row, T ns
   return finish_row_xd<VM, T>(a, row, nsum, a.x[row], a.diag[row], sh_t, shift_add);
 }
 
+// x[c] for all PT slots of a thread (c = -1 marks an empty slot, whose value is 0).  Every
+// load is unconditional, so that all of them are in flight before the first is used: an
+// empty slot reads x[0], and with a hub cache a column below HUB reads xs[c] while its
+// global load is redirected to x[0] as well (one shared cache line per wave).  Selecting
+// between the LDS and the global pointer instead would make generic-address loads that
+// the compiler waits for one at a time.
+template <typename T, int PT, int HUB>
+__device__ __forceinline__ void gather_slots(const int (&ci)[PT], const T* __restrict__ x,
+                                             const T* xs, T (&g)[PT]) {
+  T gg[PT];
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    const int c = ci[k];
+    const bool glob = HUB > 0 ? c >= HUB : c >= 0;
+    gg[k] = x[glob ? c : 0];
+  }
+  if constexpr (HUB > 0) {
+    T gl[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int c = ci[k];
+      gl[k] = xs[(c >= 0 && c < HUB) ? c : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int c = ci[k];
+      g[k] = c < 0 ? T(0) : (c < HUB ? gl[k] : gg[k]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < PT; ++k) g[k] = ci[k] < 0 ? T(0) : gg[k];
+  }
+}
+
 // Sparse product over work units (persistent grid, units taken round-robin).  A stream unit
-// loads all its column indices (and row pointers) in one coalesced batch, then all its x
-// gathers in a second batch, staging the products in LDS; each row is then summed from
-// LDS by G lanes and finished.  A chunk unit of a long row sums its nonzeros into one
+// loads its column indices and its rows' pointers, own x entries and diagonal entries in one
+// coalesced batch, gathers x for all its nonzeros and stages the products in LDS; each row
+// is then summed from LDS by G lanes into a row sum in LDS, and every thread finishes the
+// rows it loaded (coalesced stores).  A chunk unit of a long row sums its nonzeros into one
 // partial.  Two shapes: 256 threads / 2048-nonzero units (8 workgroups per CU), and, for
 // power-law graphs, 1024 threads / 8192-nonzero units with x of the HUB highest-degree
 // columns (the first HUB labels after relabelling) staged once per workgroup in LDS, so
-// that those gathers never reach L2.  TAG only separates the symbol of the bandwidth probe
+// that those gathers never reach L2.  A thread's slots of the next unit are loaded as soon
+// as the current unit is finished.  TAG only separates the symbol of the bandwidth probe
 // (isira_time_spmv) from the solver's launches in profiler summaries.
 template <typename T, int VM, int TAG, int NT, int UNNZ, int UROWS, int HUB>
 __global__ __launch_bounds__(NT) void k_spmv(SpmvArgs<T> a, const int4* __restrict__ units,
                                              int n_units, double* partials,
                                              double* __restrict__ chunk_part) {
   if (a.check_done && a.st->done) return;
-  constexpr int PT = UNNZ / NT;
+  constexpr int PT = UNNZ / NT;           // nonzeros per thread and unit
+  constexpr int RPT = (UROWS + NT) / NT;  // row pointers per thread (UROWS + 1 entries)
+  constexpr int RRT = UROWS / NT;         // rows finished per thread
+  static_assert(UROWS % NT == 0, "unit rows");
   __shared__ T prod[UNNZ];
   __shared__ int srp[UROWS + 1];
+  __shared__ T srow[UROWS];
   __shared__ T xs[HUB > 0 ? HUB : 1];
   __shared__ double sh_t[kMaxC];
   __shared__ T shT[NT / 64];
@@ -318,101 +366,117 @@ __global__ __launch_bounds__(NT) void k_spmv(SpmvArgs<T> a, const int4* __restri
   for (int j = tid; j < a.c; j += NT) sh_t[j] = tv[j];
   const T shift_add = (a.sig_over_n != 0.0) ? (T)(a.sig_over_n * a.st->sump) : T(0);
   const T* __restrict__ x = a.x;
+  const T* __restrict__ dg = a.diag;
   const int32_t* __restrict__ col = a.col;
+  const int32_t* __restrict__ rp = a.rp;
   if constexpr (HUB > 0) {
     const int hn = a.n < HUB ? a.n : HUB;
     for (int i = tid; i < hn; i += NT) xs[i] = x[i];
   }
   __syncthreads();
-  // x gathers; the hub shape reads the staged labels from LDS
-  auto gx = [&](int c) -> T {
-    if constexpr (HUB > 0) {
-      return c < HUB ? xs[c] : x[c];
-    } else {
-      return x[c];
-    }
-  };
-  double acc = 0.0;
-  // Software pipeline: unit descriptors are read two units ahead and the column indices
-  // and values of the next unit are loaded while the current unit is gathered and reduced.
-  const int G0 = gridDim.x;
-  int u = blockIdx.x;
+  // x gathers for all slots at once (see gather_slots)
+  auto gather = [&](const int (&ci)[PT], T (&g)[PT]) { gather_slots<T, PT, HUB>(ci, x, xs, g); };
   // descriptors kept as plain scalars: int4 copies of HIP's vector type go through scratch
   struct Desc {
-    int x, y, z, w;
+    int x, y, z, w;  // {r0 | row, j0, j1, (rows << 8 | G) | -(chunk + 1)}
   };
   auto ld_desc = [&](int i) -> Desc {
     if (i < n_units) {
       const int4 t = units[i];
       return Desc{t.x, t.y, t.z, t.w};
     }
-    return Desc{0, 0, 0, 0};
+    return Desc{0, 0, 0, 0};  // j0 = j1 and no rows: every load below is skipped
   };
-  Desc dcur = ld_desc(u);
-  Desc dnxt = ld_desc(u + G0);
-  int ci[PT];
-  T v[PT];
-#pragma unroll
-  for (int k = 0; k < PT; ++k) {
-    const int e = dcur.y + tid + k * NT;
-    const bool in = u < n_units && e < dcur.z;
-    ci[k] = in ? col[e] : -1;
-    v[k] = in ? edge_val<VM, T>(a.vals, e) : T(0);
-  }
-  for (; u < n_units; u += G0) {
-    const Desc un = dcur;  // {r0 | row, j0, j1, (rows << 8 | G) | -(chunk + 1)}
-    const Desc dnn = ld_desc(u + 2 * G0);
-    // dnxt is all zero past the last unit, so every lane of the prefetch is out of range.
-    // Only the hub shape prefetches a unit ahead: it runs one workgroup per CU, so the
-    // registers are free; the stream shape keeps its occupancy instead.
-    constexpr bool PIPE = HUB > 0;
-    int cn[PT];
-    T vn[PT];
+  // everything a unit needs before its gathers, for the thread's slots
+  struct Slots {
+    int ci[PT];
+    T v[PT];
+    int rpv[RPT];
+    T xv[RRT], dv[RRT];
+  };
+  auto load_slots = [&](const Desc& d, Slots& sl) {
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
-      const int e = dnxt.y + tid + k * NT;
-      const bool in = PIPE && e < dnxt.z;
-      cn[k] = in ? col[e] : -1;
-      vn[k] = in ? edge_val<VM, T>(a.vals, e) : T(0);
+      const int e = d.y + tid + k * NT;
+      const bool in = e < d.z;
+      sl.ci[k] = in ? col[e] : -1;
+      sl.v[k] = in ? edge_val<VM, T>(a.vals, e) : T(0);
     }
+    const int nr = d.w >= 0 ? (d.w >> 8) : -1;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int t = tid + k * NT;
+      sl.rpv[k] = (t <= nr) ? rp[d.x + t] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < RRT; ++k) {
+      const int t = tid + k * NT;
+      const bool in = t < nr;
+      sl.xv[k] = in ? x[d.x + t] : T(0);
+      sl.dv[k] = in ? dg[d.x + t] : T(0);
+    }
+  };
+  double acc = 0.0;
+  const int G0 = gridDim.x;
+  int u = blockIdx.x;
+  Desc dcur = ld_desc(u);
+  Desc dnxt = ld_desc(u + G0);
+  Slots cur;
+  load_slots(dcur, cur);
+  for (; u < n_units; u += G0) {
+    const Desc un = dcur;
     const int j0 = un.y;
     if (un.w >= 0) {
       const int r0 = un.x, nr = un.w >> 8, G = un.w & 255;
       const int R = NT / G, grp = tid / G, gl = tid - grp * G;
-      for (int t = tid; t <= nr; t += NT) srp[t] = a.rp[r0 + t] - j0;
-      // the first two rows of each group: own x and diagonal entries, loaded early
-      T xl0 = T(0), dl0 = T(0), xl1 = T(0), dl1 = T(0);
-      if (gl == 0 && grp < nr) {
-        xl0 = x[r0 + grp];
-        dl0 = a.diag[r0 + grp];
-        if (grp + R < nr) {
-          xl1 = x[r0 + grp + R];
-          dl1 = a.diag[r0 + grp + R];
-        }
-      }
 #pragma unroll
-      for (int k = 0; k < PT; ++k)
-        if (ci[k] >= 0) prod[tid + k * NT] = v[k] * gx(ci[k]);
-      __syncthreads();
-      int it = 0;
-      for (int rr = grp; rr < nr; rr += R, ++it) {
-        T s = T(0);
-        const int e = srp[rr + 1];
-        for (int j = srp[rr] + gl; j < e; j += G) s += prod[j];
-        s = group_sum(s, G);
-        if (gl == 0) {
-          const int row = r0 + rr;
-          if (it == 0) acc += finish_row_xd<VM, T>(a, row, s, xl0, dl0, sh_t, shift_add);
-          else if (it == 1) acc += finish_row_xd<VM, T>(a, row, s, xl1, dl1, sh_t, shift_add);
-          else acc += finish_row<VM, T>(a, row, s, sh_t, shift_add);
-        }
+      for (int k = 0; k < RPT; ++k) {
+        const int t = tid + k * NT;
+        if (t <= nr) srp[t] = cur.rpv[k] - j0;
       }
+      T gv[PT];
+      gather(cur.ci, gv);
+#pragma unroll
+      for (int k = 0; k < PT; ++k) prod[tid + k * NT] = cur.v[k] * gv[k];
       __syncthreads();
+      if (G == 1) {
+        // one lane per row: the rows a thread sums are the rows it loaded
+#pragma unroll
+        for (int k = 0; k < RRT; ++k) {
+          const int t = tid + k * NT;
+          if (t < nr) {
+            T s = T(0);
+            const int e = srp[t + 1];
+            for (int j = srp[t]; j < e; ++j) s += prod[j];
+            acc += finish_row_xd<VM, T>(a, r0 + t, s, cur.xv[k], cur.dv[k], sh_t, shift_add);
+          }
+        }
+        // prod and srp are rewritten by the next unit only after this barrier (G is uniform)
+        __syncthreads();
+      } else {
+        for (int rr = grp; rr < nr; rr += R) {
+          T s = T(0);
+          const int e = srp[rr + 1];
+          for (int j = srp[rr] + gl; j < e; j += G) s += prod[j];
+          s = group_sum(s, G);
+          if (gl == 0) srow[rr] = s;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RRT; ++k) {
+          const int t = tid + k * NT;
+          if (t < nr)
+            acc += finish_row_xd<VM, T>(a, r0 + t, srow[t], cur.xv[k], cur.dv[k], sh_t, shift_add);
+        }
+        // prod and srp were last read before the barrier above; srow is rewritten by the
+        // next unit only after its first barrier
+      }
     } else {
+      T gv[PT];
+      gather(cur.ci, gv);
       T s = T(0);
 #pragma unroll
-      for (int k = 0; k < PT; ++k)
-        if (ci[k] >= 0) s += v[k] * gx(ci[k]);
+      for (int k = 0; k < PT; ++k) s += cur.v[k] * gv[k];
       s = wave_sum(s);
       if ((tid & 63) == 0) shT[tid >> 6] = s;
       __syncthreads();
@@ -424,19 +488,8 @@ __global__ __launch_bounds__(NT) void k_spmv(SpmvArgs<T> a, const int4* __restri
       __syncthreads();
     }
     dcur = dnxt;
-    dnxt = dnn;
-#pragma unroll
-    for (int k = 0; k < PT; ++k) {
-      if constexpr (PIPE) {
-        ci[k] = cn[k];
-        v[k] = vn[k];
-      } else {
-        const int e = dcur.y + tid + k * NT;
-        const bool in = e < dcur.z;
-        ci[k] = in ? col[e] : -1;
-        v[k] = in ? edge_val<VM, T>(a.vals, e) : T(0);
-      }
-    }
+    dnxt = ld_desc(u + 2 * G0);
+    load_slots(dcur, cur);
   }
   if (a.red == 0) return;
   const double bs = block_sum_any(acc);
@@ -451,7 +504,14 @@ __global__ __launch_bounds__(kFin) void k_spmv_fin(SpmvArgs<T> a, SplitInfo sp, 
                                                    const double* partials) {
   if (a.check_done && a.st->done) return;
   __shared__ double sh_t[kMaxC];
+  __shared__ double fold[1 + kMaxC];
   const int tid = threadIdx.x;
+  if (a.fold_partials) {
+    // sum(p) and V-hat^T p of the p-update, in a fixed order
+    final_reduce(a.fold_partials, 1 + a.fold_c, a.fold_nblk, fold);
+    if (tid == 0) a.st->sump = fold[0];
+    for (int j = tid; j < a.fold_c; j += blockDim.x) a.st->t1[j] = fold[1 + j];
+  }
   const double* tv = a.tvec ? a.tvec : (a.st ? a.st->t1 : nullptr);
   for (int j = tid; j < a.c; j += blockDim.x) sh_t[j] = tv[j];
   const T shift_add = (a.sig_over_n != 0.0) ? (T)(a.sig_over_n * a.st->sump) : T(0);
@@ -470,10 +530,10 @@ __global__ __launch_bounds__(kFin) void k_spmv_fin(SpmvArgs<T> a, SplitInfo sp, 
     DevState* st = a.st;
     if (a.red == 1) {
       double pq = tot;
-      if (a.fold_c > 0) {
+      if (a.fold_partials) {
         double tt = 0.0;
-        for (int j = 0; j < a.fold_c; ++j) tt += st->t1[j] * st->t1[j];
-        pq += a.delta * tt;
+        for (int j = 0; j < a.fold_c; ++j) tt += fold[1 + j] * fold[1 + j];
+        pq += a.delta * tt + a.fold_sig_over_n * fold[0] * fold[0];
       }
       st->pq = pq;
       const double alpha = st->rho / pq;
@@ -499,8 +559,8 @@ template <typename T, int VM, int TAG>
 static void spmv_dispatch(const SpmvPlan& plan, const SpmvArgs<T>& a, double* partials,
                           hipStream_t s) {
   const SplitInfo sp = split_info(plan);
+  constexpr int HUB = sizeof(T) == 8 ? kHubX64 : kHubX32;
   if (plan.hub) {
-    constexpr int HUB = sizeof(T) == 8 ? kHubX64 : kHubX32;
     k_spmv<T, VM, TAG, kHubThreads, kHubUnitNnz, kHubUnitRows, HUB>
         <<<plan.grid, kHubThreads, 0, s>>>(a, plan.units, plan.n_units, partials,
                                            plan.split_part);
@@ -515,11 +575,12 @@ static void spmv_dispatch(const SpmvPlan& plan, const SpmvArgs<T>& a, double* pa
 template <typename T>
 void launch_spmv(const SpmvPlan& plan, int valmode, const SpmvArgs<T>& a, RedBuf rb,
                  hipStream_t s) {
+  double* part = rb.partials ? rb.partials + kSpmvPartOff : nullptr;
   switch (valmode) {
-    case kUnitNeg: spmv_dispatch<T, kUnitNeg, 0>(plan, a, rb.partials, s); break;
-    case kF32Neg: spmv_dispatch<T, kF32Neg, 0>(plan, a, rb.partials, s); break;
-    case kF64Neg: spmv_dispatch<T, kF64Neg, 0>(plan, a, rb.partials, s); break;
-    default: spmv_dispatch<T, kF32Pos, 0>(plan, a, rb.partials, s); break;
+    case kUnitNeg: spmv_dispatch<T, kUnitNeg, 0>(plan, a, part, s); break;
+    case kF32Neg: spmv_dispatch<T, kF32Neg, 0>(plan, a, part, s); break;
+    case kF64Neg: spmv_dispatch<T, kF64Neg, 0>(plan, a, part, s); break;
+    default: spmv_dispatch<T, kF32Pos, 0>(plan, a, part, s); break;
   }
   HIP_LAUNCH_CHECK();
 }
@@ -555,13 +616,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update1(int n, T* __restrict__ x
                                                         const T* __restrict__ dinv,
                                                         const T* __restrict__ V, int64_t ldv,
                                                         int c, const double* Ginv,
-                                                        double delta, int init, DevState* st,
-                                                        double* partials, unsigned* counter) {
+                                                        double delta, int trim,
+                                                        double sig_over_n, int init,
+                                                        DevState* st, double* partials) {
   if (st->done) return;
   constexpr int NV = 2 + (CM > 0 ? CM : 0);
   __shared__ T st1[CM > 0 ? CM : 1];
   if constexpr (CM > 0) {
-    for (int j = threadIdx.x; j < c; j += kBlock) st1[j] = init ? T(0) : (T)st->t1[j];
+    for (int j = threadIdx.x; j < CM; j += kBlock) st1[j] = (init || j >= c) ? T(0) : (T)st->t1[j];
     __syncthreads();
   }
   double acc[NV];
@@ -569,29 +631,27 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update1(int n, T* __restrict__ x
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   const T alpha = init ? T(0) : (T)st->alpha;
   const T dl = (T)delta;
+  const T r1 = init ? T(0) : (T)(sig_over_n * st->sump);  // (sigma/n) 1-hat^T p
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    // all CM columns unconditionally (columns c..CM-1 are finite padding, weighted by 0),
+    // so that every load is in flight before the first is used
     T vreg[CM > 0 ? CM : 1];
     T vt = T(0);
 #pragma unroll
-    for (int j = 0; j < CM; ++j) {
-      vreg[j] = T(0);
-      if (j < c) {
-        vreg[j] = V[l + (int64_t)j * ldv];
-        vt += vreg[j] * st1[j];
-      }
-    }
+    for (int j = 0; j < CM; ++j) vreg[j] = V[l + (int64_t)j * ldv];
+#pragma unroll
+    for (int j = 0; j < CM; ++j) vt += vreg[j] * st1[j];
     T rl = r[l];
     if (!init) {
       x[l] += alpha * p[l];
-      rl -= alpha * (q[l] + dl * vt);
+      rl -= alpha * (q[l] + dl * vt + (l == trim ? T(0) : r1));
       r[l] = rl;
     }
     const T u = dinv[l] * rl;
     acc[0] += (double)rl * (double)rl;
     acc[1] += (double)rl * (double)u;
 #pragma unroll
-    for (int j = 0; j < CM; ++j)
-      if (j < c) acc[2 + j] += (double)vreg[j] * (double)u;
+    for (int j = 0; j < CM; ++j) acc[2 + j] += (double)vreg[j] * (double)u;
   }
   write_partials<NV>(acc, 2 + c, partials);
 }
@@ -659,12 +719,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update2(int n, const T* __restri
                                                         const T* __restrict__ dinv,
                                                         const T* __restrict__ V, int64_t ldv,
                                                         int c, double delta, int init,
-                                                        DevState* st, double* partials,
-                                                        unsigned* counter) {
+                                                        DevState* st, double* partials) {
   if (st->done) return;
   constexpr int NV = 1 + (CM > 0 ? CM : 0);
   __shared__ T sg[CM > 0 ? CM : 1];
-  for (int j = threadIdx.x; j < c; j += kBlock) sg[j] = (T)st->g[j];
+  for (int j = threadIdx.x; j < CM; j += kBlock) sg[j] = j < c ? (T)st->g[j] : T(0);
   __syncthreads();
   double acc[NV];
 #pragma unroll
@@ -675,111 +734,70 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update2(int n, const T* __restri
     T vreg[CM > 0 ? CM : 1];
     T s = T(0);
 #pragma unroll
-    for (int j = 0; j < CM; ++j) {
-      vreg[j] = T(0);
-      if (j < c) {
-        vreg[j] = V[l + (int64_t)j * ldv];
-        s += vreg[j] * sg[j];
-      }
-    }
+    for (int j = 0; j < CM; ++j) vreg[j] = V[l + (int64_t)j * ldv];
+#pragma unroll
+    for (int j = 0; j < CM; ++j) s += vreg[j] * sg[j];
     const T z = dinv[l] * (r[l] - dl * s);
     const T pn = init ? z : z + beta * p[l];
     p[l] = pn;
     acc[0] += (double)pn;
 #pragma unroll
-    for (int j = 0; j < CM; ++j)
-      if (j < c) acc[1 + j] += (double)vreg[j] * (double)pn;
+    for (int j = 0; j < CM; ++j) acc[1 + j] += (double)vreg[j] * (double)pn;
   }
   write_partials<NV>(acc, 1 + c, partials);
 }
 
-// Reduces the partials of the p-update (one workgroup): t1 = V-hat^T p, sum(p).
-__global__ __launch_bounds__(kFin) void k_pcg_fin2(int c, int nblk, const double* partials,
-                                                     DevState* st) {
-  if (st->done) return;
-  __shared__ double red[1 + kMaxC];
-  final_reduce(partials, 1 + c, nblk, red);
-  for (int j = threadIdx.x; j < c; j += blockDim.x) st->t1[j] = red[1 + j];
-  if (threadIdx.x == 0) st->sump = red[0];
-}
 
-static inline int pick_cm(int c) {
-  if (c <= 0) return 0;
-  if (c <= 8) return 8;
-  if (c <= 16) return 16;
-  if (c <= 32) return 32;
-  return 64;
-}
+#define ISIRA_CM_CASE(L, v) \
+  case v:                   \
+    L(v);                   \
+    break;
+#define ISIRA_CM_CASES(L)                                                                    \
+  ISIRA_CM_CASE(L, 0) ISIRA_CM_CASE(L, 4) ISIRA_CM_CASE(L, 8) ISIRA_CM_CASE(L, 12)            \
+  ISIRA_CM_CASE(L, 16) ISIRA_CM_CASE(L, 20) ISIRA_CM_CASE(L, 24) ISIRA_CM_CASE(L, 32)          \
+  ISIRA_CM_CASE(L, 40) ISIRA_CM_CASE(L, 48)                                                    \
+  default:                                                                                     \
+    L(64);                                                                                     \
+    break;
 
 template <typename T>
 void launch_pcg_update1(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const T* V,
-                        int64_t ldv, int c, const double* Ginv, double delta, int init,
-                        DevState* st, RedBuf rb, hipStream_t s) {
+                        int64_t ldv, int c, const double* Ginv, double delta, int trim,
+                        double sig_over_n, int init, DevState* st, RedBuf rb, hipStream_t s) {
   const int grid = stream_grid(n);
-  unsigned* cnt = rb.counters + 2;
+#define ISIRA_UPD1(CMV)                                                                   \
+  k_pcg_update1<T, CMV><<<grid, kBlock, 0, s>>>(n, x, r, p, q, dinv, V, ldv, c, Ginv, delta, \
+                                                trim, sig_over_n, init, st, rb.partials)
   switch (pick_cm(c)) {
-    case 0:
-      k_pcg_update1<T, 0><<<grid, kBlock, 0, s>>>(n, x, r, p, q, dinv, V, ldv, c, Ginv, delta,
-                                                  init, st, rb.partials, cnt);
-      break;
-    case 8:
-      k_pcg_update1<T, 8><<<grid, kBlock, 0, s>>>(n, x, r, p, q, dinv, V, ldv, c, Ginv, delta,
-                                                  init, st, rb.partials, cnt);
-      break;
-    case 16:
-      k_pcg_update1<T, 16><<<grid, kBlock, 0, s>>>(n, x, r, p, q, dinv, V, ldv, c, Ginv, delta,
-                                                   init, st, rb.partials, cnt);
-      break;
-    case 32:
-      k_pcg_update1<T, 32><<<grid, kBlock, 0, s>>>(n, x, r, p, q, dinv, V, ldv, c, Ginv, delta,
-                                                   init, st, rb.partials, cnt);
-      break;
-    default:
-      k_pcg_update1<T, 64><<<grid, kBlock, 0, s>>>(n, x, r, p, q, dinv, V, ldv, c, Ginv, delta,
-                                                   init, st, rb.partials, cnt);
-      break;
+    ISIRA_CM_CASES(ISIRA_UPD1)
   }
+#undef ISIRA_UPD1
   k_pcg_fin1<<<1, kFin, 0, s>>>(c, grid, rb.partials, Ginv, delta, init, st);
   HIP_LAUNCH_CHECK();
 }
 
+// The partials (sum(p), V-hat^T p) are reduced by the next product's finishing dispatch.
 template <typename T>
 void launch_pcg_update2(int n, const T* r, T* p, const T* dinv, const T* V, int64_t ldv, int c,
                         double delta, int init, DevState* st, RedBuf rb, hipStream_t s) {
   const int grid = stream_grid(n);
-  unsigned* cnt = rb.counters + 3;
+#define ISIRA_UPD2(CMV)                                                                   \
+  k_pcg_update2<T, CMV><<<grid, kBlock, 0, s>>>(n, r, p, dinv, V, ldv, c, delta, init, st, \
+                                                rb.partials)
   switch (pick_cm(c)) {
-    case 0:
-      k_pcg_update2<T, 0><<<grid, kBlock, 0, s>>>(n, r, p, dinv, V, ldv, c, delta, init, st,
-                                                  rb.partials, cnt);
-      break;
-    case 8:
-      k_pcg_update2<T, 8><<<grid, kBlock, 0, s>>>(n, r, p, dinv, V, ldv, c, delta, init, st,
-                                                  rb.partials, cnt);
-      break;
-    case 16:
-      k_pcg_update2<T, 16><<<grid, kBlock, 0, s>>>(n, r, p, dinv, V, ldv, c, delta, init, st,
-                                                   rb.partials, cnt);
-      break;
-    case 32:
-      k_pcg_update2<T, 32><<<grid, kBlock, 0, s>>>(n, r, p, dinv, V, ldv, c, delta, init, st,
-                                                   rb.partials, cnt);
-      break;
-    default:
-      k_pcg_update2<T, 64><<<grid, kBlock, 0, s>>>(n, r, p, dinv, V, ldv, c, delta, init, st,
-                                                   rb.partials, cnt);
-      break;
+    ISIRA_CM_CASES(ISIRA_UPD2)
   }
-  k_pcg_fin2<<<1, kFin, 0, s>>>(c, grid, rb.partials, st);
+#undef ISIRA_UPD2
   HIP_LAUNCH_CHECK();
 }
 template void launch_pcg_update1<double>(int, double*, double*, const double*, const double*,
                                          const double*, const double*, int64_t, int,
-                                         const double*, double, int, DevState*, RedBuf,
-                                         hipStream_t);
+                                         const double*, double, int, double, int, DevState*,
+                                         RedBuf, hipStream_t);
 template void launch_pcg_update1<float>(int, float*, float*, const float*, const float*,
                                         const float*, const float*, int64_t, int, const double*,
-                                        double, int, DevState*, RedBuf, hipStream_t);
+                                        double, int, double, int, DevState*, RedBuf,
+                                        hipStream_t);
 template void launch_pcg_update2<double>(int, const double*, double*, const double*,
                                          const double*, int64_t, int, double, int, DevState*,
                                          RedBuf, hipStream_t);
@@ -795,25 +813,28 @@ template <typename T, int CM>
 __global__ __launch_bounds__(kBlock) void k_pcg_update1_plain(
     int n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
     const T* __restrict__ q, const T* __restrict__ V, int64_t ldv, int c, double delta,
-    int init, DevState* st, double* partials) {
+    int trim, double sig_over_n, int init, DevState* st, double* partials) {
   if (st->done) return;
   __shared__ T st1[CM > 0 ? CM : 1];
   if constexpr (CM > 0) {
-    for (int j = threadIdx.x; j < c; j += kBlock) st1[j] = (T)st->t1[j];
+    for (int j = threadIdx.x; j < CM; j += kBlock) st1[j] = j < c ? (T)st->t1[j] : T(0);
     __syncthreads();
   }
   double acc[1] = {0.0};
   const T alpha = init ? T(0) : (T)st->alpha;
   const T dl = (T)delta;
+  const T r1 = init ? T(0) : (T)(sig_over_n * st->sump);  // (sigma/n) 1-hat^T p
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
     T rl = r[l];
     if (!init) {
+      T vreg[CM > 0 ? CM : 1];
       T vt = T(0);
 #pragma unroll
-      for (int j = 0; j < CM; ++j)
-        if (j < c) vt += V[l + (int64_t)j * ldv] * st1[j];
+      for (int j = 0; j < CM; ++j) vreg[j] = V[l + (int64_t)j * ldv];
+#pragma unroll
+      for (int j = 0; j < CM; ++j) vt += vreg[j] * st1[j];
       x[l] += alpha * p[l];
-      rl -= alpha * (q[l] + dl * vt);
+      rl -= alpha * (q[l] + dl * vt + (l == trim ? T(0) : r1));
       r[l] = rl;
     }
     acc[0] += (double)rl * (double)rl;
@@ -887,12 +908,11 @@ void launch_spai_finish_rho(int c, const double* Ginv, double delta, int init, D
 template <typename T, int CM>
 __global__ __launch_bounds__(kBlock) void k_pcg_update2_learned(
     int n, const T* __restrict__ y, T* __restrict__ p, const T* __restrict__ Y, int64_t ldv,
-    int c, const T* __restrict__ V, double delta, int init, DevState* st, double* partials,
-    unsigned* counter) {
+    int c, const T* __restrict__ V, double delta, int init, DevState* st, double* partials) {
   if (st->done) return;
   constexpr int NV = 1 + (CM > 0 ? CM : 0);
   __shared__ T sg[CM > 0 ? CM : 1];
-  for (int j = threadIdx.x; j < c; j += kBlock) sg[j] = (T)st->g[j];
+  for (int j = threadIdx.x; j < CM; j += kBlock) sg[j] = j < c ? (T)st->g[j] : T(0);
   __syncthreads();
   double acc[NV];
 #pragma unroll
@@ -900,88 +920,61 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update2_learned(
   const T beta = init ? T(0) : (T)st->beta;
   const T dl = (T)delta;
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    T yreg[CM > 0 ? CM : 1], vreg[CM > 0 ? CM : 1];
+#pragma unroll
+    for (int j = 0; j < CM; ++j) yreg[j] = Y[l + (int64_t)j * ldv];
+#pragma unroll
+    for (int j = 0; j < CM; ++j) vreg[j] = V[l + (int64_t)j * ldv];
     T s = T(0);
 #pragma unroll
-    for (int j = 0; j < CM; ++j)
-      if (j < c) s += Y[l + (int64_t)j * ldv] * sg[j];
+    for (int j = 0; j < CM; ++j) s += yreg[j] * sg[j];
     const T z = y[l] - dl * s;
     const T pn = init ? z : z + beta * p[l];
     p[l] = pn;
     acc[0] += (double)pn;
 #pragma unroll
-    for (int j = 0; j < CM; ++j)
-      if (j < c) acc[1 + j] += (double)V[l + (int64_t)j * ldv] * (double)pn;
+    for (int j = 0; j < CM; ++j) acc[1 + j] += (double)vreg[j] * (double)pn;
   }
   write_partials<NV>(acc, 1 + c, partials);
 }
 
 template <typename T>
 void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, const T* V,
-                              int64_t ldv, int c, double delta, int init, DevState* st,
-                              RedBuf rb, hipStream_t s) {
+                              int64_t ldv, int c, double delta, int trim, double sig_over_n,
+                              int init, DevState* st, RedBuf rb, hipStream_t s) {
   const int grid = stream_grid(n);
+#define ISIRA_UPD1P(CMV)                                                                  \
+  k_pcg_update1_plain<T, CMV><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, trim, \
+                                                      sig_over_n, init, st, rb.partials)
   switch (pick_cm(c)) {
-    case 0:
-      k_pcg_update1_plain<T, 0><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, init,
-                                                        st, rb.partials);
-      break;
-    case 8:
-      k_pcg_update1_plain<T, 8><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, init,
-                                                        st, rb.partials);
-      break;
-    case 16:
-      k_pcg_update1_plain<T, 16><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, init,
-                                                         st, rb.partials);
-      break;
-    case 32:
-      k_pcg_update1_plain<T, 32><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, init,
-                                                         st, rb.partials);
-      break;
-    default:
-      k_pcg_update1_plain<T, 64><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, init,
-                                                         st, rb.partials);
-      break;
+    ISIRA_CM_CASES(ISIRA_UPD1P)
   }
+#undef ISIRA_UPD1P
   k_pcg_fin1_plain<<<1, kFin, 0, s>>>(grid, rb.partials, init, st);
   HIP_LAUNCH_CHECK();
 }
+// The partials (sum(p), V-hat^T p) are reduced by the next product's finishing dispatch.
 template <typename T>
 void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv, int c,
                                 const T* V, double delta, int init, DevState* st, RedBuf rb,
                                 hipStream_t s) {
   const int grid = stream_grid(n);
-  unsigned* cnt = rb.counters + 5;
+#define ISIRA_UPD2L(CMV)                                                                    \
+  k_pcg_update2_learned<T, CMV><<<grid, kBlock, 0, s>>>(n, y, p, Y, ldv, c, V, delta, init, st, \
+                                                        rb.partials)
   switch (pick_cm(c)) {
-    case 0:
-      k_pcg_update2_learned<T, 0><<<grid, kBlock, 0, s>>>(n, y, p, Y, ldv, c, V, delta, init,
-                                                          st, rb.partials, cnt);
-      break;
-    case 8:
-      k_pcg_update2_learned<T, 8><<<grid, kBlock, 0, s>>>(n, y, p, Y, ldv, c, V, delta, init,
-                                                          st, rb.partials, cnt);
-      break;
-    case 16:
-      k_pcg_update2_learned<T, 16><<<grid, kBlock, 0, s>>>(n, y, p, Y, ldv, c, V, delta, init,
-                                                           st, rb.partials, cnt);
-      break;
-    case 32:
-      k_pcg_update2_learned<T, 32><<<grid, kBlock, 0, s>>>(n, y, p, Y, ldv, c, V, delta, init,
-                                                           st, rb.partials, cnt);
-      break;
-    default:
-      k_pcg_update2_learned<T, 64><<<grid, kBlock, 0, s>>>(n, y, p, Y, ldv, c, V, delta, init,
-                                                           st, rb.partials, cnt);
-      break;
+    ISIRA_CM_CASES(ISIRA_UPD2L)
   }
-  k_pcg_fin2<<<1, kFin, 0, s>>>(c, grid, rb.partials, st);
+#undef ISIRA_UPD2L
   HIP_LAUNCH_CHECK();
 }
 template void launch_pcg_update1_plain<double>(int, double*, double*, const double*,
                                                const double*, const double*, int64_t, int,
-                                               double, int, DevState*, RedBuf, hipStream_t);
+                                               double, int, double, int, DevState*, RedBuf,
+                                               hipStream_t);
 template void launch_pcg_update1_plain<float>(int, float*, float*, const float*, const float*,
-                                              const float*, int64_t, int, double, int,
-                                              DevState*, RedBuf, hipStream_t);
+                                              const float*, int64_t, int, double, int, double,
+                                              int, DevState*, RedBuf, hipStream_t);
 template void launch_pcg_update2_learned<double>(int, const double*, double*, const double*,
                                                  int64_t, int, const double*, double, int,
                                                  DevState*, RedBuf, hipStream_t);
