@@ -47,6 +47,58 @@ def workload(name):
     raise KeyError(name)
 
 
+SPAI_WEIGHTS = os.path.join(HERE, "paper_1710_07080_amd", "weights", "spai_rmat_h16.npy")
+CAL_BYTES = 256 << 20  # size of the calibration copy in --probe runs
+# HBM traffic of the dominant kernel from rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE),
+# with the sources it was measured on; it is reported only while those sources are unchanged.
+TRAFFIC_SUMMARY = os.path.join(HERE, "profiles", "k_spmv_fp64_rmat20_traffic.md")
+KERNEL_SOURCES = [os.path.join(HERE, "paper_1710_07080_amd", "csrc", f)
+                  for f in ("kernels.hip", "internal.h", "api.hip")]
+
+
+def sources_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """Bytes per launch of the FP64 product from the committed counter summary, or None when
+    there is none for this workload or the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    rec = None
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            if line.startswith("traffic_json: "):
+                rec = json.loads(line[len("traffic_json: "):])
+    if not rec or rec.get("workload") != workload or rec.get("sources_digest") != sources_digest():
+        return None
+    return rec
+
+
+def golden(name):
+    """Oracle eigenvalues of the workload (written by tests/golden/make_golden.py), if any."""
+    path = os.path.join(HERE, "tests", "golden", f"{name}_k20.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return np.array(json.load(f)["evals_sorted"])
+
+
+def rel_err(ev, gold):
+    """Per-eigenpair relative eigenvalue error against the oracle (sorted, max and list)."""
+    ev = np.sort(np.asarray(ev))
+    if len(ev) != len(gold):
+        return None
+    e = np.abs(ev - gold) / gold
+    return {"max": float(e.max()), "per_pair": [float(f"{v:.3g}") for v in e]}
+
+
 def spmv_bytes(g, s):
     """Algorithmic bytes of one Laplacian product: row pointers, column indices, weights
     (if any), x read once, the degree vector and y written (s bytes per scalar)."""
@@ -91,6 +143,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="only a 256 MiB device copy (counter calibration) and launches of the "
+                         "FP64 and FP32 products, for rocprofv3 counter runs")
+    ap.add_argument("--probe-reps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -112,6 +168,20 @@ def main():
     t = time.perf_counter()
     ctx = P.Context.from_graph(g)
     log(f"context created ({time.perf_counter() - t:.1f} s): {ctx.info()}")
+    if args.probe:
+        a = torch.ones(CAL_BYTES // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # the calibration copy: CAL_BYTES read, CAL_BYTES written
+        torch.cuda.synchronize()
+        del a, b
+        ms64 = ctx.time_spmv(P.isira.FP64, reps=args.probe_reps)
+        ms32 = ctx.time_spmv(P.isira.FP32, reps=args.probe_reps)
+        print(json.dumps({"probe": args.workload, "calibration_copy_bytes": CAL_BYTES,
+                          "spmv64_ms": ms64, "spmv64_bytes": spmv_bytes(g, 8),
+                          "spmv32_ms": ms32, "spmv32_bytes": spmv_bytes(g, 4),
+                          "reps": args.probe_reps}), flush=True)
+        return
     u0 = gg.start_block(g.n, 4, 1)
     opts = dict(u0=u0, inner_rtol=args.inner_rtol)
     stream = torch.cuda.current_stream()
@@ -142,6 +212,8 @@ def main():
     achieved = b64 / (ms_spmv * 1e-3) / 1e9
     ms_spmv32 = ctx.time_spmv(P.isira.FP32, reps=200)
     b32 = spmv_bytes(g, 4)
+    trec = measured_traffic(args.workload)
+    traffic = trec["bytes_per_launch"] if trec else None
     out = {
         "metric": "time to k eigpairs @ resid 1e-8 (learned+FP32 vs plain FP64); SpMV HBM GB/s",
         "value": sec_per_step,
@@ -170,20 +242,40 @@ def main():
         "wall_s_per_step": wall / args.steps,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_spmv<double, unit weights> (FP64 Laplacian SpMV)",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_spmv<double, ..., TAG=1, ...> main dispatch of the FP64 Laplacian product (isira_time_spmv)",
             "bytes_per_launch": b64, "ms_per_launch": ms_spmv,
         },
         "spmv_fp32": {"ms_per_launch": ms_spmv32, "bytes_per_launch": b32,
                       "achieved_GBs": b32 / (ms_spmv32 * 1e-3) / 1e9},
     }
+    gold = golden(args.workload)
+    if gold is not None:
+        out["rel_eval_err_vs_oracle"] = rel_err(ev, gold)
     if not args.no_variants:
-        ev32, X32, res32, st32 = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], inner_prec=P.isira.FP32, **opts)
-        out["fp32_inner"] = {"s": st32["ms_total"] / 1e3, "converged": st32["n_converged"],
-                             "max_resid": float(np.max(res32)) if len(res32) else None,
-                             "max_rel_eval_diff_vs_fp64": float(np.max(np.abs(np.sort(ev32) - np.sort(ev)) / np.sort(ev)))
-                             if len(ev32) == len(ev) else None}
-        log(f"fp32 inner: {out['fp32_inner']}")
+        # the same solve with FP32 inner solves, Jacobi and learned preconditioner
+        variants = [("fp32_jacobi", P.isira.FP32, P.isira.PC_JACOBI)]
+        if os.path.exists(SPAI_WEIGHTS):
+            from paper_1710_07080_amd import spai_train
+
+            ctx.spai_install(spai_train.load(SPAI_WEIGHTS), sigma=cfg["sigma"])
+            variants.append(("fp32_learned", P.isira.FP32, P.isira.PC_LEARNED))
+        for name, prec, pc in variants:
+            best = None
+            for _ in range(max(1, args.steps)):
+                evv, Xv, resv, stv = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], inner_prec=prec,
+                                               precond=pc, **opts)
+                if best is None or stv["ms_total"] < best[3]["ms_total"]:
+                    best = (evv, Xv, resv, stv)
+            evv, Xv, resv, stv = best
+            row = {"s": stv["ms_total"] / 1e3, "converged": stv["n_converged"],
+                   "outer_total": stv["outer_total"], "inner_total": stv["inner_total"],
+                   "max_resid": float(np.max(resv)) if len(resv) else None,
+                   "speedup_vs_plain_fp64": (st["ms_total"] / stv["ms_total"])}
+            if gold is not None:
+                row["rel_eval_err_vs_oracle"] = rel_err(evv, gold)
+            out[name] = row
+            log(f"{name}: {row}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(g, cfg, st, u0, args.inner_rtol, args.cpu_budget)

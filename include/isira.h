@@ -146,8 +146,11 @@ int isira_solve(isira_ctx* ctx, int32_t k, double sigma, double tol, const isira
 int isira_laplacian_apply(isira_ctx* ctx, const double* x, double* y);
 /* y = L x with FP32 vectors and FP32 weights (the inner-solve operator precision). */
 int isira_laplacian_apply_f32(isira_ctx* ctx, const float* x, float* y);
-/* Time `reps` back-to-back FP64 (prec 0) or FP32 (prec 1) Laplacian products on
- * internal vectors with HIP events on the context stream; *ms_per = average ms. */
+/* Time `reps` back-to-back launches of the main dispatch of the FP64 (prec 0) or FP32
+ * (prec 1) Laplacian product (kernel symbol k_spmv<..., TAG = 1, ...>) on internal vectors,
+ * with HIP events on the context stream; *ms_per = average ms per launch.  The finishing
+ * dispatch of rows split into chunks (a few of the longest rows) is left out, so the
+ * probe's output is not a complete product and is not used. */
 int isira_time_spmv(isira_ctx* ctx, int32_t prec, int32_t reps, double* ms_per);
 
 /* One inner solve of Algorithm 3.2's expansion step: solve the trimmed, shifted,
