@@ -142,3 +142,31 @@ def test_learned_inner_solve(P, prec):
     else:
         Lt = L @ z + delta * V @ (V.T @ z)
         assert np.linalg.norm(Lt - r) <= 5e-3 * np.linalg.norm(r)
+
+
+def test_trained_network_gain(P):
+    """What the trained network gains over the method without it, on a held-out graph: the
+    same eigenpairs (to the oracle's tolerance) with fewer inner iterations than Jacobi.
+    Wall time is printed, not asserted: on these graphs the extra sparse product per inner
+    iteration outweighs the iterations saved."""
+    import os
+
+    from paper_1710_07080_amd import spai_train
+
+    if not os.path.exists(spai_train.DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights")
+    g = gg.rmat(17, 8, seed=4002)  # not among the training seeds 1000..1063
+    ctx = P.Context.from_graph(g)
+    ctx.spai_install(spai_train.load(), sigma=0.0)
+    u0 = gg.start_block(g.n, 4, 1)
+    runs = {}
+    for name, pc in [("jacobi", P.isira.PC_JACOBI), ("learned", P.isira.PC_LEARNED)]:
+        ev, X, res, st = ctx.solve(10, 0.0, 1e-8, u0=u0, inner_prec=P.isira.FP32, precond=pc,
+                                   inner_rtol=1e-4)
+        assert st["n_converged"] == 10 and res.max() < 1e-8
+        runs[name] = (np.sort(ev), st)
+    (ej, sj), (el, sl) = runs["jacobi"], runs["learned"]
+    print(f"inner iterations: Jacobi {sj['inner_total']}, learned {sl['inner_total']}; "
+          f"time: Jacobi {sj['ms_total']:.1f} ms, learned {sl['ms_total']:.1f} ms")
+    assert np.max(np.abs(el - ej) / ej) <= 1e-9
+    assert sl["inner_total"] < 0.97 * sj["inner_total"]
