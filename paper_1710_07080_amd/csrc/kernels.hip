@@ -1150,8 +1150,17 @@ __global__ __launch_bounds__(64) void k_values_fin(int nv, int nblk, const doubl
                                                    double* h) {
   const int v = blockIdx.x;
   if (v >= nv) return;
+  const double* pv = partials + (size_t)v * nblk;
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += 64) s += partials[(size_t)v * nblk + b];
+  int b = threadIdx.x;
+  for (; b + 7 * 64 < nblk; b += 8 * 64) {  // eight loads in flight, summed in a fixed order
+    double t[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = pv[b + i * 64];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += t[i];
+  }
+  for (; b < nblk; b += 64) s += pv[b];
   s = wave_sum(s);
   if (threadIdx.x == 0) h[v] = s;
 }
