@@ -133,6 +133,57 @@ def cpu_baseline(g, cfg, gpu_stats, u0, inner_rtol, budget):
     }
 
 
+def trim_study(ctx, g, cfg, opts, args):
+    """Time to k pairs for several trimmed vertices (Table 2 of the paper compares a
+    degree-1 vertex, vertex 1 and the maximum-degree vertex; Remark 4.1 recommends the
+    last).  Thm 2.4 makes the eigenpairs independent of the choice; the work is not."""
+    d = g.counts() if g.w is None else None
+    if d is None:
+        d = np.zeros(g.n)
+        np.add.at(d, np.repeat(np.arange(g.n), np.diff(g.row_ptr)), g.w)
+    choices = [("max_degree", int(np.argmax(d))), ("min_degree", int(np.argmin(d))), ("vertex_0", 0)]
+    rows, ref = [], None
+    for name, trim in choices:
+        ts = []
+        for _ in range(max(1, args.steps)):
+            ev, X, res, st = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], trim_index=trim, **opts)
+            ts.append(st["ms_total"] / 1e3)
+        ev = np.sort(ev)
+        ref = ev if ref is None else ref
+        row = {"trim": name, "vertex": trim, "degree": float(d[trim]), "s": min(ts),
+               "outer_total": st["outer_total"], "inner_total": st["inner_total"],
+               "converged": st["n_converged"], "max_resid": float(np.max(res)),
+               "max_rel_eval_diff_vs_max_degree": float(np.max(np.abs(ev - ref) / ref))
+               if len(ev) == len(ref) else None}
+        rows.append(row)
+        log(f"trim {row}")
+    print(json.dumps({"study": "trim", "workload": args.workload, "n": g.n, "nnz": g.nnz,
+                      "k": cfg["k"], "tol": cfg["tol"], "rows": rows}), flush=True)
+
+
+def rank_one_study(ctx, g, cfg, opts, args):
+    """Remark 3.1 ablation: with sigma = lambda_1 / 2 (lambda_1 from a sigma = 0 solve), the
+    inner operator with and without (sigma/n) 1-hat 1-hat^T; iterations, time, fallbacks."""
+    ev0, _, _, _ = ctx.solve(cfg["k"], 0.0, cfg["tol"], **opts)
+    sigma = 0.5 * float(np.min(ev0))
+    rows, ref = [], None
+    for name, drop in [("kept", 0), ("dropped", 1)]:
+        ts = []
+        for _ in range(max(1, args.steps)):
+            ev, X, res, st = ctx.solve(cfg["k"], sigma, cfg["tol"], drop_rank_one=drop, **opts)
+            ts.append(st["ms_total"] / 1e3)
+        ev = np.sort(ev)
+        ref = ev if ref is None else ref
+        rows.append({"rank_one_term": name, "s": min(ts), "outer_total": st["outer_total"],
+                     "inner_total": st["inner_total"], "inner_fallbacks": st["inner_fallbacks"],
+                     "converged": st["n_converged"], "max_resid": float(np.max(res)),
+                     "max_rel_eval_diff_vs_kept": float(np.max(np.abs(ev - ref) / ref))
+                     if len(ev) == len(ref) else None})
+        log(f"rank1 {rows[-1]}")
+    print(json.dumps({"study": "rank1", "workload": args.workload, "n": g.n, "sigma": sigma,
+                      "k": cfg["k"], "tol": cfg["tol"], "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +198,11 @@ def main():
                     help="only a 256 MiB device copy (counter calibration) and launches of the "
                          "FP64 and FP32 products, for rocprofv3 counter runs")
     ap.add_argument("--probe-reps", type=int, default=20)
+    ap.add_argument("--study", choices=["trim", "rank1"], default=None,
+                    help="trim: the paper's Table 2 comparison of trimmed vertices (maximum "
+                         "degree, a minimum-degree vertex, vertex 0) on this workload; "
+                         "rank1: sigma = lambda_1 / 2 with and without the (sigma/n) 1 1^T "
+                         "term of the inner operator (Remark 3.1)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -184,6 +240,12 @@ def main():
         return
     u0 = gg.start_block(g.n, 4, 1)
     opts = dict(u0=u0, inner_rtol=args.inner_rtol)
+    if args.study == "trim":
+        trim_study(ctx, g, cfg, opts, args)
+        return
+    if args.study == "rank1":
+        rank_one_study(ctx, g, cfg, opts, args)
+        return
     stream = torch.cuda.current_stream()
     for w in range(args.warmup):
         ev, X, res, st = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], **opts)

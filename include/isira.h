@@ -86,6 +86,9 @@ typedef struct {
   double* capture_z;
   int32_t capture_cap;
   int32_t* capture_count;
+  int32_t drop_rank_one;  /* 1: leave the rank-one term (sigma/n) 1-hat 1-hat^T out of the inner
+                             operator (the simplification Remark 3.1 allows for large n);
+                             default 0 keeps the exact operator of eq. (2.15) */
 } isira_options;
 
 #define ISIRA_STATS_MAX 64

@@ -95,13 +95,15 @@ def enlarge(zhat: np.ndarray, i: int, n: int) -> np.ndarray:
 
 
 def trimmed_operator(Lhat: sp.csr_matrix, n: int, sigma: float, delta: float,
-                     Vhat: np.ndarray) -> Callable[[np.ndarray], np.ndarray]:
+                     Vhat: np.ndarray, rank_one: bool = True) -> Callable[[np.ndarray], np.ndarray]:
     """K-hat of eq. (2.15):  (L-hat - sigma I) + (sigma/n) 1 1^T + delta V-hat V-hat^T,
-    acting on (n-1)-vectors.  With V empty and sigma = 0 this is eq. (2.4)."""
+    acting on (n-1)-vectors.  With V empty and sigma = 0 this is eq. (2.4).
+    ``rank_one=False`` leaves out the (sigma/n) 1 1^T term, as Remark 3.1 allows."""
 
     def apply(x: np.ndarray) -> np.ndarray:
         y = Lhat @ x - sigma * x
-        y = y + (sigma / n) * np.sum(x) * np.ones_like(x)
+        if rank_one:
+            y = y + (sigma / n) * np.sum(x) * np.ones_like(x)
         if Vhat.shape[1] > 0:
             y = y + delta * (Vhat @ (Vhat.T @ x))
         return y
@@ -167,7 +169,8 @@ def pcg(apply_A, b: np.ndarray, apply_P, rtol: float, maxit: int):
 
 def inner_solve(L: sp.csr_matrix, d: np.ndarray, r: np.ndarray, i: int, sigma: float,
                 delta: float, V: np.ndarray, rtol: float, maxit: int,
-                apply_minv_hat: Optional[Callable] = None, Lhat: Optional[sp.csr_matrix] = None):
+                apply_minv_hat: Optional[Callable] = None, Lhat: Optional[sp.csr_matrix] = None,
+                rank_one: bool = True):
     """Subspace expansion of Algorithm 3.2: (i) solve the trimmed system (eq. (2.4) when
     V is empty and sigma = 0, eq. (2.15) otherwise) with the Remark 3.2 preconditioner,
     (ii) enlarge by eq. (2.5).  The right-hand side r must be orthogonal to 1 (Lemma 2.1).
@@ -178,7 +181,7 @@ def inner_solve(L: sp.csr_matrix, d: np.ndarray, r: np.ndarray, i: int, sigma: f
         Lhat = trimmed_matrix(L, i)
     Vhat = trim(V, i)
     rhat = trim(r, i)
-    A = trimmed_operator(Lhat, n, sigma, delta, Vhat)
+    A = trimmed_operator(Lhat, n, sigma, delta, Vhat, rank_one)
     if apply_minv_hat is None:
         P = jacobi_smw_preconditioner(trim(d, i), sigma, delta, Vhat)
     else:
@@ -253,7 +256,7 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
           q: Optional[int] = None, inner_rtol: float = 1e-12, max_inner: int = 5000,
           max_outer: int = 100000, trim: Optional[int] = None, delta: Optional[float] = None,
           seed: int = 12345, apply_minv_hat_factory: Optional[Callable] = None,
-          time_budget: Optional[float] = None) -> IsiraResult:
+          time_budget: Optional[float] = None, rank_one: bool = True) -> IsiraResult:
     """Algorithm 3.2 with the readings listed in the module docstring.
 
     k: number of wanted eigenpairs (d in Algorithm 3.2); U0: n-by-k0 start block, whose
@@ -261,7 +264,8 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
     subspace dimension (defaults q = k + 10, m = 2 q).
     ``apply_minv_hat_factory(i, sigma)`` may return an SPD approximate inverse of
     L-hat - sigma I on (n-1)-vectors to replace the Jacobi preconditioner.
-    ``time_budget`` (seconds) stops the loop early; the partial result is returned."""
+    ``time_budget`` (seconds) stops the loop early; the partial result is returned.
+    ``rank_one=False`` drops (sigma/n) 1 1^T from the inner operator (Remark 3.1)."""
     import time as _time
 
     t_start = _time.perf_counter()
@@ -345,7 +349,8 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
                 H = np.diag(theta[:q])
             # subspace expansion: trimmed (deflated) inner solve and enlargement
             rr = r - np.mean(r)  # Lemma 2.1: the right-hand side must be orthogonal to 1
-            zstar, its, _ = inner_solve(L, dvec, rr, i, sigma, dl, V, inner_rtol, max_inner, minv_hat, Lhat)
+            zstar, its, _ = inner_solve(L, dvec, rr, i, sigma, dl, V, inner_rtol, max_inner, minv_hat, Lhat,
+                                        rank_one)
             inner_here += its
             # orthonormalize against U and V (and 1/sqrt(n))
             Q = np.column_stack([U, V, ones])

@@ -130,7 +130,57 @@ struct isira_ctx {
   spai::SpaiWork spw;
 };
 
-// SpMV work units from the relabelled CSR (rows by decreasing length): rows longer than
+// Power-law test on the degree-sorted labels: at least a quarter of the gathers hit the
+// kHubX64 highest-degree vertices (the hub-cached product shape is then used).
+static bool power_law(int64_t n, const int32_t* rp, const int32_t* col,
+                      const std::vector<int32_t>& rank) {
+  if (n <= 4 * (int64_t)kHubX64) return false;
+  int64_t hits = 0;
+  const int64_t nnz = rp[n];
+  for (int64_t j = 0; j < nnz; ++j) hits += rank[col[j]] < kHubX64;
+  return (double)hits >= 0.25 * (double)nnz;
+}
+
+// Reverse Cuthill-McKee order of a connected graph: breadth-first search from a
+// pseudo-peripheral vertex (two sweeps starting at a minimum-degree vertex), neighbours
+// taken in increasing degree, and the visiting order reversed.  perm[new] = old label.
+static void rcm_order(int64_t n, const int32_t* rp, const int32_t* col,
+                      const std::vector<int32_t>& deg, std::vector<int32_t>& perm,
+                      std::vector<int32_t>& iperm) {
+  std::vector<int32_t> order(n), level(n);
+  auto bfs = [&](int32_t start, bool sorted) {
+    std::fill(level.begin(), level.end(), -1);
+    int64_t head = 0, tail = 0;
+    order[tail++] = start;
+    level[start] = 0;
+    std::vector<int32_t> nb;
+    while (head < tail) {
+      const int32_t v = order[head++];
+      nb.clear();
+      for (int32_t j = rp[v]; j < rp[v + 1]; ++j)
+        if (level[col[j]] < 0) {
+          level[col[j]] = level[v] + 1;
+          nb.push_back(col[j]);
+        }
+      if (sorted)
+        std::stable_sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+      for (int32_t u : nb) order[tail++] = u;
+    }
+    return order[tail - 1];  // a vertex of the last level
+  };
+  int32_t start = 0;
+  for (int64_t i = 1; i < n; ++i)
+    if (deg[i] < deg[start]) start = (int32_t)i;
+  for (int sweep = 0; sweep < 2; ++sweep) start = bfs(start, false);
+  bfs(start, true);
+  for (int64_t i = 0; i < n; ++i) {
+    perm[i] = order[n - 1 - i];
+    iperm[perm[i]] = (int32_t)i;
+  }
+}
+
+// SpMV work units from the relabelled CSR (rows by decreasing length, or in reverse
+// Cuthill-McKee order when no row is longer than a stream unit): rows longer than
 // the unit size are cut into chunks; the remaining rows are packed greedily, in order, into
 // stream units of at most unit-size nonzeros and a row limit.  A stream unit sums each row
 // with G lanes, G the smallest power of two >= (longest row) / 8, capped at 64.  Graphs
@@ -167,10 +217,10 @@ static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp,
   }
   while (row < n) {
     const int r0 = row;
-    const int lmax = rp[row + 1] - rp[row];
-    int nnz = 0;
+    int lmax = 0, nnz = 0;
     while (row < n && row - r0 < urows && nnz + (rp[row + 1] - rp[row]) <= unnz) {
       nnz += rp[row + 1] - rp[row];
+      lmax = std::max(lmax, rp[row + 1] - rp[row]);
       ++row;
     }
     int G = 1;
@@ -354,6 +404,10 @@ extern "C" int isira_create(isira_ctx** out, int64_t n, int64_t nnz, const int32
       ctx->iperm[i] = (int32_t)pos;
     }
   }
+  // Graphs whose gathers do not concentrate on a few hub labels (and whose rows all fit one
+  // stream unit) are relabelled in reverse Cuthill-McKee order instead, so that the x
+  // entries a unit gathers sit close together in memory.
+  if (maxc <= kUnitNnz && !power_law(n, row_ptr, col, ctx->iperm)) rcm_order(n, row_ptr, col, cnt, ctx->perm, ctx->iperm);
   std::vector<int32_t> rp2(n + 1), col2(nnz);
   rp2[0] = 0;
   for (int64_t r = 0; r < n; ++r) rp2[r + 1] = rp2[r] + cnt[ctx->perm[r]];
@@ -592,6 +646,7 @@ struct InnerCfg {
   double sigma, delta, rtol;
   int trim;     // internal index
   int maxit, check_every;
+  bool rank_one = true;  // the (sigma/n) 1-hat 1-hat^T term of eq. (2.15) in the operator
 };
 
 // Solve the trimmed shifted deflated system (2.15) for right-hand side r64 (internal order,
@@ -646,8 +701,8 @@ void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
   a.fold_c = nc;
   a.fold_nblk = stream_grid(n);
   a.fold_partials = c->rb.partials;
-  a.fold_sig_over_n = cfg.sigma / (double)n;
-  const double sig_over_n = cfg.sigma / (double)n;
+  const double sig_over_n = cfg.rank_one ? cfg.sigma / (double)n : 0.0;
+  a.fold_sig_over_n = sig_over_n;
   // one iteration: [product] then the residual update and the preconditioned direction;
   // the first call (init) has no product and starts from x = 0, r = rhs
   for (int it = 0; it < iters; ++it) {
@@ -783,6 +838,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
   cfg.trim = trim;
   cfg.maxit = opt.max_inner > 0 ? opt.max_inner : 1000;
   cfg.check_every = opt.check_every > 0 ? opt.check_every : 8;
+  cfg.rank_one = opt.drop_rank_one == 0;
   const int max_outer = opt.max_outer > 0 ? opt.max_outer : 20000;
   // Jacobi inverse diagonal (Remark 3.2) in both precisions
   launch_dinv<double>(n, c->deg, sigma, trim, c->dinv64, s);

@@ -21,10 +21,16 @@ constexpr int kUnitNnz = 2048;        // nonzeros per SpMV unit (stream unit or 
 constexpr int kUnitRows = 256;        // rows per stream unit at most
 // hub-cached shape for power-law graphs (one 1024-thread workgroup per CU)
 constexpr int kHubThreads = 1024;
-constexpr int kHubUnitNnz = 8192;
-constexpr int kHubUnitRows = 2048;
-constexpr int kHubX64 = 8192;         // FP64 x entries staged in LDS (64 KB)
-constexpr int kHubX32 = 24576;        // FP32 x entries staged in LDS (96 KB)
+#ifndef ISIRA_HUB_UNNZ
+#define ISIRA_HUB_UNNZ 8192
+#define ISIRA_HUB_UROWS 2048
+#define ISIRA_HUB_X64 8192
+#define ISIRA_HUB_X32 24576
+#endif
+constexpr int kHubUnitNnz = ISIRA_HUB_UNNZ;
+constexpr int kHubUnitRows = ISIRA_HUB_UROWS;
+constexpr int kHubX64 = ISIRA_HUB_X64;  // FP64 x entries staged in LDS
+constexpr int kHubX32 = ISIRA_HUB_X32;  // FP32 x entries staged in LDS
 constexpr int kHubGrid = 256;
 constexpr int kMaxC = ISIRA_MAX_K;     // deflation columns in the inner solve
 constexpr int kTile = 512;             // rows per tile of the column-dot kernels

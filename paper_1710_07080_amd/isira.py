@@ -48,6 +48,7 @@ class Options(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("u0", _c_double_p), ("check_every", ctypes.c_int32),
         ("verbose", ctypes.c_int32), ("capture_r", _c_double_p), ("capture_z", _c_double_p),
         ("capture_cap", ctypes.c_int32), ("capture_count", _c_int32_p),
+        ("drop_rank_one", ctypes.c_int32),
     ]
 
 

@@ -235,6 +235,40 @@ def test_solve_rmat14_vs_oracle(P):
     _compare(res_o, ev, X.cpu().numpy(), resid, g, 1e-9)
 
 
+@pytest.mark.parametrize("which", ["max_degree", "min_degree", "label0"])
+def test_solve_trim_index_choices(P, which):
+    """Thm 2.4: the enlarged inner solution does not depend on the trimmed vertex, so every
+    trim choice (the paper's Table 2 compares a degree-1 vertex, vertex 1 and the
+    maximum-degree vertex) reaches the same eigenpairs; the oracle runs with the same one."""
+    g = gg.rmat(13, 8, seed=12)
+    d = O.degrees(g)
+    trim = {"max_degree": int(np.argmax(d)), "min_degree": int(np.argmin(d)), "label0": 0}[which]
+    ctx = P.Context.from_graph(g)
+    U0 = gg.start_block(g.n, 4, 3)
+    ev, X, resid, st = ctx.solve(10, 0.0, 1e-9, u0=U0, trim_index=trim)
+    assert st["trim_index"] == trim
+    res_o = O.isira(g, 10, 0.0, 1e-9, U0, inner_rtol=1e-6, trim=trim)
+    _compare(res_o, ev, X.cpu().numpy(), resid, g, 1e-9)
+
+
+def test_solve_without_rank_one_term(P):
+    """Remark 3.1: with sigma > 0 the inner operator may leave out (sigma/n) 1-hat 1-hat^T;
+    the GPU with that option matches the oracle run the same way, and both reach the
+    eigenpairs of the exact method."""
+    g = gg.rmat(11, 8, seed=15)
+    d = O.degrees(g)
+    i = O.trim_index(d)
+    Lhat = O.trimmed_matrix(O.laplacian(g), i).toarray()
+    sigma = 0.5 * np.linalg.eigvalsh(Lhat).min()  # keeps L-hat - sigma I positive definite
+    ctx = P.Context.from_graph(g)
+    U0 = gg.start_block(g.n, 4, 5)
+    ev, X, resid, st = ctx.solve(8, sigma, 1e-9, u0=U0, drop_rank_one=1)
+    res_o = O.isira(g, 8, sigma, 1e-9, U0, inner_rtol=1e-6, rank_one=False)
+    _compare(res_o, ev, X.cpu().numpy(), resid, g, 1e-9)
+    ev_exact, _, _, _ = ctx.solve(8, sigma, 1e-9, u0=U0)
+    assert np.allclose(np.sort(ev), np.sort(ev_exact), rtol=1e-9, atol=0)
+
+
 def test_solve_errors(P):
     g = gg.grid2d(8, 8)
     ctx = P.Context.from_graph(g)

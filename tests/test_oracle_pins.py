@@ -186,6 +186,37 @@ def test_inner_solve_shifted_deflated(sigma_frac, c):
         assert np.allclose(z, ref, atol=1e-9 * np.abs(ref).max())
 
 
+def test_trimmed_operator_without_rank_one_term():
+    # Remark 3.1: dropping (sigma/n) 1 1^T leaves (L-hat - sigma I) + delta V-hat V-hat^T, the
+    # trimmed principal submatrix of L + delta V V^T - sigma I built from the edge list;
+    # at sigma = 0 both operators coincide.
+    g = gg.random_connected(50, 90, seed=14, weights=(0.5, 1.5))
+    Ld = dense_laplacian_from_edges(g)
+    lam, X = np.linalg.eigh(Ld)
+    V = X[:, 1:3]
+    delta = 2 * Ld.diagonal().max()
+    i = O.trim_index(O.degrees(g))
+    keep = [t for t in range(g.n) if t != i]
+    Lhat = O.trimmed_matrix(O.laplacian(g), i)
+    Vhat = V[keep]
+    x = np.random.default_rng(3).standard_normal(g.n - 1)
+    sigma = 0.3 * lam[1]
+    dense = (Ld + delta * V @ V.T - sigma * np.eye(g.n))[np.ix_(keep, keep)]
+    y = O.trimmed_operator(Lhat, g.n, sigma, delta, Vhat, rank_one=False)(x)
+    assert np.allclose(y, dense @ x, atol=1e-11 * np.abs(dense @ x).max())
+    y1 = O.trimmed_operator(Lhat, g.n, sigma, delta, Vhat)(x)
+    assert np.allclose(y1 - y, (sigma / g.n) * x.sum(), atol=1e-11 * np.abs(y).max())
+    y0 = O.trimmed_operator(Lhat, g.n, 0.0, delta, Vhat, rank_one=False)(x)
+    assert np.array_equal(y0, O.trimmed_operator(Lhat, g.n, 0.0, delta, Vhat)(x))
+    # the inner solve then solves that trimmed system (SPD here: sigma < its smallest eigenvalue)
+    assert np.linalg.eigvalsh(dense).min() > 0
+    r = _rhs_perp_one(g.n, 4)
+    z, its, rel = O.inner_solve(O.laplacian(g), O.degrees(g), r, i, sigma, delta, V, 1e-14, 5000,
+                                rank_one=False)
+    zhat = np.linalg.solve(dense, r[keep])
+    assert np.allclose(z, O.enlarge(zhat, i, g.n), atol=1e-9 * np.abs(zhat).max())
+
+
 def test_trimmed_operator_inertia():
     # K-hat is congruent to a Schur complement of J (L~ - sigma I) J^T (proof of Theorem
     # 2.8): it is positive definite iff sigma < lambda_{c+1}, with one negative
