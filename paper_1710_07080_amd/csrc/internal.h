@@ -17,8 +17,12 @@ constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 // max workgroups of grid-stride streaming kernels (compile-time tunable)
 constexpr int kStreamGrid = ISIRA_STREAM_GRID;
 constexpr int kSpmvGrid = 2048;       // max workgroups of the persistent SpMV grid
-constexpr int kUnitNnz = 2048;        // nonzeros per SpMV unit (stream unit or long-row chunk)
-constexpr int kUnitRows = 256;        // rows per stream unit at most
+#ifndef ISIRA_UNIT_NNZ
+#define ISIRA_UNIT_NNZ 2048
+#define ISIRA_UNIT_ROWS 512
+#endif
+constexpr int kUnitNnz = ISIRA_UNIT_NNZ;    // nonzeros per SpMV unit (stream unit or long-row chunk)
+constexpr int kUnitRows = ISIRA_UNIT_ROWS;  // rows per stream unit at most
 // hub-cached shape for power-law graphs (one 1024-thread workgroup per CU)
 constexpr int kHubThreads = 1024;
 #ifndef ISIRA_HUB_UNNZ
@@ -133,8 +137,8 @@ struct SpmvArgs {
   int32_t check_done;  // return at once when st->done
   // PCG product (red 1) only: the deflation term delta V-hat (V-hat^T p) and the rank-one
   // term (sigma/n) 1-hat (1-hat^T p) of the operator are applied by the residual update;
-  // the finishing dispatch first reduces the partials of the p-update (fold_nblk workgroups:
-  // sum(p), then V-hat^T p) into st->sump, st->t1, and folds delta ||t1||^2 and
+  // the finishing dispatch first reduces the p-update's partial sums of p (fold_nblk
+  // workgroups) into st->sump, and folds delta ||st->t1(0:fold_c)||^2 and
   // fold_sig_over_n * sump^2 into p^T q.
   int32_t fold_c;
   int32_t fold_nblk;

@@ -504,13 +504,12 @@ __global__ __launch_bounds__(kFin) void k_spmv_fin(SpmvArgs<T> a, SplitInfo sp, 
                                                    const double* partials) {
   if (a.check_done && a.st->done) return;
   __shared__ double sh_t[kMaxC];
-  __shared__ double fold[1 + kMaxC];
+  __shared__ double fold[1];
   const int tid = threadIdx.x;
   if (a.fold_partials) {
-    // sum(p) and V-hat^T p of the p-update, in a fixed order
-    final_reduce(a.fold_partials, 1 + a.fold_c, a.fold_nblk, fold);
+    // sum(p) of the p-update, in a fixed order (V-hat^T p is already in st->t1)
+    final_reduce(a.fold_partials, 1, a.fold_nblk, fold);
     if (tid == 0) a.st->sump = fold[0];
-    for (int j = tid; j < a.fold_c; j += blockDim.x) a.st->t1[j] = fold[1 + j];
   }
   const double* tv = a.tvec ? a.tvec : (a.st ? a.st->t1 : nullptr);
   for (int j = tid; j < a.c; j += blockDim.x) sh_t[j] = tv[j];
@@ -532,7 +531,7 @@ __global__ __launch_bounds__(kFin) void k_spmv_fin(SpmvArgs<T> a, SplitInfo sp, 
       double pq = tot;
       if (a.fold_partials) {
         double tt = 0.0;
-        for (int j = 0; j < a.fold_c; ++j) tt += fold[1 + j] * fold[1 + j];
+        for (int j = 0; j < a.fold_c; ++j) tt += st->t1[j] * st->t1[j];
         pq += a.delta * tt + a.fold_sig_over_n * fold[0] * fold[0];
       }
       st->pq = pq;
@@ -658,6 +657,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update1(int n, T* __restrict__ x
   write_partials<NV>(acc, 2 + c, partials);
 }
 
+// V-hat^T p of the next direction without a pass over V-hat: with z = (I - delta M V-hat
+// G^-1 V-hat^T) M r (eq. (3.5)) and G = I + delta V-hat^T M V-hat, V-hat^T z = G^-1 V-hat^T M r
+// = g, so V-hat^T (z + beta p) = g + beta V-hat^T p.  Called by the workgroup that has just
+// set beta (thread 0) and holds g in LDS; nothing is left to do once the iteration stopped.
+__device__ void next_t1(int c, const double* g, int init, DevState* st) {
+  __syncthreads();
+  if (st->done) return;
+  const double beta = init ? 0.0 : st->beta;
+  for (int j = threadIdx.x; j < c; j += blockDim.x) st->t1[j] = g[j] + beta * st->t1[j];
+}
+
 // Reduces the partials of k_pcg_update1 (one workgroup), forms g = G^-1 t2 and
 // rho = r^T M^-1 r - delta t2^T g, tests convergence and sets beta.
 __global__ __launch_bounds__(kFin) void k_pcg_fin1(int c, int nblk, const double* partials,
@@ -712,9 +722,10 @@ __global__ __launch_bounds__(kFin) void k_pcg_fin1(int c, int nblk, const double
       }
     }
   }
+  next_t1(c, gsh, init, st);
 }
 
-// z = M^-1 (r - delta V-hat g); p = z + beta p; partials V-hat^T p and sum(p).
+// z = M^-1 (r - delta V-hat g); p = z + beta p; partial sum(p).
 template <typename T, int CM>
 __global__ __launch_bounds__(kBlock) void k_pcg_update2(int n, const T* __restrict__ r,
                                                         T* __restrict__ p,
@@ -723,13 +734,10 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update2(int n, const T* __restri
                                                         int c, double delta, int init,
                                                         DevState* st, double* partials) {
   if (st->done) return;
-  constexpr int NV = 1 + (CM > 0 ? CM : 0);
   __shared__ T sg[CM > 0 ? CM : 1];
   for (int j = threadIdx.x; j < CM; j += kBlock) sg[j] = j < c ? (T)st->g[j] : T(0);
   __syncthreads();
-  double acc[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  double acc[1] = {0.0};
   const T beta = init ? T(0) : (T)st->beta;
   const T dl = (T)delta;
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
@@ -743,10 +751,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update2(int n, const T* __restri
     const T pn = init ? z : z + beta * p[l];
     p[l] = pn;
     acc[0] += (double)pn;
-#pragma unroll
-    for (int j = 0; j < CM; ++j) acc[1 + j] += (double)vreg[j] * (double)pn;
   }
-  write_partials<NV>(acc, 1 + c, partials);
+  write_partials<1>(acc, 1, partials);
 }
 
 
@@ -898,6 +904,7 @@ __global__ void k_spai_finish_rho(int c, const double* Ginv, double delta, int i
       st->rho = rho_new;
     }
   }
+  next_t1(c, st->g, init, st);
 }
 
 void launch_spai_finish_rho(int c, const double* Ginv, double delta, int init, DevState* st,
@@ -906,27 +913,22 @@ void launch_spai_finish_rho(int c, const double* Ginv, double delta, int init, D
   HIP_LAUNCH_CHECK();
 }
 
-// z = y - delta Y g; p = z + beta p; partials V-hat^T p and sum(p).
+// z = y - delta Y g; p = z + beta p; partial sum(p).
 template <typename T, int CM>
 __global__ __launch_bounds__(kBlock) void k_pcg_update2_learned(
     int n, const T* __restrict__ y, T* __restrict__ p, const T* __restrict__ Y, int64_t ldv,
     int c, const T* __restrict__ V, double delta, int init, DevState* st, double* partials) {
   if (st->done) return;
-  constexpr int NV = 1 + (CM > 0 ? CM : 0);
   __shared__ T sg[CM > 0 ? CM : 1];
   for (int j = threadIdx.x; j < CM; j += kBlock) sg[j] = j < c ? (T)st->g[j] : T(0);
   __syncthreads();
-  double acc[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  double acc[1] = {0.0};
   const T beta = init ? T(0) : (T)st->beta;
   const T dl = (T)delta;
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
-    T yreg[CM > 0 ? CM : 1], vreg[CM > 0 ? CM : 1];
+    T yreg[CM > 0 ? CM : 1];
 #pragma unroll
     for (int j = 0; j < CM; ++j) yreg[j] = Y[l + (int64_t)j * ldv];
-#pragma unroll
-    for (int j = 0; j < CM; ++j) vreg[j] = V[l + (int64_t)j * ldv];
     T s = T(0);
 #pragma unroll
     for (int j = 0; j < CM; ++j) s += yreg[j] * sg[j];
@@ -934,10 +936,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update2_learned(
     const T pn = init ? z : z + beta * p[l];
     p[l] = pn;
     acc[0] += (double)pn;
-#pragma unroll
-    for (int j = 0; j < CM; ++j) acc[1 + j] += (double)vreg[j] * (double)pn;
   }
-  write_partials<NV>(acc, 1 + c, partials);
+  write_partials<1>(acc, 1, partials);
 }
 
 template <typename T>
