@@ -12,7 +12,8 @@ for the small Rayleigh-Ritz problem.
 
 Readings of points the paper leaves open (each also listed in the design notes):
   * inner solver = PCG on the SPD trimmed system, stopped at ||r|| <= rtol ||b||;
-  * the shift sigma is fixed for the whole solve (0 <= sigma < lambda_1);
+  * the shift sigma is fixed for the whole solve (0 <= sigma < lambda_1); the purge step's
+    moving shift is an option (sigma <- theta_2 after each lock, inner solver MINRES);
   * the rank-one term (sigma/n) 1 1^T of eq. (2.15) is kept in the operator and
     dropped from the preconditioner (Remark 3.1 applied to the preconditioner only);
   * W is carried incrementally (one new column per expansion);
@@ -167,15 +168,67 @@ def pcg(apply_A, b: np.ndarray, apply_P, rtol: float, maxit: int):
     return x, it, rel
 
 
+def minres(apply_A, b: np.ndarray, apply_P, rtol: float, maxit: int):
+    """Preconditioned MINRES (Paige and Saunders, SIAM J. Numer. Anal. 12 (1975); the
+    preconditioned form as in Elman, Silvester and Wathen's book) for a symmetric, possibly
+    indefinite A with an SPD preconditioner P, from x0 = 0.  Each step extends the Lanczos
+    basis of the P-inner product by one vector, updates the QR factorization of the
+    tridiagonal Lanczos matrix by one Givens rotation, and updates x along the new
+    direction; eta is the P^{-1}-norm of the residual, recursively updated.  Stopped when
+    |eta| <= rtol * eta_0.  Returns (x, iterations, |eta| / eta_0)."""
+    x = np.zeros_like(b)
+    v_old = np.zeros_like(b)
+    v = b.copy()
+    z = apply_P(v)
+    gamma = math.sqrt(max(0.0, v @ z))
+    if gamma == 0.0:
+        return x, 0, 0.0
+    eta0 = eta = gamma
+    gamma_old = 1.0
+    c_old = c = 1.0
+    s_old = s = 0.0
+    w_old = np.zeros_like(b)
+    w = np.zeros_like(b)
+    it = 0
+    rel = 1.0
+    while it < maxit:
+        it += 1
+        z = z / gamma
+        Az = apply_A(z)
+        dlt = Az @ z
+        v_new = Az - (dlt / gamma) * v - (gamma / gamma_old) * v_old
+        z_new = apply_P(v_new)
+        gamma_new = math.sqrt(max(0.0, v_new @ z_new))
+        a0 = c * dlt - c_old * s * gamma
+        a1 = math.hypot(a0, gamma_new)
+        a2 = s * dlt + c_old * c * gamma
+        a3 = s_old * gamma
+        c_old, s_old = c, s
+        c, s = a0 / a1, gamma_new / a1
+        w_new = (z - a3 * w_old - a2 * w) / a1
+        x = x + (c * eta) * w_new
+        eta = -s * eta
+        rel = abs(eta) / eta0
+        v_old, v = v, v_new
+        w_old, w = w, w_new
+        gamma_old, gamma = gamma, gamma_new
+        z = z_new
+        if rel <= rtol or gamma == 0.0:
+            break
+    return x, it, rel
+
+
 def inner_solve(L: sp.csr_matrix, d: np.ndarray, r: np.ndarray, i: int, sigma: float,
                 delta: float, V: np.ndarray, rtol: float, maxit: int,
                 apply_minv_hat: Optional[Callable] = None, Lhat: Optional[sp.csr_matrix] = None,
-                rank_one: bool = True):
+                rank_one: bool = True, solver: str = "pcg"):
     """Subspace expansion of Algorithm 3.2: (i) solve the trimmed system (eq. (2.4) when
     V is empty and sigma = 0, eq. (2.15) otherwise) with the Remark 3.2 preconditioner,
     (ii) enlarge by eq. (2.5).  The right-hand side r must be orthogonal to 1 (Lemma 2.1).
     ``apply_minv_hat`` replaces the Jacobi M^{-1} by another SPD approximate inverse of
-    L-hat - sigma I acting on (n-1)-vectors.  Returns (z*, iterations, relative residual)."""
+    L-hat - sigma I acting on (n-1)-vectors.  ``solver="minres"`` solves with preconditioned
+    MINRES instead of PCG, for a shift that makes the trimmed system indefinite (Thm 2.8).
+    Returns (z*, iterations, relative residual)."""
     n = L.shape[0]
     if Lhat is None:
         Lhat = trimmed_matrix(L, i)
@@ -186,7 +239,10 @@ def inner_solve(L: sp.csr_matrix, d: np.ndarray, r: np.ndarray, i: int, sigma: f
         P = jacobi_smw_preconditioner(trim(d, i), sigma, delta, Vhat)
     else:
         P = smw_preconditioner(apply_minv_hat, delta, Vhat)
-    zhat, its, rel = pcg(A, rhat, P, rtol, maxit)
+    if solver == "minres":
+        zhat, its, rel = minres(A, rhat, P, rtol, maxit)
+    else:
+        zhat, its, rel = pcg(A, rhat, P, rtol, maxit)
     return enlarge(zhat, i, n), its, rel
 
 
@@ -256,7 +312,8 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
           q: Optional[int] = None, inner_rtol: float = 1e-12, max_inner: int = 5000,
           max_outer: int = 100000, trim: Optional[int] = None, delta: Optional[float] = None,
           seed: int = 12345, apply_minv_hat_factory: Optional[Callable] = None,
-          time_budget: Optional[float] = None, rank_one: bool = True) -> IsiraResult:
+          time_budget: Optional[float] = None, rank_one: bool = True,
+          moving_shift: bool = False) -> IsiraResult:
     """Algorithm 3.2 with the readings listed in the module docstring.
 
     k: number of wanted eigenpairs (d in Algorithm 3.2); U0: n-by-k0 start block, whose
@@ -265,7 +322,11 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
     ``apply_minv_hat_factory(i, sigma)`` may return an SPD approximate inverse of
     L-hat - sigma I on (n-1)-vectors to replace the Jacobi preconditioner.
     ``time_budget`` (seconds) stops the loop early; the partial result is returned.
-    ``rank_one=False`` drops (sigma/n) 1 1^T from the inner operator (Remark 3.1)."""
+    ``rank_one=False`` drops (sigma/n) 1 1^T from the inner operator (Remark 3.1).
+    ``moving_shift=True`` follows the purge step's "move sigma to about theta_2": after each
+    locked pair sigma becomes the smallest remaining Ritz value, capped at half the minimum
+    degree (the Jacobi part of the preconditioner stays SPD); the trimmed system may then be
+    indefinite, so every inner solve of such a run uses preconditioned MINRES."""
     import time as _time
 
     t_start = _time.perf_counter()
@@ -278,6 +339,9 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
         raise ValueError("need 1 <= k <= q < m")
     i = trim_index(dvec) if trim is None else int(trim)
     dl = deflation_shift(dvec) if delta is None else float(delta)
+    sigma_cap = 0.5 * float(np.min(dvec))
+    if moving_shift and apply_minv_hat_factory is not None:
+        raise ValueError("a preconditioner built for one shift cannot follow a moving shift")
     ones = np.ones(n) / math.sqrt(n)
     minv_hat = None if apply_minv_hat_factory is None else apply_minv_hat_factory(i, sigma)
     Lhat = trimmed_matrix(L, i)
@@ -333,6 +397,8 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
                     W = W @ S[:, 1:]
                     H = np.diag(theta[1:])
                     V = np.column_stack([V, y])
+                    if moving_shift and len(theta) > 1:
+                        sigma = min(float(theta[1]), sigma_cap)
                     if U.shape[1] == 0:
                         U, W, H, draws, breakdowns = _reseed(L, V, dl, ones, n, seed, draws, breakdowns)
                     break
@@ -350,7 +416,7 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
             # subspace expansion: trimmed (deflated) inner solve and enlargement
             rr = r - np.mean(r)  # Lemma 2.1: the right-hand side must be orthogonal to 1
             zstar, its, _ = inner_solve(L, dvec, rr, i, sigma, dl, V, inner_rtol, max_inner, minv_hat, Lhat,
-                                        rank_one)
+                                        rank_one, "minres" if moving_shift else "pcg")
             inner_here += its
             # orthonormalize against U and V (and 1/sqrt(n))
             Q = np.column_stack([U, V, ones])

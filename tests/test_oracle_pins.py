@@ -349,3 +349,74 @@ def test_isira_spider_multiplicity():
     _check_result(g, res, k, 1e-10, lam[1:k + 1], rel=1e-9)
     first = 2 - 2 * np.cos(np.pi / (2 * l + 1))
     assert np.sum(np.abs(res.evals - first) < 1e-9) >= p - 1
+
+
+
+def _minres_norm_check(K, b, P, x, rel):
+    # eta is the P-norm of the residual (P the preconditioner, the inverse of M)
+    r = b - K @ x
+    true = math.sqrt(r @ (P @ r)) / math.sqrt(b @ (P @ b))
+    assert abs(true - rel) <= 1e-6 * max(true, 1e-300) + 1e-13
+
+
+def test_minres_spd_and_indefinite():
+    # MINRES (Paige-Saunders, preconditioned): on the SPD trimmed Laplacian and on an
+    # indefinite shift of it, the iterate converges to the unique solution, and the
+    # recursively updated residual norm equals the true P-norm of b - K x.
+    g = gg.random_connected(80, 160, seed=21, weights=(0.5, 1.5))
+    L = O.laplacian(g).toarray()
+    d = L.diagonal()
+    i = int(np.argmax(d))
+    keep = [t for t in range(g.n) if t != i]
+    Lh = L[np.ix_(keep, keep)]
+    mu = np.linalg.eigvalsh(Lh)
+    b = np.random.default_rng(5).standard_normal(g.n - 1)
+    for sigma in [0.0, 0.5 * mu[0], 0.5 * (mu[2] + mu[3])]:  # SPD, SPD, 3 negative eigenvalues
+        K = Lh - sigma * np.eye(g.n - 1)
+        P = np.diag(1.0 / (d[keep] - sigma))
+        x, its, rel = O.minres(lambda v: K @ v, b, lambda v: P @ v, 1e-12, 2000)
+        assert rel <= 1e-12 and 0 < its <= 2000
+        xs = np.linalg.solve(K, b)
+        assert np.allclose(x, xs, atol=1e-9 * np.abs(xs).max())
+        _minres_norm_check(K, b, P, x, rel)
+        # stopped early, the recursion still reports the true residual norm
+        x5, its5, rel5 = O.minres(lambda v: K @ v, b, lambda v: P @ v, 0.0, 5)
+        assert its5 == 5
+        _minres_norm_check(K, b, P, x5, rel5)
+
+
+def test_inner_solve_minres_indefinite():
+    # Thm 2.8 with sigma between lambda_{c+1} and lambda_{c+2} of the deflated L: K-hat has one
+    # negative eigenvalue, PCG does not apply, MINRES still returns the solution of
+    # (L + delta V V^T - sigma I) z = r with 1^T z = 0, for any trimmed index.
+    g = gg.random_connected(70, 120, seed=11, weights=(0.5, 1.5))
+    Ld = dense_laplacian_from_edges(g)
+    lam, X = np.linalg.eigh(Ld)
+    V = X[:, 1:3]
+    delta = 2 * Ld.diagonal().max()
+    Lt = Ld + delta * V @ V.T
+    lt, Xt = np.linalg.eigh(Lt)
+    sigma = 0.5 * (lt[1] + lt[2])
+    r = _rhs_perp_one(g.n, 2)
+    ref = Xt[:, 1:] @ ((Xt[:, 1:].T @ r) / (lt[1:] - sigma))
+    L = O.laplacian(g)
+    d = O.degrees(g)
+    for i in [O.trim_index(d), 0]:
+        z, its, rel = O.inner_solve(L, d, r, i, sigma, delta, V, 1e-13, 5000, solver="minres")
+        assert rel <= 1e-13
+        assert abs(z.sum()) <= 1e-10 * np.abs(z).max()
+        assert np.allclose((Lt - sigma * np.eye(g.n)) @ z, r, atol=1e-8 * np.abs(r).max())
+        assert np.allclose(z, ref, atol=1e-8 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("g,k", [(gg.grid2d(9, 7), 6), (gg.random_connected(120, 300, seed=4), 8),
+                                 (gg.rmat(8, 8, seed=9), 8)], ids=lambda x: getattr(x, "name", str(x)))
+def test_isira_moving_shift_matches_dense(g, k):
+    # Algorithm 3.2 with the purge step's moving shift (sigma <- theta_2, MINRES inner solves)
+    # reaches the k smallest positive eigenvalues of the dense eigendecomposition.
+    lam, _ = O.smallest_positive_eigenpairs_dense(g, k)
+    U0 = gg.start_block(g.n, 4, 1)
+    res = O.isira(g, k, 0.0, 1e-10, U0, inner_rtol=1e-10, moving_shift=True)
+    assert res.converged == k
+    assert np.allclose(np.sort(res.evals), lam, rtol=1e-9, atol=0)
+    assert res.resid.max() < 1e-10
