@@ -41,6 +41,8 @@ def workload(name):
         return gg.grid2d(64, 64), dict(k=10, sigma=0.0, tol=1e-10)
     if name == "grid128w":
         return gg.grid3d(128, 128, 128, weights=(0.5, 1.5), seed=3), dict(k=20, sigma=0.0, tol=1e-8)
+    if name == "chunglu24":  # n = 2^24, beta 2.1, mean degree 24 (generation takes minutes)
+        return gg.chung_lu(1 << 24, 2.1, 24.0, seed=5), dict(k=50, sigma=0.0, tol=1e-8)
     if name.startswith("rmat"):
         s = int(name[4:])
         return gg.rmat(s, 8, seed=2), dict(k=20, sigma=0.0, tol=1e-8)
@@ -184,6 +186,37 @@ def rank_one_study(ctx, g, cfg, opts, args):
                       "k": cfg["k"], "tol": cfg["tol"], "rows": rows}), flush=True)
 
 
+def shift_study(ctx, g, cfg, opts, args, P):
+    """Algorithm 3.2's purge step moves sigma to about theta_2; with the moving shift the
+    inner systems can be indefinite and are solved by MINRES.  Fixed sigma (PCG) against
+    moving sigma (MINRES), FP64 and FP32 inner solves."""
+    rows, ref = [], None
+    for name, mode, prec in [("fixed_fp64", P.isira.SHIFT_FIXED, P.isira.FP64),
+                             ("moving_fp64", P.isira.SHIFT_MOVING, P.isira.FP64),
+                             ("fixed_fp32", P.isira.SHIFT_FIXED, P.isira.FP32),
+                             ("moving_fp32", P.isira.SHIFT_MOVING, P.isira.FP32)]:
+        ts = []
+        for _ in range(max(1, args.steps)):
+            ev, X, res, st = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], shift_mode=mode,
+                                       inner_prec=prec, **opts)
+            ts.append(st["ms_total"] / 1e3)
+        ev = np.sort(ev)
+        ref = ev if ref is None else ref
+        row = {"variant": name, "s": min(ts), "outer_total": st["outer_total"],
+               "inner_total": st["inner_total"], "inner_fallbacks": st["inner_fallbacks"],
+               "sigma_last": st["sigma_last"], "converged": st["n_converged"],
+               "max_resid": float(np.max(res)) if len(res) else None,
+               "max_rel_eval_diff_vs_fixed_fp64": float(np.max(np.abs(ev - ref) / ref))
+               if len(ev) == len(ref) else None}
+        gold = golden(args.workload)
+        if gold is not None:
+            row["rel_eval_err_vs_oracle"] = rel_err(ev, gold)
+        rows.append(row)
+        log(f"shift {row}")
+    print(json.dumps({"study": "shift", "workload": args.workload, "n": g.n, "k": cfg["k"],
+                      "tol": cfg["tol"], "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,11 +231,12 @@ def main():
                     help="only a 256 MiB device copy (counter calibration) and launches of the "
                          "FP64 and FP32 products, for rocprofv3 counter runs")
     ap.add_argument("--probe-reps", type=int, default=20)
-    ap.add_argument("--study", choices=["trim", "rank1"], default=None,
+    ap.add_argument("--study", choices=["trim", "rank1", "shift"], default=None,
                     help="trim: the paper's Table 2 comparison of trimmed vertices (maximum "
                          "degree, a minimum-degree vertex, vertex 0) on this workload; "
                          "rank1: sigma = lambda_1 / 2 with and without the (sigma/n) 1 1^T "
-                         "term of the inner operator (Remark 3.1)")
+                         "term of the inner operator (Remark 3.1); shift: fixed sigma = 0 (PCG) "
+                         "against the purge step's moving shift (MINRES)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -245,6 +279,9 @@ def main():
         return
     if args.study == "rank1":
         rank_one_study(ctx, g, cfg, opts, args)
+        return
+    if args.study == "shift":
+        shift_study(ctx, g, cfg, opts, args, P)
         return
     stream = torch.cuda.current_stream()
     for w in range(args.warmup):
@@ -316,17 +353,21 @@ def main():
         out["rel_eval_err_vs_oracle"] = rel_err(ev, gold)
     if not args.no_variants:
         # the same solve with FP32 inner solves, Jacobi and learned preconditioner
-        variants = [("fp32_jacobi", P.isira.FP32, P.isira.PC_JACOBI)]
+        # and the purge step's moving shift (sigma <- theta_2, MINRES inner solves)
+        fixed, moving = P.isira.SHIFT_FIXED, P.isira.SHIFT_MOVING
+        variants = [("fp32_jacobi", P.isira.FP32, P.isira.PC_JACOBI, fixed)]
         if os.path.exists(SPAI_WEIGHTS):
             from paper_1710_07080_amd import spai_train
 
             ctx.spai_install(spai_train.load(SPAI_WEIGHTS), sigma=cfg["sigma"])
-            variants.append(("fp32_learned", P.isira.FP32, P.isira.PC_LEARNED))
-        for name, prec, pc in variants:
+            variants.append(("fp32_learned", P.isira.FP32, P.isira.PC_LEARNED, fixed))
+        variants += [("moving_shift_fp64", P.isira.FP64, P.isira.PC_JACOBI, moving),
+                     ("moving_shift_fp32", P.isira.FP32, P.isira.PC_JACOBI, moving)]
+        for name, prec, pc, mode in variants:
             best = None
             for _ in range(max(1, args.steps)):
                 evv, Xv, resv, stv = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], inner_prec=prec,
-                                               precond=pc, **opts)
+                                               precond=pc, shift_mode=mode, **opts)
                 if best is None or stv["ms_total"] < best[3]["ms_total"]:
                     best = (evv, Xv, resv, stv)
             evv, Xv, resv, stv = best

@@ -55,6 +55,15 @@ extern "C" {
 #define ISIRA_PC_JACOBI 0  /* M-hat_sigma = diag(d - sigma), Remark 3.2, with eq. (3.5) */
 #define ISIRA_PC_LEARNED 1 /* learned sparse approximate inverse, with eq. (3.5) */
 
+/* ---- inner solver ---- */
+#define ISIRA_SOLVER_PCG 0    /* preconditioned conjugate gradients (SPD systems) */
+#define ISIRA_SOLVER_MINRES 1 /* preconditioned MINRES (symmetric, possibly indefinite) */
+
+/* ---- shift strategy ---- */
+#define ISIRA_SHIFT_FIXED 0   /* sigma stays the caller's value (inner solver PCG) */
+#define ISIRA_SHIFT_MOVING 1  /* Algorithm 3.2's purge step: sigma <- theta_2 after each locked
+                                 pair, capped at half the minimum degree (inner solver MINRES) */
+
 #define ISIRA_MAX_K 64        /* at most 64 wanted pairs per solve */
 #define ISIRA_MAX_BASIS 192   /* m (maximal search-space dimension) is at most 192 */
 
@@ -89,6 +98,8 @@ typedef struct {
   int32_t drop_rank_one;  /* 1: leave the rank-one term (sigma/n) 1-hat 1-hat^T out of the inner
                              operator (the simplification Remark 3.1 allows for large n);
                              default 0 keeps the exact operator of eq. (2.15) */
+  int32_t shift_mode;     /* ISIRA_SHIFT_FIXED (default) or ISIRA_SHIFT_MOVING; the moving shift
+                             is not combined with the learned preconditioner (ISIRA_E_PRECOND) */
 } isira_options;
 
 #define ISIRA_STATS_MAX 64
@@ -103,6 +114,7 @@ typedef struct {
   double ms_total, ms_inner, ms_ortho, ms_rr_host, ms_residual, ms_restart;
   int64_t trim_index;                  /* caller label of the trimmed vertex */
   double delta;
+  double sigma_last;                   /* the shift of the last inner solve */
 } isira_stats;
 
 typedef struct {
@@ -164,8 +176,8 @@ int isira_time_spmv(isira_ctx* ctx, int32_t prec, int32_t reps, double* ms_per);
  * delta <= 0 selects the default.  z: device n FP64 output.  *iters, *relres: host. */
 int isira_inner_solve(isira_ctx* ctx, const double* r, const double* V, int32_t c,
                       double sigma, double delta, int64_t trim, double rtol, int32_t max_it,
-                      int32_t prec, int32_t precond, double* z, int32_t* iters,
-                      double* relres);
+                      int32_t prec, int32_t precond, int32_t solver, double* z,
+                      int32_t* iters, double* relres);
 
 /* Classical Gram-Schmidt applied twice against the ncols orthonormal columns of Q and
  * the unit vector 1/sqrt(n), then normalization (the orthonormalization step of

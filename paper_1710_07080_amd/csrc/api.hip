@@ -120,6 +120,9 @@ struct isira_ctx {
          *y64 = nullptr;
   float *x32 = nullptr, *ri32 = nullptr, *p32 = nullptr, *q32 = nullptr, *dinv32 = nullptr,
         *y32 = nullptr;
+  double *wa64 = nullptr, *wb64 = nullptr;  // MINRES directions
+  float *wa32 = nullptr, *wb32 = nullptr;
+  int minres_next = 1;  // number of the next MINRES iteration to queue
   double* svec = nullptr;  // device ISIRA_MAX_BASIS
   double* Sdev = nullptr;  // device ISIRA_MAX_BASIS^2
   double* Ginv = nullptr;  // device kMaxC^2
@@ -252,6 +255,7 @@ static void free_workspace(isira_ctx* c) {
   dfree(c->Y32); dfree(c->r64); dfree(c->z64); dfree(c->tmp64); dfree(c->x64); dfree(c->ri64);
   dfree(c->p64); dfree(c->q64); dfree(c->dinv64); dfree(c->y64); dfree(c->x32); dfree(c->ri32);
   dfree(c->p32); dfree(c->q32); dfree(c->dinv32); dfree(c->y32);
+  dfree(c->wa64); dfree(c->wb64); dfree(c->wa32); dfree(c->wb32);
   c->ws_m = c->ws_k = 0;
 }
 
@@ -275,9 +279,9 @@ static int ensure_workspace(isira_ctx* c, int m, int kmax) {
   CKH(hipMemset(c->Vin32, 0, ld * kpad * sizeof(float)));
   CKH(hipMemset(c->Y32, 0, ld * kpad * sizeof(float)));
   for (double** p : {&c->r64, &c->z64, &c->tmp64, &c->x64, &c->ri64, &c->p64, &c->q64,
-                     &c->dinv64, &c->y64})
+                     &c->dinv64, &c->y64, &c->wa64, &c->wb64})
     if ((rc = dalloc(p, ld))) return rc;
-  for (float** p : {&c->x32, &c->ri32, &c->p32, &c->q32, &c->dinv32, &c->y32})
+  for (float** p : {&c->x32, &c->ri32, &c->p32, &c->q32, &c->dinv32, &c->y32, &c->wa32, &c->wb32})
     if ((rc = dalloc(p, ld))) return rc;
   c->ws_m = m;
   c->ws_k = kmax;
@@ -647,6 +651,7 @@ struct InnerCfg {
   int trim;     // internal index
   int maxit, check_every;
   bool rank_one = true;  // the (sigma/n) 1-hat 1-hat^T term of eq. (2.15) in the operator
+  int solver = ISIRA_SOLVER_PCG;
 };
 
 // Solve the trimmed shifted deflated system (2.15) for right-hand side r64 (internal order,
@@ -657,15 +662,68 @@ struct InnerCfg {
 // (still trimmed, inner precision) is left in x32/x64.
 template <typename T>
 struct PcgBufs {
-  T *x, *r, *p, *q, *dinv, *y;
+  T *x, *r, *p, *q, *dinv, *y, *wa, *wb;
   const T *V, *Y;
 };
 template <typename T>
 PcgBufs<T> pcg_bufs(isira_ctx* c) {
   if constexpr (sizeof(T) == 8) {
-    return PcgBufs<T>{c->x64, c->ri64, c->p64, c->q64, c->dinv64, c->y64, c->Vin64, c->Y64};
+    return PcgBufs<T>{c->x64, c->ri64, c->p64, c->q64, c->dinv64, c->y64, c->wa64, c->wb64,
+                      c->Vin64, c->Y64};
   } else {
-    return PcgBufs<T>{c->x32, c->ri32, c->p32, c->q32, c->dinv32, c->y32, c->Vin32, c->Y32};
+    return PcgBufs<T>{c->x32, c->ri32, c->p32, c->q32, c->dinv32, c->y32, c->wa32, c->wb32,
+                      c->Vin32, c->Y32};
+  }
+}
+
+// Preconditioned MINRES iterations (Jacobi + eq. (3.5) preconditioner, which stays SPD for
+// any shift below the minimum degree).  Buffers: x; the Lanczos vectors v_j, v_{j-1} in r and
+// y (they swap roles every iteration); z (normalized preconditioned vector) in p; the
+// directions w_j, w_{j-1} in wa and wb (swapping); the product in q.  Iteration j (from 1)
+// has parity (j - 1) & 1; the first call (init) sets up v_1 = rhs, gamma_1 and z_1.
+template <typename T>
+void minres_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init, int j0) {
+  const int n = (int)c->n;
+  const PcgBufs<T> b = pcg_bufs<T>(c);
+  hipStream_t s = c->stream;
+  const int vm = sizeof(T) == 8 ? valmode64(c) : valmode32(c);
+  T* vb[2] = {b.r, b.y};
+  T* wb[2] = {b.wa, b.wb};
+  const double sig_over_n = cfg.rank_one ? cfg.sigma / (double)n : 0.0;
+  SpmvArgs<T> a{};
+  a.rp = c->rp;
+  a.col = c->col;
+  a.vals = sizeof(T) == 8 ? (const void*)c->w64 : (const void*)c->w32;
+  a.x = b.p;
+  a.y = b.q;
+  a.diag = sizeof(T) == 8 ? (const T*)c->deg : (const T*)c->deg32;
+  a.n = n;
+  a.trim = cfg.trim;
+  a.sigma = cfg.sigma;
+  a.ldv = c->ld;
+  a.delta = cfg.delta;
+  a.red = 4;  // delta_j = z^T K-hat z, the deflation and rank-one terms folded in
+  a.st = c->st;
+  a.check_done = 1;
+  a.fold_c = nc;
+  a.fold_nblk = stream_grid(n);
+  a.fold_partials = c->rb.partials;
+  a.fold_sig_over_n = sig_over_n;
+  int it = 0;
+  if (init) {
+    launch_minres_a<T>(n, b.q, vb[0], vb[1], b.dinv, b.V, c->ld, nc, c->Ginv, cfg.delta,
+                       cfg.trim, sig_over_n, 1, c->st, c->rb, s);
+    launch_minres_b<T>(n, b.p, wb[1], wb[0], b.x, vb[0], vb[1], b.dinv, b.V, c->ld, nc,
+                       cfg.delta, 1, 0, c->st, c->rb, s);
+  }
+  for (; it < iters; ++it) {
+    const int j = j0 + it;  // iteration number, from 1
+    const int par = (j - 1) & 1;
+    launch_spmv<T>(c->plan, vm, a, c->rb, s);
+    launch_minres_a<T>(n, b.q, vb[par], vb[1 - par], b.dinv, b.V, c->ld, nc, c->Ginv,
+                       cfg.delta, cfg.trim, sig_over_n, 0, c->st, c->rb, s);
+    launch_minres_b<T>(n, b.p, wb[1 - par], wb[par], b.x, vb[1 - par], nullptr, b.dinv, b.V,
+                       c->ld, nc, cfg.delta, 0, j, c->st, c->rb, s);
   }
 }
 
@@ -733,7 +791,12 @@ void inner_pcg_start(isira_ctx* c, const InnerCfg& cfg, const double* r64, doubl
   const PcgBufs<T> b = pcg_bufs<T>(c);
   launch_pcg_reset(c->st, cfg.rtol * cfg.rtol, cfg.maxit, c->stream);
   launch_rhs_prep<T>(n, r64, mean, mean_sum, 1.0 / (double)n, cfg.trim, b.r, b.x, c->stream);
-  pcg_batch<T>(c, cfg, nc, 1 + cfg.check_every, 1);
+  if (cfg.solver == ISIRA_SOLVER_MINRES) {
+    minres_batch<T>(c, cfg, nc, cfg.check_every, 1, 1);
+    c->minres_next = 1 + cfg.check_every;
+  } else {
+    pcg_batch<T>(c, cfg, nc, 1 + cfg.check_every, 1);
+  }
 }
 
 // `synced`: st_host already holds the state after the queued batch (no wait needed first).
@@ -745,7 +808,12 @@ int inner_pcg_finish(isira_ctx* c, const InnerCfg& cfg, int nc, bool synced, int
     if (!synced && (rc = sync_state(c))) return rc;
     synced = false;
     if (c->st_host->done) break;
-    pcg_batch<T>(c, cfg, nc, cfg.check_every, 0);
+    if (cfg.solver == ISIRA_SOLVER_MINRES) {
+      minres_batch<T>(c, cfg, nc, cfg.check_every, 0, c->minres_next);
+      c->minres_next += cfg.check_every;
+    } else {
+      pcg_batch<T>(c, cfg, nc, cfg.check_every, 0);
+    }
   }
   *iters = c->st_host->it;
   *status = c->st_host->status;
@@ -822,6 +890,11 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
   }
   if (opt.precond == ISIRA_PC_LEARNED && (c->spai_trim != trim || c->spai_sigma != sigma))
     return fail(ISIRA_E_PRECOND, "learned preconditioner was installed for another sigma or trim index");
+  if (opt.shift_mode != ISIRA_SHIFT_FIXED && opt.shift_mode != ISIRA_SHIFT_MOVING)
+    return fail(ISIRA_E_ARG, "bad shift_mode");
+  const bool moving = opt.shift_mode == ISIRA_SHIFT_MOVING;
+  if (moving && opt.precond == ISIRA_PC_LEARNED)
+    return fail(ISIRA_E_PRECOND, "the learned preconditioner is built for one shift; it cannot follow a moving shift");
   const double delta = opt.delta > 0 ? opt.delta : 2.0 * c->max_deg;
   int rc = ensure_workspace(c, m, k);
   if (rc) return rc;
@@ -839,6 +912,9 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
   cfg.maxit = opt.max_inner > 0 ? opt.max_inner : 1000;
   cfg.check_every = opt.check_every > 0 ? opt.check_every : 8;
   cfg.rank_one = opt.drop_rank_one == 0;
+  // a moving shift can make the trimmed system indefinite (Thm 2.8), so it is solved by MINRES
+  cfg.solver = moving ? ISIRA_SOLVER_MINRES : ISIRA_SOLVER_PCG;
+  const double sigma_cap = 0.5 * c->min_deg;  // keeps diag(d - sigma) positive
   const int max_outer = opt.max_outer > 0 ? opt.max_outer : 20000;
   // Jacobi inverse diagonal (Remark 3.2) in both precisions
   launch_dinv<double>(n, c->deg, sigma, trim, c->dinv64, s);
@@ -1039,7 +1115,18 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
         S.ms_restart += now_ms() - t0;
         nconv += 1;
         if (nconv < k) {
-          if ((rc = refresh_smw(nconv - 1))) return rc;
+          // the purge step's moving shift: sigma <- theta_2 (capped); the Jacobi diagonal
+          // and the whole SMW capacitance matrix then change with it
+          const double sigma_new = (moving && kk >= 1) ? std::min(theta[1], sigma_cap) : cfg.sigma;
+          if (sigma_new != cfg.sigma) {
+            cfg.sigma = sigma_new;
+            launch_dinv<double>(n, c->deg, cfg.sigma, trim, c->dinv64, s);
+            launch_dinv<float>(n, c->deg, cfg.sigma, trim, c->dinv32, s);
+            for (int j = 0; j < nconv; ++j)
+              if ((rc = refresh_smw(j))) return rc;
+          } else if ((rc = refresh_smw(nconv - 1))) {
+            return rc;
+          }
           if (kk == 0) {  // empty basis: start again from a replacement vector
             launch_fill_replacement(n, opt.seed, draws++, c->d_perm, c->z64, s);
             if ((rc = expand_with(c->z64))) return rc;
@@ -1119,7 +1206,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
       }
       SpmvArgs<double> ca{};
       ca.rp = c->rp; ca.col = c->col; ca.vals = c->w64; ca.x = zin; ca.y = c->tmp64;
-      ca.diag = c->deg; ca.n = n; ca.trim = trim; ca.sigma = sigma;
+      ca.diag = c->deg; ca.n = n; ca.trim = trim; ca.sigma = cfg.sigma;
       launch_spmv<double>(c->plan, valmode64(c), ca, c->rb, s);
       launch_gather<double, double>(n, c->tmp64, c->d_iperm, cr, s);
       capture_count++;
@@ -1139,6 +1226,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
   S.ms_total = now_ms() - t_start;
   S.trim_index = c->perm[trim];
   S.delta = delta;
+  S.sigma_last = cfg.sigma;
   if (stats) *stats = S;
   return not_conv ? ISIRA_NOT_CONVERGED : ISIRA_OK;
 }
@@ -1214,13 +1302,16 @@ extern "C" int isira_time_spmv(isira_ctx* c, int32_t prec, int32_t reps, double*
 
 extern "C" int isira_inner_solve(isira_ctx* c, const double* r, const double* V, int32_t nc,
                                  double sigma, double delta, int64_t trim, double rtol,
-                                 int32_t max_it, int32_t prec, int32_t precond, double* z,
-                                 int32_t* iters, double* relres) {
+                                 int32_t max_it, int32_t prec, int32_t precond, int32_t solver,
+                                 double* z, int32_t* iters, double* relres) {
   if (!c || !r || !z || (nc > 0 && !V)) return fail(ISIRA_E_ARG, "NULL argument");
   if (nc < 0 || nc > kMaxC || nc > c->n - 3) return fail(ISIRA_E_ARG, "bad c");
   if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
   if (prec != ISIRA_FP64 && prec != ISIRA_FP32) return fail(ISIRA_E_ARG, "bad prec");
   if (precond == ISIRA_PC_LEARNED && !c->has_learned) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
+  if (solver != ISIRA_SOLVER_PCG && solver != ISIRA_SOLVER_MINRES) return fail(ISIRA_E_ARG, "bad solver");
+  if (solver == ISIRA_SOLVER_MINRES && precond != ISIRA_PC_JACOBI)
+    return fail(ISIRA_E_ARG, "MINRES runs with the Jacobi preconditioner only");
   int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, std::max(1, (int)nc)));
   if (rc) return rc;
   const int n = (int)c->n;
@@ -1237,6 +1328,7 @@ extern "C" int isira_inner_solve(isira_ctx* c, const double* r, const double* V,
     return fail(ISIRA_E_PRECOND, "learned preconditioner was installed for another sigma or trim index");
   cfg.maxit = max_it > 0 ? max_it : 1000;
   cfg.check_every = 8;
+  cfg.solver = solver;
   launch_dinv<double>(n, c->deg, sigma, cfg.trim, c->dinv64, s);
   launch_dinv<float>(n, c->deg, sigma, cfg.trim, c->dinv32, s);
   // deflation columns (internal order, trimmed row zeroed) and the SMW capacitance

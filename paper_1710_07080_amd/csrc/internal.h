@@ -83,6 +83,11 @@ struct DevState {
   double t1[kMaxC];  // V-hat^T p
   double t2[kMaxC + 1];  // V-hat^T (M^-1 r); learned variant: [V-hat^T y, r^T y]
   double g[kMaxC];   // G^{-1} t2
+  // MINRES: gamma_{j-1}, c_j, c_{j-1}, s_j, s_{j-1}, eta, eta_0, alpha_1, alpha_2, alpha_3
+  // (gamma_j in rho, delta_j in pq, c_{j+1} eta in alpha); last_it: the iteration whose
+  // solution update still runs after the test has stopped the iteration
+  double mr[10];
+  int32_t last_it;
 };
 
 enum PcgStatus { kPcgOk = 0, kPcgCapped = 1, kPcgBreakdown = 2 };
@@ -131,7 +136,7 @@ struct SpmvArgs {
   const double* tvec;
   double delta;
   int32_t red;         // 0 none; 1 PCG p^T q -> alpha; 2 ||y - theta x||^2 -> st->red[0];
-                       // 3 x^T y -> st->red[1]
+                       // 3 x^T y -> st->red[1]; 4 MINRES z^T q -> st->pq only
   double theta;
   DevState* st;
   int32_t check_done;  // return at once when st->done
@@ -169,6 +174,15 @@ void launch_pcg_update2(int n, const T* r, T* p, const T* dinv, const T* V, int6
                         int c, double delta, int init, DevState* st, RedBuf rb, hipStream_t s);
 // learned preconditioner variants: update1 without the Jacobi dots; apply y = M r with
 // the SMW dots; update2 with z = y - delta Y g.
+// preconditioned MINRES for the indefinite inner systems of a moving shift
+template <typename T>
+void launch_minres_a(int n, const T* q, const T* vcur, T* vprev, const T* dinv, const T* V,
+                     int64_t ldv, int c, const double* Ginv, double delta, int trim,
+                     double sig_over_n, int init, DevState* st, RedBuf rb, hipStream_t s);
+template <typename T>
+void launch_minres_b(int n, T* z, T* wprev, T* wcur, T* x, const T* v, T* vzero, const T* dinv,
+                     const T* V, int64_t ldv, int c, double delta, int init, int jit,
+                     DevState* st, RedBuf rb, hipStream_t s);
 template <typename T>
 void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, const T* V,
                               int64_t ldv, int c, double delta, int trim, double sig_over_n,

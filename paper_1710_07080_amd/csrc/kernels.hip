@@ -111,6 +111,12 @@ static_assert((size_t)kSpmvGrid <= kPartialsElems, "SpMV partials");
 
 
 
+// column indices and weights of the product streamed with non-temporal loads, so that they
+// do not evict the gathered x from the caches (compile-time tunable)
+#ifndef ISIRA_NT_STREAM
+#define ISIRA_NT_STREAM 0
+#endif
+
 #define HIP_LAUNCH_CHECK() (void)hipGetLastError()
 
 // ------------------------------------------------------------------ setup kernels
@@ -249,9 +255,17 @@ __device__ __forceinline__ T edge_val(const void* vals, int j) {
   if constexpr (VM == kUnitNeg) {
     return T(1);
   } else if constexpr (VM == kF64Neg) {
+#if ISIRA_NT_STREAM
+    return (T)__builtin_nontemporal_load((const double*)vals + j);
+#else
     return (T)((const double*)vals)[j];
+#endif
   } else {
+#if ISIRA_NT_STREAM
+    return (T)__builtin_nontemporal_load((const float*)vals + j);
+#else
     return (T)((const float*)vals)[j];
+#endif
   }
 }
 
@@ -291,7 +305,7 @@ __device__ __forceinline__ double finish_row_xd(const SpmvArgs<T>& a, int row, T
     const double dd = (double)y - a.theta * (double)xl;
     return dd * dd;
   }
-  if (a.red == 1 || a.red == 3) return (double)xl * (double)y;
+  if (a.red == 1 || a.red == 3 || a.red == 4) return (double)xl * (double)y;
   return 0.0;
 }
 
@@ -399,7 +413,11 @@ __global__ __launch_bounds__(NT) void k_spmv(SpmvArgs<T> a, const int4* __restri
     for (int k = 0; k < PT; ++k) {
       const int e = d.y + tid + k * NT;
       const bool in = e < d.z;
+#if ISIRA_NT_STREAM
+      sl.ci[k] = in ? __builtin_nontemporal_load(col + e) : -1;
+#else
       sl.ci[k] = in ? col[e] : -1;
+#endif
       sl.v[k] = in ? edge_val<VM, T>(a.vals, e) : T(0);
     }
     const int nr = d.w >= 0 ? (d.w >> 8) : -1;
@@ -527,7 +545,7 @@ __global__ __launch_bounds__(kFin) void k_spmv_fin(SpmvArgs<T> a, SplitInfo sp, 
   const double tot = block_sum_any(acc);
   if (tid == 0) {
     DevState* st = a.st;
-    if (a.red == 1) {
+    if (a.red == 1 || a.red == 4) {
       double pq = tot;
       if (a.fold_partials) {
         double tt = 0.0;
@@ -535,6 +553,7 @@ __global__ __launch_bounds__(kFin) void k_spmv_fin(SpmvArgs<T> a, SplitInfo sp, 
         pq += a.delta * tt + a.fold_sig_over_n * fold[0] * fold[0];
       }
       st->pq = pq;
+      if (a.red == 4) return;  // MINRES: delta_j = z^T K z, any sign
       const double alpha = st->rho / pq;
       if (!(pq > 0.0) || !isfinite(alpha)) {
         st->done = 1;
@@ -812,6 +831,236 @@ template void launch_pcg_update2<double>(int, const double*, double*, const doub
 template void launch_pcg_update2<float>(int, const float*, float*, const float*, const float*,
                                         int64_t, int, double, int, DevState*, RedBuf,
                                         hipStream_t);
+
+// ---- preconditioned MINRES (Paige-Saunders) for the indefinite inner systems of a moving
+// shift.  One iteration: the product q = (L-hat - sigma I) z with its finishing dispatch
+// (delta_j = z^T K-hat z with the deflation and rank-one terms folded in), k_minres_a + its
+// finishing dispatch (the next Lanczos vector, gamma_{j+1} and the Givens rotation), and
+// k_minres_b (the new direction, the solution update and the next preconditioned vector). ----
+
+// v_new = K-hat z - (delta_j / gamma_j) v_j - (gamma_j / gamma_{j-1}) v_{j-1}, written over
+// v_{j-1}; K-hat z = q + delta V-hat t1 + (sigma/n) 1-hat (1-hat^T z) with t1 = V-hat^T z.
+// init: v_new = v_1 = vcur (the right-hand side), nothing written.
+// Partials ||v||^2, v^T D^-1 v, V-hat^T (D^-1 v).
+template <typename T, int CM>
+__global__ __launch_bounds__(kBlock) void k_minres_a(int n, const T* __restrict__ q,
+                                                     const T* __restrict__ vcur,
+                                                     T* __restrict__ vprev,
+                                                     const T* __restrict__ dinv,
+                                                     const T* __restrict__ V, int64_t ldv,
+                                                     int c, double delta, int trim,
+                                                     double sig_over_n, int init,
+                                                     DevState* st, double* partials) {
+  if (st->done) return;
+  constexpr int NV = 2 + (CM > 0 ? CM : 0);
+  __shared__ T st1[CM > 0 ? CM : 1];
+  if constexpr (CM > 0) {
+    for (int j = threadIdx.x; j < CM; j += kBlock) st1[j] = j < c ? (T)st->t1[j] : T(0);
+    __syncthreads();
+  }
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  const double gam = st->rho;
+  const T cd = init ? T(0) : (T)(st->pq / gam);
+  const T cg = init ? T(0) : (T)(gam / st->mr[0]);
+  const T dl = (T)delta;
+  const T r1 = init ? T(0) : (T)(sig_over_n * st->sump);
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    T vreg[CM > 0 ? CM : 1];
+#pragma unroll
+    for (int j = 0; j < CM; ++j) vreg[j] = V[l + (int64_t)j * ldv];
+    T vt = T(0);
+#pragma unroll
+    for (int j = 0; j < CM; ++j) vt += vreg[j] * st1[j];
+    T vn = vcur[l];
+    if (!init) {
+      const T kz = q[l] + dl * vt + (l == trim ? T(0) : r1);
+      vn = kz - cd * vn - cg * vprev[l];
+      vprev[l] = vn;
+    }
+    const T u = dinv[l] * vn;
+    acc[0] += (double)vn * (double)vn;
+    acc[1] += (double)vn * (double)u;
+#pragma unroll
+    for (int j = 0; j < CM; ++j) acc[2 + j] += (double)vreg[j] * (double)u;
+  }
+  write_partials<NV>(acc, 2 + c, partials);
+}
+
+// Reduces the partials of the Lanczos step (one workgroup): g = G^-1 t2 (eq. (3.5)),
+// gamma_{j+1} = sqrt(v^T M^-1 v) = sqrt(v^T D^-1 v - delta t2^T g), then one Givens rotation
+// of the tridiagonal QR factorization and the recursively updated residual norm eta; stops
+// when |eta| <= rtol eta_0.  V-hat^T z_{j+1} = g / gamma_{j+1} by the SMW identity.
+__global__ __launch_bounds__(kFin) void k_minres_fin_a(int c, int nblk, const double* partials,
+                                                         const double* Ginv, double delta,
+                                                         int init, DevState* st) {
+  if (st->done) return;
+  __shared__ double red[2 + kMaxC];
+  __shared__ double gsh[kMaxC];
+  __shared__ double gnew_sh;
+  final_reduce(partials, 2 + c, nblk, red);
+  for (int j = threadIdx.x; j < c; j += blockDim.x) {
+    double gj = 0.0;
+    for (int i = 0; i < c; ++i) gj += Ginv[j + i * c] * red[2 + i];
+    gsh[j] = gj;
+    st->g[j] = gj;
+    st->t2[j] = red[2 + j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tg = 0.0;
+    for (int j = 0; j < c; ++j) tg += red[2 + j] * gsh[j];
+    const double vmv = red[1] - delta * tg;
+    const double gnew = (vmv > 0.0 && isfinite(vmv)) ? sqrt(vmv) : 0.0;
+    double* mr = st->mr;
+    if (init) {
+      mr[0] = 1.0;                  // gamma_0 (multiplies v_0 = 0)
+      mr[1] = mr[2] = 1.0;          // c_1, c_0
+      mr[3] = mr[4] = 0.0;          // s_1, s_0
+      mr[5] = mr[6] = gnew;         // eta, eta_0
+      st->rho = gnew;
+      st->rr = st->rr0 = gnew * gnew;
+      st->thresh2 = st->rtol2 * gnew * gnew;
+      st->it = 0;
+      st->last_it = -1;
+      if (!(gnew > 0.0)) st->done = 1;
+    } else {
+      const double gam = st->rho, dlt = st->pq;
+      const double cj = mr[1], cjm = mr[2], sj = mr[3], sjm = mr[4], eta = mr[5];
+      const double a0 = cj * dlt - cjm * sj * gam;
+      const double a1 = sqrt(a0 * a0 + gnew * gnew);
+      const double a2 = sj * dlt + cjm * cj * gam;
+      const double a3 = sjm * gam;
+      st->it += 1;
+      if (!(a1 > 0.0) || !isfinite(a1) || !isfinite(dlt)) {
+        st->done = 1;
+        st->status = kPcgBreakdown;
+        st->last_it = -1;
+      } else {
+        const double cn = a0 / a1, sn = gnew / a1;
+        mr[2] = cj;
+        mr[4] = sj;
+        mr[1] = cn;
+        mr[3] = sn;
+        mr[7] = a1;
+        mr[8] = a2;
+        mr[9] = a3;
+        st->alpha = cn * eta;
+        const double etan = -sn * eta;
+        mr[5] = etan;
+        mr[0] = gam;
+        st->rho = gnew;
+        st->rr = etan * etan;
+        if (etan * etan <= st->thresh2 || !(gnew > 0.0)) {
+          st->done = 1;
+          st->last_it = st->it;
+        } else if (st->it >= st->maxit) {
+          st->done = 1;
+          st->status = kPcgCapped;
+          st->last_it = st->it;
+        }
+      }
+    }
+    gnew_sh = gnew;
+  }
+  __syncthreads();
+  const double inv = gnew_sh > 0.0 ? 1.0 / gnew_sh : 0.0;
+  for (int j = threadIdx.x; j < c; j += blockDim.x) st->t1[j] = gsh[j] * inv;
+}
+
+// w_{j+1} = (z_j - alpha_3 w_{j-1} - alpha_2 w_j) / alpha_1 (written over w_{j-1}),
+// x += c_{j+1} eta w_{j+1}, and z_{j+1} = M^-1 v_{j+1} / gamma_{j+1} with eq. (3.5)
+// (over z_j); partial sum(z_{j+1}).  Iteration `jit` runs even when the test stopped the
+// iteration at jit, to apply its solution update.  init: z_1 only, and w, v_0 cleared.
+template <typename T, int CM>
+__global__ __launch_bounds__(kBlock) void k_minres_b(int n, T* __restrict__ z,
+                                                     T* __restrict__ wprev,
+                                                     T* __restrict__ wcur, T* __restrict__ x,
+                                                     const T* __restrict__ v,
+                                                     T* __restrict__ vzero,
+                                                     const T* __restrict__ dinv,
+                                                     const T* __restrict__ V, int64_t ldv,
+                                                     int c, double delta, int init, int jit,
+                                                     DevState* st, double* partials) {
+  if (st->done && st->last_it != jit) return;
+  __shared__ T sg[CM > 0 ? CM : 1];
+  for (int j = threadIdx.x; j < CM; j += kBlock) sg[j] = j < c ? (T)st->g[j] : T(0);
+  __syncthreads();
+  const double gnew = st->rho;
+  const T inv = gnew > 0.0 ? (T)(1.0 / gnew) : T(0);
+  const double* mr = st->mr;
+  const T ia1 = init ? T(0) : (T)(1.0 / mr[7]);
+  const T a2 = init ? T(0) : (T)mr[8];
+  const T a3 = init ? T(0) : (T)mr[9];
+  const T ceta = init ? T(0) : (T)st->alpha;
+  const T dl = (T)delta;
+  double acc[1] = {0.0};
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    T vreg[CM > 0 ? CM : 1];
+#pragma unroll
+    for (int j = 0; j < CM; ++j) vreg[j] = V[l + (int64_t)j * ldv];
+    T s = T(0);
+#pragma unroll
+    for (int j = 0; j < CM; ++j) s += vreg[j] * sg[j];
+    if (init) {
+      wprev[l] = T(0);
+      wcur[l] = T(0);
+      vzero[l] = T(0);
+    } else {
+      const T wn = (z[l] - a3 * wprev[l] - a2 * wcur[l]) * ia1;
+      wprev[l] = wn;
+      x[l] += ceta * wn;
+    }
+    const T zn = dinv[l] * (v[l] - dl * s) * inv;
+    z[l] = zn;
+    acc[0] += (double)zn;
+  }
+  write_partials<1>(acc, 1, partials);
+}
+
+template <typename T>
+void launch_minres_a(int n, const T* q, const T* vcur, T* vprev, const T* dinv, const T* V,
+                     int64_t ldv, int c, const double* Ginv, double delta, int trim,
+                     double sig_over_n, int init, DevState* st, RedBuf rb, hipStream_t s) {
+  const int grid = stream_grid(n);
+#define ISIRA_MRA(CMV)                                                                       \
+  k_minres_a<T, CMV><<<grid, kBlock, 0, s>>>(n, q, vcur, vprev, dinv, V, ldv, c, delta, trim, \
+                                             sig_over_n, init, st, rb.partials)
+  switch (pick_cm(c)) {
+    ISIRA_CM_CASES(ISIRA_MRA)
+  }
+#undef ISIRA_MRA
+  k_minres_fin_a<<<1, kFin, 0, s>>>(c, grid, rb.partials, Ginv, delta, init, st);
+  HIP_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_minres_b(int n, T* z, T* wprev, T* wcur, T* x, const T* v, T* vzero, const T* dinv,
+                     const T* V, int64_t ldv, int c, double delta, int init, int jit,
+                     DevState* st, RedBuf rb, hipStream_t s) {
+  const int grid = stream_grid(n);
+#define ISIRA_MRB(CMV)                                                                      \
+  k_minres_b<T, CMV><<<grid, kBlock, 0, s>>>(n, z, wprev, wcur, x, v, vzero, dinv, V, ldv, c, \
+                                             delta, init, jit, st, rb.partials)
+  switch (pick_cm(c)) {
+    ISIRA_CM_CASES(ISIRA_MRB)
+  }
+#undef ISIRA_MRB
+  HIP_LAUNCH_CHECK();
+}
+template void launch_minres_a<double>(int, const double*, const double*, double*, const double*,
+                                      const double*, int64_t, int, const double*, double, int,
+                                      double, int, DevState*, RedBuf, hipStream_t);
+template void launch_minres_a<float>(int, const float*, const float*, float*, const float*,
+                                     const float*, int64_t, int, const double*, double, int,
+                                     double, int, DevState*, RedBuf, hipStream_t);
+template void launch_minres_b<double>(int, double*, double*, double*, double*, const double*,
+                                      double*, const double*, const double*, int64_t, int,
+                                      double, int, int, DevState*, RedBuf, hipStream_t);
+template void launch_minres_b<float>(int, float*, float*, float*, float*, const float*, float*,
+                                     const float*, const float*, int64_t, int, double, int, int,
+                                     DevState*, RedBuf, hipStream_t);
 
 // ---- learned preconditioner variants ----
 

@@ -26,6 +26,8 @@ ISIRA_E_STATE = -6
 W_NONE, W_F32, W_F64 = 0, 1, 2
 FP64, FP32 = 0, 1
 PC_JACOBI, PC_LEARNED = 0, 1
+SOLVER_PCG, SOLVER_MINRES = 0, 1
+SHIFT_FIXED, SHIFT_MOVING = 0, 1
 MAX_K = 64
 STATS_MAX = 64
 
@@ -48,7 +50,7 @@ class Options(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("u0", _c_double_p), ("check_every", ctypes.c_int32),
         ("verbose", ctypes.c_int32), ("capture_r", _c_double_p), ("capture_z", _c_double_p),
         ("capture_cap", ctypes.c_int32), ("capture_count", _c_int32_p),
-        ("drop_rank_one", ctypes.c_int32),
+        ("drop_rank_one", ctypes.c_int32), ("shift_mode", ctypes.c_int32),
     ]
 
 
@@ -63,6 +65,7 @@ class Stats(ctypes.Structure):
         ("ms_total", ctypes.c_double), ("ms_inner", ctypes.c_double), ("ms_ortho", ctypes.c_double),
         ("ms_rr_host", ctypes.c_double), ("ms_residual", ctypes.c_double),
         ("ms_restart", ctypes.c_double), ("trim_index", ctypes.c_int64), ("delta", ctypes.c_double),
+        ("sigma_last", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -120,7 +123,7 @@ def load() -> ctypes.CDLL:
         "isira_laplacian_apply": (i32, [vp, vp, vp]),
         "isira_laplacian_apply_f32": (i32, [vp, vp, vp]),
         "isira_time_spmv": (i32, [vp, i32, i32, _c_double_p]),
-        "isira_inner_solve": (i32, [vp, vp, vp, i32, dbl, dbl, i64, dbl, i32, i32, i32, vp,
+        "isira_inner_solve": (i32, [vp, vp, vp, i32, dbl, dbl, i64, dbl, i32, i32, i32, i32, vp,
                                     _c_int32_p, _c_double_p]),
         "isira_orthonormalize": (i32, [vp, vp, i32, vp, vp, _c_double_p]),
         "isira_symeig": (i32, [i32, vp, vp, vp]),
@@ -300,7 +303,7 @@ class Context:
 
     def inner_solve(self, r, V=None, sigma: float = 0.0, delta: float = 0.0, trim: int = -1,
                     rtol: float = 1e-10, max_it: int = 5000, prec: int = FP64,
-                    precond: int = PC_JACOBI):
+                    precond: int = PC_JACOBI, solver: int = SOLVER_PCG):
         """Trimmed, shifted, deflated solve (2.15) + enlargement (2.5).  r: CUDA float64 (n),
         V: CUDA float64 (c, n) rows = deflation vectors.  Returns (z, iters, relres)."""
         import torch
@@ -316,7 +319,8 @@ class Context:
         its = ctypes.c_int32(0)
         rel = ctypes.c_double(0)
         _check(self._lib.isira_inner_solve(self._h, _ptr(r), vp, c, float(sigma), float(delta), int(trim),
-                                           float(rtol), int(max_it), int(prec), int(precond), _ptr(z),
+                                           float(rtol), int(max_it), int(prec), int(precond), int(solver),
+                                           _ptr(z),
                                            ctypes.byref(its), ctypes.byref(rel)))
         return z, its.value, rel.value
 

@@ -126,6 +126,62 @@ def test_inner_solve_fp64(P, case):
     assert np.linalg.norm(z - z_ref) <= 1e-8 * np.linalg.norm(z_ref)
 
 
+@pytest.mark.parametrize("case", [
+    dict(g="rmat14", c=3, where="between"),   # one negative eigenvalue of K-hat
+    dict(g="grid3d_w", c=2, where="between"),
+    dict(g="rmat14", c=2, where="below"),     # SPD: MINRES and PCG reach the same solution
+], ids=["rmat14_indefinite", "grid3d_indefinite", "rmat14_spd"])
+def test_inner_solve_minres(P, case):
+    """Preconditioned MINRES on the trimmed deflated system (2.15) against the oracle's MINRES,
+    with sigma between lambda_{c+1} and lambda_{c+2} (indefinite, Thm 2.8) or below."""
+    g = GRAPHS[case["g"]]()
+    ctx = P.Context.from_graph(g)
+    L = O.laplacian(g)
+    d = O.degrees(g)
+    c = case["c"]
+    res = O.isira(g, c + 2, 0.0, 1e-10, gg.start_block(g.n, 4, 3), inner_rtol=1e-8)
+    order = np.argsort(res.evals)
+    V = res.evecs[:, order[:c]]  # the c smallest: deflated, lambda_{c+1..c+2} remain lowest
+    lam = res.evals[order]
+    sigma = 0.5 * (lam[c] + lam[c + 1]) if case["where"] == "between" else 0.5 * lam[0]
+    i = O.trim_index(d)
+    delta = O.deflation_shift(d)
+    r = np.random.default_rng(6).standard_normal(g.n)
+    r -= r.mean()
+    z_ref, its_ref, rel_ref = O.inner_solve(L, d, r, i, sigma, delta, V, 1e-12, 20000, solver="minres")
+    z, its, rel = ctx.inner_solve(_dev(r), _dev(V.T), sigma=sigma, delta=delta, trim=i, rtol=1e-12,
+                                  max_it=20000, prec=P.isira.FP64, solver=P.isira.SOLVER_MINRES)
+    z = z.cpu().numpy()
+    assert rel <= 1e-12 and rel_ref <= 1e-12
+    assert abs(its - its_ref) <= max(3, 0.05 * its_ref)
+    assert abs(z.sum()) <= 1e-9 * np.abs(z).max()
+    assert np.linalg.norm(z - z_ref) <= 1e-7 * np.linalg.norm(z_ref)
+    # the solved system itself
+    Kz = L @ z + delta * V @ (V.T @ z) - sigma * z
+    assert np.linalg.norm(Kz - r) <= 1e-8 * np.linalg.norm(r) * max(1.0, np.abs(z).max())
+    if case["where"] == "below":
+        zp, _, _ = ctx.inner_solve(_dev(r), _dev(V.T), sigma=sigma, delta=delta, trim=i, rtol=1e-12,
+                                   max_it=20000, prec=P.isira.FP64)
+        assert np.linalg.norm(zp.cpu().numpy() - z) <= 1e-8 * np.linalg.norm(z)
+    # FP32 MINRES: the recursion reaches a loose tolerance
+    z32, its32, rel32 = ctx.inner_solve(_dev(r), _dev(V.T), sigma=sigma, delta=delta, trim=i, rtol=1e-4,
+                                        max_it=20000, prec=P.isira.FP32, solver=P.isira.SOLVER_MINRES)
+    assert rel32 <= 1e-4
+
+
+@pytest.mark.parametrize("name,k", [("grid64", 8), ("rmat14", 10), ("grid3d_w", 8)])
+def test_solve_moving_shift(P, name, k):
+    """Algorithm 3.2 with the purge step's moving shift (sigma <- theta_2, MINRES inner
+    solves) against the oracle run the same way."""
+    g = GRAPHS[name]()
+    ctx = P.Context.from_graph(g)
+    U0 = gg.start_block(g.n, 4, 2)
+    ev, X, resid, st = ctx.solve(k, 0.0, 1e-9, u0=U0, shift_mode=P.isira.SHIFT_MOVING)
+    assert st["sigma_last"] > 0.0
+    res_o = O.isira(g, k, 0.0, 1e-9, U0, inner_rtol=1e-6, moving_shift=True)
+    _compare(res_o, ev, X.cpu().numpy(), resid, g, 1e-9)
+
+
 def test_inner_solve_fp32_accuracy(P):
     g = GRAPHS["rmat14"]()
     ctx = P.Context.from_graph(g)
