@@ -111,12 +111,6 @@ static_assert((size_t)kSpmvGrid <= kPartialsElems, "SpMV partials");
 
 
 
-// column indices and weights of the product streamed with non-temporal loads, so that they
-// do not evict the gathered x from the caches (compile-time tunable)
-#ifndef ISIRA_NT_STREAM
-#define ISIRA_NT_STREAM 0
-#endif
-
 #define HIP_LAUNCH_CHECK() (void)hipGetLastError()
 
 // ------------------------------------------------------------------ setup kernels
@@ -255,17 +249,9 @@ __device__ __forceinline__ T edge_val(const void* vals, int j) {
   if constexpr (VM == kUnitNeg) {
     return T(1);
   } else if constexpr (VM == kF64Neg) {
-#if ISIRA_NT_STREAM
-    return (T)__builtin_nontemporal_load((const double*)vals + j);
-#else
     return (T)((const double*)vals)[j];
-#endif
   } else {
-#if ISIRA_NT_STREAM
-    return (T)__builtin_nontemporal_load((const float*)vals + j);
-#else
     return (T)((const float*)vals)[j];
-#endif
   }
 }
 
@@ -413,11 +399,7 @@ __global__ __launch_bounds__(NT) void k_spmv(SpmvArgs<T> a, const int4* __restri
     for (int k = 0; k < PT; ++k) {
       const int e = d.y + tid + k * NT;
       const bool in = e < d.z;
-#if ISIRA_NT_STREAM
-      sl.ci[k] = in ? __builtin_nontemporal_load(col + e) : -1;
-#else
       sl.ci[k] = in ? col[e] : -1;
-#endif
       sl.v[k] = in ? edge_val<VM, T>(a.vals, e) : T(0);
     }
     const int nr = d.w >= 0 ? (d.w >> 8) : -1;
@@ -1287,8 +1269,7 @@ void launch_pcg_reset(DevState* st, double rtol2, int maxit, hipStream_t s) {
 // eq. (2.5): z = x - (1^T x / n) 1, in FP64 (x carries the trimmed zero in place).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sum(int n, const T* __restrict__ x,
-                                                DevState* st, double* partials,
-                                                unsigned* counter) {
+                                                DevState* st, double* partials) {
   double acc[1] = {0.0};
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
     acc[0] += (double)x[l];
@@ -1310,7 +1291,7 @@ __global__ __launch_bounds__(kBlock) void k_enlarge(int n, const T* __restrict__
 template <typename T>
 void launch_enlarge(int n, const T* x, double* z, DevState* st, RedBuf rb, hipStream_t s) {
   const int grid = stream_grid(n);
-  k_sum<T><<<grid, kBlock, 0, s>>>(n, x, st, rb.partials, rb.counters + 6);
+  k_sum<T><<<grid, kBlock, 0, s>>>(n, x, st, rb.partials);
   k_sum_fin<<<1, kFin, 0, s>>>(grid, rb.partials, st);
   k_enlarge<T><<<grid, kBlock, 0, s>>>(n, x, z, st);
   HIP_LAUNCH_CHECK();
@@ -1331,7 +1312,7 @@ __global__ __launch_bounds__(kBlock) void k_multidot(int n, const T* __restrict_
                                                      int nb, const T* __restrict__ z,
                                                      const T* __restrict__ wz, int with_sum,
                                                      int with_self, double* h,
-                                                     double* partials, unsigned* counter) {
+                                                     double* partials) {
   __shared__ T zt[kTile];
   __shared__ double acc[kMaxCols];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1421,7 +1402,7 @@ void launch_multidot(int n, const T* A, int64_t lda, int na, const T* B, int64_t
   int grid = (n + kTile - 1) / kTile;
   if (grid > kStreamGrid) grid = kStreamGrid;
   k_multidot<T><<<grid, kBlock, 0, s>>>(n, A, lda, na, B, ldb, nb, z, wz, with_sum, with_self,
-                                        h, rb.partials, rb.counters + 7);
+                                        h, rb.partials);
   const int nv = na + nb + with_sum + with_self;
   k_values_fin<<<nv, 64, 0, s>>>(nv, grid, rb.partials, h);
   HIP_LAUNCH_CHECK();
@@ -1440,7 +1421,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv_sub(int n, const double* __rest
                                                      int nb, const double* __restrict__ h,
                                                      int with_sum, double* __restrict__ z,
                                                      int with_norm, DevState* st,
-                                                     double* partials, unsigned* counter) {
+                                                     double* partials) {
   __shared__ double sh[kMaxCols];
   const int ncol = na + nb;
   for (int v = threadIdx.x; v < ncol + with_sum; v += kBlock) sh[v] = h[v];
@@ -1463,7 +1444,7 @@ void launch_gemv_sub(int n, const double* A, int64_t lda, int na, const double* 
                      int nb, const double* h, int with_sum, double* z, int with_norm,
                      DevState* st, RedBuf rb, hipStream_t s) {
   k_gemv_sub<<<stream_grid(n), kBlock, 0, s>>>(n, A, lda, na, B, ldb, nb, h, with_sum, z,
-                                               with_norm, st, rb.partials, rb.counters + 8);
+                                               with_norm, st, rb.partials);
   if (with_norm) k_values_fin<<<1, 64, 0, s>>>(1, stream_grid(n), rb.partials, st->red + 2);
   HIP_LAUNCH_CHECK();
 }
@@ -1500,8 +1481,7 @@ __global__ __launch_bounds__(kBlock) void k_ritz_residual(int n, const double* _
                                                           int64_t ld, int k,
                                                           const double* __restrict__ svec,
                                                           double theta, double* __restrict__ r,
-                                                          DevState* st, double* partials,
-                                                          unsigned* counter) {
+                                                          DevState* st, double* partials) {
   __shared__ double sh[ISIRA_MAX_BASIS];
   for (int j = threadIdx.x; j < k; j += kBlock) sh[j] = svec[j];
   __syncthreads();
@@ -1523,7 +1503,7 @@ void launch_ritz_residual(int n, const double* U, const double* W, int64_t ld, i
                           const double* svec, double theta, double* r, DevState* st, RedBuf rb,
                           hipStream_t s) {
   k_ritz_residual<<<stream_grid(n), kBlock, 0, s>>>(n, U, W, ld, k, svec, theta, r, st,
-                                                    rb.partials, rb.counters + 9);
+                                                    rb.partials);
   k_values_fin<<<2, 64, 0, s>>>(2, stream_grid(n), rb.partials, st->red);
   HIP_LAUNCH_CHECK();
 }
