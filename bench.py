@@ -363,6 +363,14 @@ def main():
             variants.append(("fp32_learned", P.isira.FP32, P.isira.PC_LEARNED, fixed))
         variants += [("moving_shift_fp64", P.isira.FP64, P.isira.PC_JACOBI, moving),
                      ("moving_shift_fp32", P.isira.FP32, P.isira.PC_JACOBI, moving)]
+        # multilevel preconditioner (aggregation multigrid for L-hat): set-up once per
+        # graph and trim index, outside the timed solves, reported on its own
+        mlinfo = ctx.ml_setup()
+        out["multilevel_setup"] = {k: mlinfo[k] for k in ("levels", "rows", "connected", "coarsest_dense",
+                                                          "stored_nnz", "device_bytes", "setup_ms")}
+        log(f"multilevel set-up: {out['multilevel_setup']}")
+        variants += [("multilevel_fp64", P.isira.FP64, P.isira.PC_MULTILEVEL, fixed),
+                     ("multilevel_fp32", P.isira.FP32, P.isira.PC_MULTILEVEL, fixed)]
         for name, prec, pc, mode in variants:
             best = None
             for _ in range(max(1, args.steps)):

@@ -54,6 +54,8 @@ extern "C" {
 /* ---- inner preconditioner ---- */
 #define ISIRA_PC_JACOBI 0  /* M-hat_sigma = diag(d - sigma), Remark 3.2, with eq. (3.5) */
 #define ISIRA_PC_LEARNED 1 /* learned sparse approximate inverse, with eq. (3.5) */
+#define ISIRA_PC_MULTILEVEL 2 /* aggregation multigrid V-cycle for L-hat (the multilevel
+                                 slot of Section 3), with eq. (3.5); set up by isira_ml_setup */
 
 /* ---- inner solver ---- */
 #define ISIRA_SOLVER_PCG 0    /* preconditioned conjugate gradients (SPD systems) */
@@ -78,7 +80,7 @@ typedef struct {
   int32_t max_inner;    /* PCG iteration cap per inner solve; default 1000 */
   int32_t max_outer;    /* cap on outer iterations of the whole solve; default 20000 */
   int32_t inner_prec;   /* ISIRA_FP64 (default) or ISIRA_FP32 */
-  int32_t precond;      /* ISIRA_PC_JACOBI (default) or ISIRA_PC_LEARNED */
+  int32_t precond;      /* ISIRA_PC_JACOBI (default), ISIRA_PC_LEARNED or ISIRA_PC_MULTILEVEL */
   int64_t trim_index;   /* trimmed vertex (caller label); -1 = max degree, lowest label on ties */
   double delta;         /* deflation shift; <= 0 selects 2 * max diag(L) (Remark 4.1(ii)) */
   uint64_t seed;        /* seed of the SplitMix64 replacement vectors (breakdowns, default start) */
@@ -219,6 +221,52 @@ int isira_spai_loss_grad(isira_ctx* ctx, const float* params, double sigma, int6
 int isira_adam_step(isira_ctx* ctx, float* param, const float* grad, float* m, float* v,
                     int32_t count, float lr, float beta1, float beta2, float eps,
                     int32_t step);
+
+/* ---- multilevel preconditioner (the multilevel solver slot of Section 3) ----
+ * An unsmoothed-aggregation multigrid V-cycle approximating L-hat^{-1}, L-hat the
+ * Laplacian with the trimmed vertex deleted (eq. (2.4)); Remark 3.2 allows any SPD
+ * approximation of the trimmed operator, and eq. (3.5) adds the deflation term as for
+ * Jacobi.  The shift is not part of the hierarchy, which is built once per trim index.
+ *   Levels: A_0 = L-hat, A_{l+1} = P_l^T A_l P_l with P_l the 0/1 aggregation matrix.
+ *   Aggregation, on the graph of A_l's off-diagonal pattern: a vertex without neighbours
+ *   belongs to no aggregate; the others are visited by decreasing number of neighbours
+ *   (ties: caller label on the finest level, index on coarser ones); a visited vertex
+ *   that is unassigned with all neighbours unassigned forms an aggregate with them (ids in
+ *   order of creation); each vertex left then joins, among these aggregates holding one of
+ *   its neighbours, the one holding the most (ties: smallest id).
+ *   A level with at most coarse_max vertices that have neighbours is the coarsest and is
+ *   solved exactly (dense Cholesky inverse; 1/A_vv for a vertex without neighbours).
+ *   Cycle: one damped Jacobi sweep, weight omega (1 for a vertex without neighbours),
+ *   before and after the coarse correction, from x = 0: symmetric positive definite for
+ *   0 < omega < 1.
+ * The set-up runs on the host (O(nnz) per level) and uploads the matrices of each level's
+ * two sparse products; it replaces any previous hierarchy of the context. */
+#define ISIRA_ML_MAX_LEVELS 32
+typedef struct {
+  double omega;        /* smoothing weight, 0 < omega < 1; default 2/3 */
+  int32_t coarse_max;  /* 0..2048; default 512 (0: coarsen until no vertex has a neighbour) */
+  int32_t max_levels;  /* 1..ISIRA_ML_MAX_LEVELS; default 24 (E_PRECOND if not enough) */
+  int64_t trim_index;  /* caller label of the trimmed vertex; -1 = the default trim vertex */
+} isira_ml_options;
+typedef struct {
+  int32_t levels;                            /* including the finest and the coarsest */
+  int64_t rows[ISIRA_ML_MAX_LEVELS];         /* vertices per level (finest: n - 1) */
+  int64_t offdiag_nnz[ISIRA_ML_MAX_LEVELS];  /* stored off-diagonal entries of A_l */
+  int64_t connected[ISIRA_ML_MAX_LEVELS];    /* vertices with at least one neighbour */
+  int64_t coarsest_dense;                    /* order of the coarsest level's dense inverse */
+  int64_t stored_nnz;                        /* entries of all transfer-product matrices */
+  int64_t device_bytes;                      /* device memory held by the hierarchy */
+  double setup_ms;                           /* host wall time of isira_ml_setup */
+} isira_ml_info;
+int isira_ml_default_options(isira_ml_options* opt);
+/* Build the hierarchy for opt->trim_index (opt may be NULL: defaults).  info: host, may be
+ * NULL.  E_ARG for options out of range, E_PRECOND if max_levels does not suffice. */
+int isira_ml_setup(isira_ctx* ctx, const isira_ml_options* opt, isira_ml_info* info);
+int isira_ml_get_info(const isira_ctx* ctx, isira_ml_info* info);
+/* y = cycle(x-hat) enlarged by a zero at the trimmed vertex; x, y device n FP64, caller
+ * labels (x's trimmed entry is ignored).  prec: ISIRA_FP64, or ISIRA_FP32 (the cycle in
+ * FP32 vectors and matrix values, as inside FP32 inner solves).  E_STATE before set-up. */
+int isira_ml_apply(isira_ctx* ctx, int32_t prec, const double* x, double* y);
 
 const char* isira_strerror(int code);
 const char* isira_last_error(void);

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libisira.so")
 
-SOURCES = ["kernels.hip", "api.hip", "spai.hip", "spai_net.hip", "symeig.cpp"]
+SOURCES = ["kernels.hip", "api.hip", "spai.hip", "spai_net.hip", "multilevel.hip", "symeig.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall",

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "multilevel.h"
 #include "spai.h"
 
 using namespace isira;
@@ -130,6 +131,8 @@ struct isira_ctx {
   double spai_sigma = 0.0;
   int spai_trim = -1;
   bool has_learned = false;
+  // multilevel preconditioner (hierarchy of L-hat for the trim index ml.trim)
+  ml::Hierarchy ml;
   spai::SpaiWork spw;
 };
 
@@ -182,21 +185,18 @@ static void rcm_order(int64_t n, const int32_t* rp, const int32_t* col,
   }
 }
 
-// SpMV work units from the relabelled CSR (rows by decreasing length, or in reverse
-// Cuthill-McKee order when no row is longer than a stream unit): rows longer than
-// the unit size are cut into chunks; the remaining rows are packed greedily, in order, into
-// stream units of at most unit-size nonzeros and a row limit.  A stream unit sums each row
-// with G lanes, G the smallest power of two >= (longest row) / 8, capped at 64.  Graphs
-// whose gathers concentrate on the highest-degree labels use the hub-cached shape.
-static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp,
-                      const std::vector<int32_t>& col) {
-  const int n = (int)ctx->n;
-  SpmvPlan& P = ctx->plan;
-  // power-law test: share of the gathers that hit the first kHubX64 labels (the
-  // highest-degree vertices after relabelling)
+// SpMV work units of a CSR matrix with n rows (the relabelled Laplacian: rows by
+// decreasing length, or in reverse Cuthill-McKee order; a multilevel transfer matrix: any
+// order): a row longer than the unit size is cut into chunks; runs of the other rows are
+// packed greedily, in order, into stream units of at most unit-size nonzeros and a row
+// limit.  A stream unit sums each row with G lanes, G the smallest power of two >=
+// (longest row) / 8, capped at 64.  Matrices whose gathers concentrate on the first kHubX64
+// columns (the highest-degree vertices after relabelling) use the hub-cached shape.
+int isira::build_spmv_plan(int n, const int32_t* rp, const int32_t* col, SpmvPlan& P) {
+  const int64_t nnz = rp[n];
   int64_t hits = 0;
-  for (size_t j = 0; j < col.size(); ++j) hits += col[j] < kHubX64;
-  P.hub = (n > 4 * kHubX64 && (double)hits >= 0.25 * (double)col.size()) ? 1 : 0;
+  for (int64_t j = 0; j < nnz; ++j) hits += col[j] < kHubX64;
+  P.hub = (n > 4 * kHubX64 && (double)hits >= 0.25 * (double)nnz) ? 1 : 0;
   const int unnz = P.hub ? kHubUnitNnz : kUnitNnz;
   const int urows = P.hub ? kHubUnitRows : kUnitRows;
   const int chunk = unnz;  // nonzeros per piece of a long row
@@ -204,26 +204,29 @@ static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp,
   std::vector<int32_t> rowof, base, nch;
   int nchunks = 0;
   int row = 0;
-  while (row < n && rp[row + 1] - rp[row] > unnz) {
-    const int len = rp[row + 1] - rp[row];
-    const int nc = (len + chunk - 1) / chunk;
-    rowof.push_back(row);
-    base.push_back(nchunks);
-    nch.push_back(nc);
-    for (int c = 0; c < nc; ++c) {
-      const int j0 = rp[row] + c * chunk;
-      const int j1 = std::min(rp[row + 1], j0 + chunk);
-      units.push_back(make_int4(row, j0, j1, -(nchunks + c + 1)));
-    }
-    nchunks += nc;
-    ++row;
-  }
   while (row < n) {
+    const int len = rp[row + 1] - rp[row];
+    if (len > unnz) {
+      const int nc = (len + chunk - 1) / chunk;
+      rowof.push_back(row);
+      base.push_back(nchunks);
+      nch.push_back(nc);
+      for (int c = 0; c < nc; ++c) {
+        const int j0 = rp[row] + c * chunk;
+        const int j1 = std::min(rp[row + 1], j0 + chunk);
+        units.push_back(make_int4(row, j0, j1, -(nchunks + c + 1)));
+      }
+      nchunks += nc;
+      ++row;
+      continue;
+    }
     const int r0 = row;
-    int lmax = 0, nnz = 0;
-    while (row < n && row - r0 < urows && nnz + (rp[row + 1] - rp[row]) <= unnz) {
-      nnz += rp[row + 1] - rp[row];
-      lmax = std::max(lmax, rp[row + 1] - rp[row]);
+    int lmax = 0, cnt = 0;
+    while (row < n && row - r0 < urows) {
+      const int l = rp[row + 1] - rp[row];
+      if (l > unnz || cnt + l > unnz) break;
+      cnt += l;
+      lmax = std::max(lmax, l);
       ++row;
     }
     int G = 1;
@@ -241,13 +244,20 @@ static int build_plan(isira_ctx* ctx, const std::vector<int32_t>& rp,
   if ((rc = dalloc(&P.split_nchunk, rowof.size()))) return rc;
   if ((rc = dalloc(&P.split_part, (size_t)nchunks))) return rc;
   if ((rc = dalloc(&P.split_red, rowof.size()))) return rc;
-  CKH(hipMemcpy(P.units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice));
+  if (!units.empty())
+    CKH(hipMemcpy(P.units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice));
   if (!rowof.empty()) {
     CKH(hipMemcpy(P.split_rowof, rowof.data(), rowof.size() * 4, hipMemcpyHostToDevice));
     CKH(hipMemcpy(P.split_base, base.data(), base.size() * 4, hipMemcpyHostToDevice));
     CKH(hipMemcpy(P.split_nchunk, nch.data(), nch.size() * 4, hipMemcpyHostToDevice));
   }
   return ISIRA_OK;
+}
+
+void isira::free_spmv_plan(SpmvPlan& P) {
+  dfree(P.units); dfree(P.split_base); dfree(P.split_nchunk); dfree(P.split_rowof);
+  dfree(P.split_part); dfree(P.split_red);
+  P = SpmvPlan{};
 }
 
 static void free_workspace(isira_ctx* c) {
@@ -486,7 +496,7 @@ extern "C" int isira_create(isira_ctx** out, int64_t n, int64_t nnz, const int32
       hipMemsetAsync(ctx->st, 0, sizeof(DevState), s) ||
       hipMemsetAsync(ctx->deg, 0, ctx->ld * 8, s) || hipMemsetAsync(ctx->deg32, 0, ctx->ld * 4, s))
     return cleanup(fail(ISIRA_E_HIP, "memset failed"));
-  if ((rc = build_plan(ctx, rp2, col2))) return cleanup(rc);
+  if ((rc = build_spmv_plan((int)n, rp2.data(), col2.data(), ctx->plan))) return cleanup(rc);
   // degrees, trim index (Remark 4.1(i)) and delta (Remark 4.1(ii)) on the GPU
   launch_degree(ctx->rp, w_dtype == ISIRA_W_NONE ? nullptr : (w_dtype == ISIRA_W_F32 ? (const void*)ctx->w32 : (const void*)ctx->w64),
                 w_dtype == ISIRA_W_NONE ? ISIRA_W_NONE : (w_dtype == ISIRA_W_F32 ? ISIRA_W_F32 : ISIRA_W_F64),
@@ -509,12 +519,11 @@ extern "C" void isira_destroy(isira_ctx* c) {
   free_workspace(c);
   dfree(c->rp); dfree(c->col); dfree(c->w64); dfree(c->w32); dfree(c->deg); dfree(c->deg32);
   dfree(c->d_perm); dfree(c->d_iperm); dfree(c->d_emap);
-  dfree(c->plan.units); dfree(c->plan.split_base); dfree(c->plan.split_nchunk);
-  dfree(c->plan.split_rowof);
-  dfree(c->plan.split_part); dfree(c->plan.split_red);
+  free_spmv_plan(c->plan);
   dfree(c->rb.partials); dfree(c->rb.counters); dfree(c->st); dfree(c->hbuf); dfree(c->scal4);
   dfree(c->svec); dfree(c->Sdev); dfree(c->Ginv);
   spai::free_work(c->spw);
+  ml::release(c->ml);
   if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->hbuf_host) (void)hipHostFree(c->hbuf_host);
   if (c->up_host) (void)hipHostFree(c->up_host);
@@ -646,7 +655,7 @@ bool spd_inverse(int c, const std::vector<double>& G, std::vector<double>& Ginv)
 // Inner-solve configuration of one solve.
 struct InnerCfg {
   int prec;     // ISIRA_FP64 / ISIRA_FP32
-  int precond;  // ISIRA_PC_JACOBI / ISIRA_PC_LEARNED
+  int precond;  // ISIRA_PC_JACOBI / ISIRA_PC_LEARNED / ISIRA_PC_MULTILEVEL
   double sigma, delta, rtol;
   int trim;     // internal index
   int maxit, check_every;
@@ -733,6 +742,7 @@ void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
   const PcgBufs<T> b = pcg_bufs<T>(c);
   hipStream_t s = c->stream;
   const bool learned = cfg.precond == ISIRA_PC_LEARNED;
+  const bool multilevel = cfg.precond == ISIRA_PC_MULTILEVEL;
   const int vm = sizeof(T) == 8 ? valmode64(c) : valmode32(c);
   SpmvArgs<T> a{};
   a.rp = c->rp;
@@ -772,6 +782,15 @@ void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
                                   sig_over_n, first, c->st, c->rb, s);
       spai::apply<T>(c->spw, c->plan, c->rp, c->col, b.r, b.y, n, cfg.trim, b.V, c->ld, nc,
                      c->st, c->rb, s);
+      launch_spai_finish_rho(nc, c->Ginv, cfg.delta, first, c->st, s);
+      launch_pcg_update2_learned<T>(n, b.y, b.p, b.Y, c->ld, nc, b.V, cfg.delta, first, c->st,
+                                    c->rb, s);
+    } else if (multilevel) {
+      // y = cycle(r) with the dots V-hat^T y and r^T y, then eq. (3.5)
+      launch_pcg_update1_plain<T>(n, b.x, b.r, b.p, b.q, b.V, c->ld, nc, cfg.delta, cfg.trim,
+                                  sig_over_n, first, c->st, c->rb, s);
+      ml::apply<T>(c->ml, b.r, b.y, 1, c->st, c->rb, s);
+      launch_multidot<T>(n, b.V, c->ld, nc, b.r, c->ld, 1, b.y, nullptr, 0, 0, c->st->t2, c->rb, s);
       launch_spai_finish_rho(nc, c->Ginv, cfg.delta, first, c->st, s);
       launch_pcg_update2_learned<T>(n, b.y, b.p, b.Y, c->ld, nc, b.V, cfg.delta, first, c->st,
                                     c->rb, s);
@@ -882,7 +901,8 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
   if (!evals || !evecs || !resid) return fail(ISIRA_E_ARG, "NULL output");
   if (opt.inner_prec != ISIRA_FP64 && opt.inner_prec != ISIRA_FP32) return fail(ISIRA_E_ARG, "bad inner_prec");
   if (opt.precond == ISIRA_PC_LEARNED && (!c->has_learned)) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
-  if (opt.precond != ISIRA_PC_JACOBI && opt.precond != ISIRA_PC_LEARNED) return fail(ISIRA_E_ARG, "bad precond");
+  if (opt.precond != ISIRA_PC_JACOBI && opt.precond != ISIRA_PC_LEARNED && opt.precond != ISIRA_PC_MULTILEVEL)
+    return fail(ISIRA_E_ARG, "bad precond");
   int trim = c->trim_default;
   if (opt.trim_index >= 0) {
     if (opt.trim_index >= n) return fail(ISIRA_E_ARG, "trim_index out of range");
@@ -895,6 +915,10 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
   const bool moving = opt.shift_mode == ISIRA_SHIFT_MOVING;
   if (moving && opt.precond == ISIRA_PC_LEARNED)
     return fail(ISIRA_E_PRECOND, "the learned preconditioner is built for one shift; it cannot follow a moving shift");
+  if (opt.precond == ISIRA_PC_MULTILEVEL && (!c->ml.ready || c->ml.trim != trim))
+    return fail(ISIRA_E_PRECOND, "no multilevel hierarchy set up for this trim index");
+  if (moving && opt.precond == ISIRA_PC_MULTILEVEL)
+    return fail(ISIRA_E_PRECOND, "the moving shift runs MINRES with the Jacobi preconditioner only");
   const double delta = opt.delta > 0 ? opt.delta : 2.0 * c->max_deg;
   int rc = ensure_workspace(c, m, k);
   if (rc) return rc;
@@ -978,7 +1002,15 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
   auto refresh_smw = [&](int cnew) -> int {
     // new column cnew of C = V-hat^T P0 V-hat (P0 = M^-1 Jacobi or learned M); then G^-1
     const int cc = cnew + 1;
-    if (cfg.precond == ISIRA_PC_LEARNED) {
+    if (cfg.precond == ISIRA_PC_MULTILEVEL) {
+      if (cfg.prec == ISIRA_FP64) {
+        ml::apply<double>(c->ml, c->Vin64 + (size_t)cnew * ld, c->Y64 + (size_t)cnew * ld, 0, c->st, c->rb, s);
+        launch_multidot<double>(n, c->Vin64, ld, cc, nullptr, ld, 0, c->Y64 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+      } else {
+        ml::apply<float>(c->ml, c->Vin32 + (size_t)cnew * ld, c->Y32 + (size_t)cnew * ld, 0, c->st, c->rb, s);
+        launch_multidot<float>(n, c->Vin32, ld, cc, nullptr, ld, 0, c->Y32 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+      }
+    } else if (cfg.precond == ISIRA_PC_LEARNED) {
       if (cfg.prec == ISIRA_FP64) {
         spai::apply_plain<double>(c->spw, c->plan, c->rp, c->col,
                                   c->Vin64 + (size_t)cnew * ld, c->Y64 + (size_t)cnew * ld, n, trim, s);
@@ -1312,6 +1344,8 @@ extern "C" int isira_inner_solve(isira_ctx* c, const double* r, const double* V,
   if (solver != ISIRA_SOLVER_PCG && solver != ISIRA_SOLVER_MINRES) return fail(ISIRA_E_ARG, "bad solver");
   if (solver == ISIRA_SOLVER_MINRES && precond != ISIRA_PC_JACOBI)
     return fail(ISIRA_E_ARG, "MINRES runs with the Jacobi preconditioner only");
+  if (precond != ISIRA_PC_JACOBI && precond != ISIRA_PC_LEARNED && precond != ISIRA_PC_MULTILEVEL)
+    return fail(ISIRA_E_ARG, "bad precond");
   int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, std::max(1, (int)nc)));
   if (rc) return rc;
   const int n = (int)c->n;
@@ -1326,6 +1360,8 @@ extern "C" int isira_inner_solve(isira_ctx* c, const double* r, const double* V,
   cfg.trim = trim >= 0 ? c->iperm[trim] : c->trim_default;
   if (precond == ISIRA_PC_LEARNED && (c->spai_trim != cfg.trim || c->spai_sigma != sigma))
     return fail(ISIRA_E_PRECOND, "learned preconditioner was installed for another sigma or trim index");
+  if (precond == ISIRA_PC_MULTILEVEL && (!c->ml.ready || c->ml.trim != cfg.trim))
+    return fail(ISIRA_E_PRECOND, "no multilevel hierarchy set up for this trim index");
   cfg.maxit = max_it > 0 ? max_it : 1000;
   cfg.check_every = 8;
   cfg.solver = solver;
@@ -1339,7 +1375,15 @@ extern "C" int isira_inner_solve(isira_ctx* c, const double* r, const double* V,
     launch_masked_copy<float>(n, c->tmp64, cfg.trim, c->Vin32 + (size_t)j * ld, s);
   }
   for (int j = 0; j < nc; ++j) {
-    if (precond == ISIRA_PC_LEARNED) {
+    if (precond == ISIRA_PC_MULTILEVEL) {
+      if (prec == ISIRA_FP64) {
+        ml::apply<double>(c->ml, c->Vin64 + (size_t)j * ld, c->Y64 + (size_t)j * ld, 0, c->st, c->rb, s);
+        launch_multidot<double>(n, c->Vin64, ld, nc, nullptr, ld, 0, c->Y64 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+      } else {
+        ml::apply<float>(c->ml, c->Vin32 + (size_t)j * ld, c->Y32 + (size_t)j * ld, 0, c->st, c->rb, s);
+        launch_multidot<float>(n, c->Vin32, ld, nc, nullptr, ld, 0, c->Y32 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+      }
+    } else if (precond == ISIRA_PC_LEARNED) {
       if (prec == ISIRA_FP64) {
         spai::apply_plain<double>(c->spw, c->plan, c->rp, c->col,
                                   c->Vin64 + (size_t)j * ld, c->Y64 + (size_t)j * ld, n, cfg.trim, s);
@@ -1397,6 +1441,90 @@ extern "C" int isira_orthonormalize(isira_ctx* c, const double* Q, int32_t ncols
   launch_scale(n, c->z64, norms[1] > 0 ? 1.0 / norms[1] : 0.0, c->tmp64, s);
   launch_gather<double, double>(n, c->tmp64, c->d_iperm, u, s);
   SYNC_OR_RETURN(c);
+  return ISIRA_OK;
+}
+
+// ------------------------------------------------------------------------------ multilevel
+
+extern "C" int isira_ml_default_options(isira_ml_options* o) {
+  if (!o) return fail(ISIRA_E_ARG, "NULL argument");
+  std::memset(o, 0, sizeof(*o));
+  o->omega = 2.0 / 3.0;
+  o->coarse_max = 512;
+  o->max_levels = 24;
+  o->trim_index = -1;
+  return ISIRA_OK;
+}
+
+static void fill_ml_info(const ml::Hierarchy& H, isira_ml_info* info) {
+  std::memset(info, 0, sizeof(*info));
+  info->levels = (int32_t)H.rows.size();
+  for (size_t l = 0; l < H.rows.size() && l < ISIRA_ML_MAX_LEVELS; ++l) {
+    info->rows[l] = H.rows[l];
+    info->offdiag_nnz[l] = H.offnnz[l];
+    info->connected[l] = H.connected[l];
+  }
+  info->coarsest_dense = H.mL;
+  info->stored_nnz = H.stored_nnz;
+  info->device_bytes = H.device_bytes;
+  info->setup_ms = H.setup_ms;
+}
+
+extern "C" int isira_ml_setup(isira_ctx* c, const isira_ml_options* opt, isira_ml_info* info) {
+  if (!c) return fail(ISIRA_E_ARG, "NULL context");
+  isira_ml_options o;
+  isira_ml_default_options(&o);
+  if (opt) o = *opt;
+  if (!(o.omega > 0.0 && o.omega < 1.0)) return fail(ISIRA_E_ARG, "need 0 < omega < 1");
+  if (o.coarse_max < 0 || o.coarse_max > 2048) return fail(ISIRA_E_ARG, "need 0 <= coarse_max <= 2048");
+  if (o.max_levels < 1 || o.max_levels > ISIRA_ML_MAX_LEVELS) return fail(ISIRA_E_ARG, "need 1 <= max_levels <= ISIRA_ML_MAX_LEVELS");
+  if (o.trim_index >= c->n) return fail(ISIRA_E_ARG, "trim_index out of range");
+  const int n = (int)c->n;
+  const int trim = o.trim_index >= 0 ? c->iperm[o.trim_index] : c->trim_default;
+  std::vector<int32_t> rp((size_t)n + 1), col((size_t)c->nnz);
+  std::vector<double> w;
+  CKH(hipStreamSynchronize(c->stream));
+  CKH(hipMemcpy(rp.data(), c->rp, rp.size() * 4, hipMemcpyDeviceToHost));
+  CKH(hipMemcpy(col.data(), c->col, col.size() * 4, hipMemcpyDeviceToHost));
+  if (c->wdt != ISIRA_W_NONE) {
+    w.resize((size_t)c->nnz);
+    CKH(hipMemcpy(w.data(), c->w64, w.size() * 8, hipMemcpyDeviceToHost));
+  }
+  ml::Params prm{o.omega, o.coarse_max, o.max_levels};
+  const int rc = ml::setup(c->ml, n, rp.data(), col.data(), w.empty() ? nullptr : w.data(),
+                           c->perm.data(), trim, prm);
+  if (rc) return rc;
+  if (info) fill_ml_info(c->ml, info);
+  return ISIRA_OK;
+}
+
+extern "C" int isira_ml_apply(isira_ctx* c, int32_t prec, const double* x, double* y) {
+  if (!c || !x || !y) return fail(ISIRA_E_ARG, "NULL argument");
+  if (prec != ISIRA_FP64 && prec != ISIRA_FP32) return fail(ISIRA_E_ARG, "bad prec");
+  if (!c->ml.ready) return fail(ISIRA_E_STATE, "no multilevel hierarchy set up");
+  int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
+  if (rc) return rc;
+  const int n = (int)c->n;
+  hipStream_t s = c->stream;
+  launch_gather<double, double>(n, x, c->d_perm, c->tmp64, s);
+  if (prec == ISIRA_FP64) {
+    launch_masked_copy<double>(n, c->tmp64, c->ml.trim, c->ri64, s);
+    ml::apply<double>(c->ml, c->ri64, c->y64, 0, c->st, c->rb, s);
+    launch_gather<double, double>(n, c->y64, c->d_iperm, y, s);
+  } else {
+    launch_masked_copy<float>(n, c->tmp64, c->ml.trim, c->ri32, s);
+    ml::apply<float>(c->ml, c->ri32, c->y32, 0, c->st, c->rb, s);
+    launch_gather<float, double>(n, c->y32, c->d_iperm, y, s);
+  }
+  CKH(hipGetLastError());
+  SYNC_OR_RETURN(c);
+  return ISIRA_OK;
+}
+
+extern "C" int isira_ml_get_info(const isira_ctx* c, isira_ml_info* info) {
+  if (!c || !info) return fail(ISIRA_E_ARG, "NULL argument");
+  if (!c->ml.ready) return fail(ISIRA_E_STATE, "no multilevel hierarchy set up");
+  fill_ml_info(c->ml, info);
   return ISIRA_OK;
 }
 

@@ -114,8 +114,13 @@ struct SpmvPlan {
   double* split_red = nullptr;     // per split row slot: reduction contribution
 };
 
+// Work units of the sparse product for a CSR matrix of n rows (host arrays); the plan's
+// device arrays are allocated here and released by free_spmv_plan.
+int build_spmv_plan(int n, const int32_t* rp, const int32_t* col, SpmvPlan& P);
+void free_spmv_plan(SpmvPlan& P);
+
 // Value mode of the sparse product y = diag .* x + sgn * sum_j v_ij x_j.
-enum ValMode { kUnitNeg = 0, kF32Neg = 1, kF64Neg = 2, kF32Pos = 3 };
+enum ValMode { kUnitNeg = 0, kF32Neg = 1, kF64Neg = 2, kF32Pos = 3, kF64Pos = 4 };
 
 // Arguments of the fused sparse product.
 template <typename T>

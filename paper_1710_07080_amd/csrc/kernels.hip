@@ -248,7 +248,7 @@ template <int VM, typename T>
 __device__ __forceinline__ T edge_val(const void* vals, int j) {
   if constexpr (VM == kUnitNeg) {
     return T(1);
-  } else if constexpr (VM == kF64Neg) {
+  } else if constexpr (VM == kF64Neg || VM == kF64Pos) {
     return (T)((const double*)vals)[j];
   } else {
     return (T)((const float*)vals)[j];
@@ -261,7 +261,7 @@ template <int VM, typename T>
 __device__ __forceinline__ double finish_row_xd(const SpmvArgs<T>& a, int row, T nsum, T xl,
                                                 T dl, const double* sh_t, T shift_add) {
   T y = dl * xl;
-  if constexpr (VM == kF32Pos) {
+  if constexpr (VM == kF32Pos || VM == kF64Pos) {
     y += nsum;
   } else {
     y -= nsum;
@@ -582,6 +582,7 @@ void launch_spmv(const SpmvPlan& plan, int valmode, const SpmvArgs<T>& a, RedBuf
     case kUnitNeg: spmv_dispatch<T, kUnitNeg, 0>(plan, a, part, s); break;
     case kF32Neg: spmv_dispatch<T, kF32Neg, 0>(plan, a, part, s); break;
     case kF64Neg: spmv_dispatch<T, kF64Neg, 0>(plan, a, part, s); break;
+    case kF64Pos: spmv_dispatch<T, kF64Pos, 0>(plan, a, part, s); break;
     default: spmv_dispatch<T, kF32Pos, 0>(plan, a, part, s); break;
   }
   HIP_LAUNCH_CHECK();

@@ -1,0 +1,580 @@
+// Multilevel preconditioner: host-side hierarchy set-up (aggregation, Galerkin coarse
+// matrices, the composite transfer matrices of the V-cycle, the coarsest-level inverse)
+// and the device-side cycle.
+//
+// Definition of the cycle (the multilevel slot of Section 3, with Remark 3.2):
+//   A_0 = L-hat (vertex `trim` deleted), A_{l+1} = P_l^T A_l P_l, P_l the 0/1 aggregation
+//   matrix.  Aggregation of a level, on the graph of A_l's off-diagonal pattern: a vertex
+//   without neighbours belongs to no aggregate; the others are visited by decreasing
+//   number of neighbours (ties: caller label on level 0, index on coarser levels); phase 1:
+//   a visited vertex that is unassigned and whose neighbours are all unassigned forms a new
+//   aggregate with them (ids in order of creation); phase 2: each vertex left joins, among
+//   the phase-1 aggregates holding a neighbour, the one holding the most, ties by the
+//   smallest id.  No floating-point value enters the rule.  A level with at most coarse_max
+//   vertices that have neighbours is the coarsest and is solved exactly.  Smoothing: one
+//   damped Jacobi sweep with S = W D^-1 (w_v = omega, or 1 for a vertex without neighbours)
+//   before and after the coarse correction, from x = 0.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "multilevel.h"
+
+namespace isira {
+namespace ml {
+namespace {
+
+int err(int code, const std::string& m) { return set_error(code, m.c_str()); }
+
+#define MLCK(expr)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return err(ISIRA_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+template <typename T>
+int dal(T** p, size_t count, int64_t& bytes) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess)
+    return err(ISIRA_E_HIP, std::string("hipMalloc(") + std::to_string(count * sizeof(T)) +
+                                " bytes): " + hipGetErrorString(e));
+  bytes += (int64_t)(count * sizeof(T));
+  return ISIRA_OK;
+}
+
+template <typename T>
+int put(T* d, const std::vector<T>& h) {
+  if (!h.empty()) MLCK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return ISIRA_OK;
+}
+
+template <typename T>
+void dfr(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+// One level on the host: A_ij = -w for the stored off-diagonal entries, A_ii = diag.
+struct HostLevel {
+  int n = 0;
+  std::vector<int32_t> rp, col;
+  std::vector<double> w, diag;
+  std::vector<uint8_t> active;  // 0 only for the trimmed vertex of level 0
+  int rowlen(int i) const { return rp[i + 1] - rp[i]; }
+};
+
+// Aggregate ids (creation order) of the vertices of A; -1 for a vertex without
+// neighbours.  by_key lists the vertices in increasing tie-break key.  Returns the count.
+int aggregate(const HostLevel& A, const std::vector<int32_t>& by_key, std::vector<int32_t>& agg) {
+  const int n = A.n;
+  int maxlen = 0;
+  for (int i = 0; i < n; ++i) maxlen = std::max(maxlen, A.rowlen(i));
+  // visiting order: decreasing row length, ties by key (stable counting sort of by_key)
+  std::vector<int32_t> start((size_t)maxlen + 2, 0), order;
+  order.reserve(n);
+  for (int v : by_key)
+    if (A.rowlen(v) > 0) start[maxlen - A.rowlen(v) + 1]++;
+  for (int b = 1; b <= maxlen + 1; ++b) start[b] += start[b - 1];
+  order.assign(start[maxlen + 1], 0);
+  for (int v : by_key) {
+    const int l = A.rowlen(v);
+    if (l > 0) order[start[maxlen - l]++] = v;
+  }
+  agg.assign(n, -1);
+  int nagg = 0;
+  for (int v : order) {  // phase 1
+    if (agg[v] >= 0) continue;
+    bool free_nb = true;
+    for (int e = A.rp[v]; e < A.rp[v + 1] && free_nb; ++e) free_nb = agg[A.col[e]] < 0;
+    if (!free_nb) continue;
+    agg[v] = nagg;
+    for (int e = A.rp[v]; e < A.rp[v + 1]; ++e) agg[A.col[e]] = nagg;
+    ++nagg;
+  }
+  std::vector<int32_t> phase1 = agg, ids;
+  for (int v = 0; v < n; ++v) {  // phase 2
+    if (phase1[v] >= 0 || A.rowlen(v) == 0) continue;
+    ids.clear();
+    for (int e = A.rp[v]; e < A.rp[v + 1]; ++e)
+      if (phase1[A.col[e]] >= 0) ids.push_back(phase1[A.col[e]]);
+    std::sort(ids.begin(), ids.end());
+    int best = -1, best_cnt = 0;
+    for (size_t a = 0; a < ids.size();) {
+      size_t b = a;
+      while (b < ids.size() && ids[b] == ids[a]) ++b;
+      if ((int)(b - a) > best_cnt) {  // ascending ids: the first maximum is the smallest id
+        best_cnt = (int)(b - a);
+        best = ids[a];
+      }
+      a = b;
+    }
+    agg[v] = best;  // >= 0: a vertex skipped in phase 1 has a phase-1 neighbour
+  }
+  return nagg;
+}
+
+// Galerkin coarse level P^T A P for the aggregation agg (nc aggregates).
+HostLevel coarsen(const HostLevel& A, const std::vector<int32_t>& agg, int nc) {
+  HostLevel C;
+  C.n = nc;
+  std::vector<int32_t> mptr((size_t)nc + 1, 0), mem;
+  for (int i = 0; i < A.n; ++i)
+    if (agg[i] >= 0) mptr[agg[i] + 1]++;
+  for (int a = 0; a < nc; ++a) mptr[a + 1] += mptr[a];
+  mem.assign(mptr[nc], 0);
+  {
+    std::vector<int32_t> fill(mptr.begin(), mptr.end() - 1);
+    for (int i = 0; i < A.n; ++i)
+      if (agg[i] >= 0) mem[fill[agg[i]]++] = i;
+  }
+  C.rp.assign((size_t)nc + 1, 0);
+  C.diag.assign(nc, 0.0);
+  C.active.assign(nc, 1);
+  std::vector<int32_t> pos(nc, -1), touched;
+  std::vector<double> acc;
+  for (int a = 0; a < nc; ++a) {
+    double dg = 0.0;
+    touched.clear();
+    acc.clear();
+    for (int k = mptr[a]; k < mptr[a + 1]; ++k) {
+      const int i = mem[k];
+      dg += A.diag[i];
+      for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+        const int b = agg[A.col[e]];
+        if (b == a) {
+          dg -= A.w[e];
+        } else {
+          if (pos[b] < 0) {
+            pos[b] = (int)touched.size();
+            touched.push_back(b);
+            acc.push_back(0.0);
+          }
+          acc[pos[b]] += A.w[e];
+        }
+      }
+    }
+    C.diag[a] = dg;
+    std::vector<int32_t> idx(touched.size());
+    for (size_t t = 0; t < idx.size(); ++t) idx[t] = (int32_t)t;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return touched[x] < touched[y]; });
+    for (int t : idx) {
+      C.col.push_back(touched[t]);
+      C.w.push_back(acc[t]);
+    }
+    C.rp[a + 1] = (int32_t)C.col.size();
+    for (int b : touched) pos[b] = -1;
+  }
+  return C;
+}
+
+// In-place inverse of an SPD row-major m x m matrix by Cholesky (A = L L^T, X = L^-1,
+// A^-1 = X^T X).  Returns false when a pivot is not positive.
+bool spd_inverse_rowmajor(int m, std::vector<double>& A) {
+  std::vector<double> L((size_t)m * m, 0.0), X((size_t)m * m, 0.0);
+  for (int j = 0; j < m; ++j) {
+    double s = A[(size_t)j * m + j];
+    for (int k = 0; k < j; ++k) s -= L[(size_t)j * m + k] * L[(size_t)j * m + k];
+    if (!(s > 0.0)) return false;
+    const double ljj = std::sqrt(s);
+    L[(size_t)j * m + j] = ljj;
+    for (int i = j + 1; i < m; ++i) {
+      double v = A[(size_t)i * m + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * m + k] * L[(size_t)j * m + k];
+      L[(size_t)i * m + j] = v / ljj;
+    }
+  }
+  // X = L^-1 (lower), row by row: X[i][j] = -(sum_{k=j}^{i-1} L[i][k] X[k][j]) / L[i][i]
+  for (int i = 0; i < m; ++i) {
+    X[(size_t)i * m + i] = 1.0 / L[(size_t)i * m + i];
+    for (int j = 0; j < i; ++j) {
+      double v = 0.0;
+      for (int k = j; k < i; ++k) v += L[(size_t)i * m + k] * X[(size_t)k * m + j];
+      X[(size_t)i * m + j] = -v / L[(size_t)i * m + i];
+    }
+  }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v = 0.0;
+      for (int k = i; k < m; ++k) v += X[(size_t)k * m + i] * X[(size_t)k * m + j];
+      A[(size_t)i * m + j] = A[(size_t)j * m + i] = v;
+    }
+  return true;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ml_coarse(int nL, int mL, const int32_t* __restrict__ cidx,
+                                                   const int32_t* __restrict__ cpos,
+                                                   const double* __restrict__ Ainv,
+                                                   const double* __restrict__ cdinv,
+                                                   const T* __restrict__ b, T* __restrict__ out,
+                                                   const DevState* st, int check_done) {
+  if (check_done && st->done) return;
+  // one wave per row; row and its dense position are uniform within the wave
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= nL) return;
+  const int p = cpos[row];
+  if (p < 0) {
+    if (lane == 0) out[row] = (T)(cdinv[row] * (double)b[row]);
+    return;
+  }
+  const double* __restrict__ a = Ainv + (size_t)p * mL;
+  double s = 0.0;
+  for (int l = lane; l < mL; l += 64) s += a[l] * (double)b[cidx[l]];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) out[row] = (T)s;
+}
+
+// The two transfer products of one level on the host (see Level).
+struct HostMats {
+  int ld = 0;
+  std::vector<int32_t> drp, dcol, urp, ucol;
+  std::vector<double> dval, uval, udiag;
+};
+
+HostMats build_level_mats(const HostLevel& A, const std::vector<int32_t>& agg, int nc,
+                          double omega) {
+  const int n = A.n;
+  HostMats M;
+  M.ld = (n + 63) / 64 * 64;
+  // smoother weights s_i = w_i / A_ii
+  std::vector<double> s(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    if (A.active[i]) s[i] = (A.rowlen(i) > 0 ? omega : 1.0) / A.diag[i];
+  // Q = (I - S A) P: row i, column b: [agg_i == b] (1 - s_i A_ii) + s_i sum_{j in b} w_ij
+  std::vector<int32_t> qrp((size_t)n + 1, 0), qcol;
+  std::vector<double> qval;
+  std::vector<int32_t> pos(nc, -1), touched;
+  std::vector<double> acc;
+  for (int i = 0; i < n; ++i) {
+    if (agg[i] >= 0) {
+      touched.clear();
+      acc.clear();
+      auto add = [&](int b, double v) {
+        if (pos[b] < 0) {
+          pos[b] = (int)touched.size();
+          touched.push_back(b);
+          acc.push_back(0.0);
+        }
+        acc[pos[b]] += v;
+      };
+      add(agg[i], 1.0 - s[i] * A.diag[i]);
+      for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) add(agg[A.col[e]], s[i] * A.w[e]);
+      std::vector<int32_t> idx(touched.size());
+      for (size_t t = 0; t < idx.size(); ++t) idx[t] = (int32_t)t;
+      std::sort(idx.begin(), idx.end(), [&](int x, int y) { return touched[x] < touched[y]; });
+      for (int t : idx) {
+        qcol.push_back(touched[t]);
+        qval.push_back(acc[t]);
+      }
+      for (int b : touched) pos[b] = -1;
+    }
+    qrp[i + 1] = (int32_t)qcol.size();
+  }
+  // up = [M | Q], M = 2S - S A S: off-diagonal s_i w_ij s_j, diagonal 2 s_i - s_i^2 A_ii
+  M.urp.assign((size_t)n + 1, 0);
+  M.udiag.assign(n, 0.0);
+  M.ucol.reserve(A.col.size() + qcol.size());
+  M.uval.reserve(A.col.size() + qcol.size());
+  for (int i = 0; i < n; ++i) {
+    for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      M.ucol.push_back(A.col[e]);
+      M.uval.push_back(s[i] * A.w[e] * s[A.col[e]]);
+    }
+    for (int e = qrp[i]; e < qrp[i + 1]; ++e) {
+      M.ucol.push_back(M.ld + qcol[e]);
+      M.uval.push_back(qval[e]);
+    }
+    M.urp[i + 1] = (int32_t)M.ucol.size();
+    if (A.active[i]) M.udiag[i] = 2.0 * s[i] - s[i] * s[i] * A.diag[i];
+  }
+  // down = Q^T (rows = aggregates, columns increasing)
+  M.drp.assign((size_t)nc + 1, 0);
+  M.dcol.assign(qcol.size(), 0);
+  M.dval.assign(qcol.size(), 0.0);
+  for (int32_t b : qcol) M.drp[b + 1]++;
+  for (int b = 0; b < nc; ++b) M.drp[b + 1] += M.drp[b];
+  std::vector<int32_t> fill(M.drp.begin(), M.drp.end() - 1);
+  for (int i = 0; i < n; ++i)
+    for (int e = qrp[i]; e < qrp[i + 1]; ++e) {
+      const int k = fill[qcol[e]]++;
+      M.dcol[k] = i;
+      M.dval[k] = qval[e];
+    }
+  return M;
+}
+
+// The coarsest level's exact solve on the host: dense inverse over its vertices with
+// neighbours, 1/A_vv for the others (0 for an inactive vertex).
+struct HostCoarsest {
+  int n = 0, m = 0;
+  std::vector<int32_t> cidx, cpos;
+  std::vector<double> Ainv, cdinv;
+};
+
+int build_coarsest(const HostLevel& A, HostCoarsest& C) {
+  const int n = A.n;
+  C.n = n;
+  C.cidx.clear();
+  C.cpos.assign(n, -1);
+  for (int i = 0; i < n; ++i)
+    if (A.rowlen(i) > 0) {
+      C.cpos[i] = (int32_t)C.cidx.size();
+      C.cidx.push_back(i);
+    }
+  const int m = C.m = (int)C.cidx.size();
+  C.Ainv.assign((size_t)m * m, 0.0);
+  C.cdinv.assign(n, 0.0);
+  for (int k = 0; k < m; ++k) {
+    const int i = C.cidx[k];
+    C.Ainv[(size_t)k * m + k] = A.diag[i];
+    for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) C.Ainv[(size_t)k * m + C.cpos[A.col[e]]] -= A.w[e];
+  }
+  for (int i = 0; i < n; ++i)
+    if (A.active[i] && C.cpos[i] < 0) C.cdinv[i] = 1.0 / A.diag[i];
+  if (m > 0 && !spd_inverse_rowmajor(m, C.Ainv))
+    return err(ISIRA_E_PRECOND, "coarsest level of the multilevel hierarchy is not positive definite");
+  return ISIRA_OK;
+}
+
+// All levels on the host: lev[0] = L-hat in internal indices (trimmed row empty and
+// inactive), aggs[l] the aggregation of level l, mats[l] its transfer products.
+int build_host(int n, const int32_t* rp, const int32_t* col, const double* w,
+               const int32_t* perm, int trim, const Params& prm, std::vector<HostLevel>& lev,
+               std::vector<std::vector<int32_t>>& aggs, std::vector<HostMats>& mats,
+               HostCoarsest& co) {
+  lev.assign(1, HostLevel{});
+  aggs.clear();
+  mats.clear();
+  {
+    HostLevel& A = lev[0];
+    A.n = n;
+    A.rp.assign((size_t)n + 1, 0);
+    A.diag.assign(n, 0.0);
+    A.active.assign(n, 1);
+    A.active[trim] = 0;
+    A.col.reserve(rp[n]);
+    A.w.reserve(rp[n]);
+    for (int i = 0; i < n; ++i) {
+      double d = 0.0;
+      for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const double we = w ? w[e] : 1.0;
+        d += we;
+        if (i != trim && col[e] != trim) {
+          A.col.push_back(col[e]);
+          A.w.push_back(we);
+        }
+      }
+      A.diag[i] = i == trim ? 0.0 : d;
+      A.rp[i + 1] = (int32_t)A.col.size();
+    }
+  }
+  std::vector<int32_t> by_key(n);
+  for (int i = 0; i < n; ++i) by_key[perm[i]] = i;  // increasing caller label
+  for (;;) {
+    const HostLevel& A = lev.back();
+    int conn = 0;
+    for (int i = 0; i < A.n; ++i) conn += A.rowlen(i) > 0;
+    if (conn <= prm.coarse_max) break;
+    if ((int)lev.size() >= prm.max_levels)
+      return err(ISIRA_E_PRECOND, "multilevel hierarchy: coarsest level still above coarse_max at max_levels");
+    std::vector<int32_t> agg;
+    const int nc = aggregate(A, by_key, agg);
+    HostLevel C = coarsen(A, agg, nc);
+    mats.push_back(build_level_mats(A, agg, nc, prm.omega));
+    aggs.push_back(std::move(agg));
+    lev.push_back(std::move(C));
+    by_key.resize(nc);
+    for (int i = 0; i < nc; ++i) by_key[i] = i;
+  }
+  return build_coarsest(lev.back(), co);
+}
+
+std::vector<float> to32(const std::vector<double>& v) {
+  std::vector<float> f(v.size());
+  for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+  return f;
+}
+
+int upload_level(Level& L, int n, int nc, const HostMats& M, Hierarchy& H) {
+  L.n = n;
+  L.nc = nc;
+  L.ld = M.ld;
+  int64_t& by = H.device_bytes;
+  int rc;
+  if ((rc = dal(&L.down_rp, M.drp.size(), by)) || (rc = dal(&L.down_col, M.dcol.size(), by)) ||
+      (rc = dal(&L.down_v64, M.dval.size(), by)) || (rc = dal(&L.down_v32, M.dval.size(), by)) ||
+      (rc = dal(&L.up_rp, M.urp.size(), by)) || (rc = dal(&L.up_col, M.ucol.size(), by)) ||
+      (rc = dal(&L.up_v64, M.uval.size(), by)) || (rc = dal(&L.up_v32, M.uval.size(), by)) ||
+      (rc = dal(&L.up_diag64, M.udiag.size(), by)) || (rc = dal(&L.up_diag32, M.udiag.size(), by)) ||
+      (rc = dal(&L.buf64, (size_t)L.ld + nc, by)) || (rc = dal(&L.buf32, (size_t)L.ld + nc, by)))
+    return rc;
+  if ((rc = put(L.down_rp, M.drp)) || (rc = put(L.down_col, M.dcol)) || (rc = put(L.down_v64, M.dval)) ||
+      (rc = put(L.down_v32, to32(M.dval))) || (rc = put(L.up_rp, M.urp)) || (rc = put(L.up_col, M.ucol)) ||
+      (rc = put(L.up_v64, M.uval)) || (rc = put(L.up_v32, to32(M.uval))) ||
+      (rc = put(L.up_diag64, M.udiag)) || (rc = put(L.up_diag32, to32(M.udiag))))
+    return rc;
+  // the level buffers are read in full by the products' own-row loads: keep them finite
+  MLCK(hipMemset(L.buf64, 0, ((size_t)L.ld + nc) * sizeof(double)));
+  MLCK(hipMemset(L.buf32, 0, ((size_t)L.ld + nc) * sizeof(float)));
+  if ((rc = build_spmv_plan(nc, M.drp.data(), M.dcol.data(), L.down))) return rc;
+  if ((rc = build_spmv_plan(n, M.urp.data(), M.ucol.data(), L.up))) return rc;
+  H.stored_nnz += (int64_t)M.dcol.size() + (int64_t)M.ucol.size();
+  return ISIRA_OK;
+}
+
+int upload_coarsest(const HostCoarsest& C, Hierarchy& H) {
+  H.nL = C.n;
+  H.mL = C.m;
+  int64_t& by = H.device_bytes;
+  int rc;
+  if ((rc = dal(&H.cidx, C.cidx.size(), by)) || (rc = dal(&H.cpos, C.cpos.size(), by)) ||
+      (rc = dal(&H.Ainv, C.Ainv.size(), by)) || (rc = dal(&H.cdinv, C.cdinv.size(), by)) ||
+      (rc = dal(&H.bufL64, (size_t)C.n, by)) || (rc = dal(&H.bufL32, (size_t)C.n, by)))
+    return rc;
+  if ((rc = put(H.cidx, C.cidx)) || (rc = put(H.cpos, C.cpos)) || (rc = put(H.Ainv, C.Ainv)) ||
+      (rc = put(H.cdinv, C.cdinv)))
+    return rc;
+  MLCK(hipMemset(H.bufL64, 0, (size_t)C.n * sizeof(double)));
+  MLCK(hipMemset(H.bufL32, 0, (size_t)C.n * sizeof(float)));
+  return ISIRA_OK;
+}
+
+}  // namespace
+
+void release(Hierarchy& H) {
+  for (Level& L : H.lv) {
+    free_spmv_plan(L.down);
+    free_spmv_plan(L.up);
+    dfr(L.down_rp); dfr(L.down_col); dfr(L.down_v64); dfr(L.down_v32);
+    dfr(L.up_rp); dfr(L.up_col); dfr(L.up_v64); dfr(L.up_v32); dfr(L.up_diag64);
+    dfr(L.up_diag32); dfr(L.buf64); dfr(L.buf32);
+  }
+  dfr(H.cidx); dfr(H.cpos); dfr(H.Ainv); dfr(H.cdinv); dfr(H.bufL64); dfr(H.bufL32);
+  dfr(H.zero64); dfr(H.zero32);
+  H = Hierarchy{};
+}
+
+int setup(Hierarchy& H, int n, const int32_t* rp, const int32_t* col, const double* w,
+          const int32_t* perm, int trim, const Params& prm) {
+  release(H);
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<HostLevel> lev;
+  std::vector<std::vector<int32_t>> aggs;
+  std::vector<HostMats> mats;
+  HostCoarsest co;
+  int rc = build_host(n, rp, col, w, perm, trim, prm, lev, aggs, mats, co);
+  if (rc) return rc;
+  const int L = (int)lev.size() - 1;
+  H.lv.resize(L);
+  H.trim = trim;
+  H.omega = prm.omega;
+  H.coarse_max = prm.coarse_max;
+  for (int l = 0; l < L; ++l)
+    if ((rc = upload_level(H.lv[l], lev[l].n, lev[l + 1].n, mats[l], H))) {
+      release(H);
+      return rc;
+    }
+  if ((rc = upload_coarsest(co, H))) {
+    release(H);
+    return rc;
+  }
+  int maxc = 1;
+  for (int l = 0; l < L; ++l) maxc = std::max(maxc, H.lv[l].nc);
+  if ((rc = dal(&H.zero64, (size_t)maxc, H.device_bytes)) ||
+      (rc = dal(&H.zero32, (size_t)maxc, H.device_bytes))) {
+    release(H);
+    return rc;
+  }
+  if (hipMemset(H.zero64, 0, (size_t)maxc * 8) != hipSuccess ||
+      hipMemset(H.zero32, 0, (size_t)maxc * 4) != hipSuccess) {
+    release(H);
+    return err(ISIRA_E_HIP, "hipMemset failed");
+  }
+  for (int l = 0; l <= L; ++l) {
+    const HostLevel& A = lev[l];
+    int conn = 0;
+    for (int i = 0; i < A.n; ++i) conn += A.rowlen(i) > 0;
+    H.rows.push_back(l == 0 ? A.n - 1 : A.n);
+    H.offnnz.push_back((int64_t)A.col.size());
+    H.connected.push_back(conn);
+  }
+  H.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  H.ready = true;
+  return ISIRA_OK;
+}
+
+template <typename T>
+void apply(const Hierarchy& H, const T* in, T* out, int check_done, DevState* st, RedBuf rb,
+           hipStream_t s) {
+  constexpr bool f64 = sizeof(T) == 8;
+  const int L = (int)H.lv.size();
+  auto buf = [&](const Level& l) -> T* {
+    if constexpr (f64) return l.buf64; else return l.buf32;
+  };
+  T* bL;
+  if constexpr (f64) bL = H.bufL64; else bL = H.bufL32;
+  const int n0 = L ? H.lv[0].n : H.nL;
+  T* b0 = L ? buf(H.lv[0]) : bL;
+  (void)hipMemcpyAsync(b0, in, (size_t)n0 * sizeof(T), hipMemcpyDeviceToDevice, s);
+  const int vm = f64 ? kF64Pos : kF32Pos;
+  for (int l = 0; l < L; ++l) {
+    const Level& lv = H.lv[l];
+    SpmvArgs<T> a{};
+    a.rp = lv.down_rp;
+    a.col = lv.down_col;
+    if constexpr (f64) {
+      a.vals = lv.down_v64;
+      a.diag = H.zero64;
+    } else {
+      a.vals = lv.down_v32;
+      a.diag = H.zero32;
+    }
+    a.x = buf(lv);
+    a.y = l + 1 < L ? buf(H.lv[l + 1]) : bL;
+    a.n = lv.n;  // length of x (bounds the hub copy)
+    a.trim = -1;
+    a.st = st;
+    a.check_done = check_done;
+    launch_spmv<T>(lv.down, vm, a, rb, s);
+  }
+  T* xL = L ? buf(H.lv[L - 1]) + H.lv[L - 1].ld : out;
+  k_ml_coarse<T><<<(H.nL + 3) / 4, 256, 0, s>>>(H.nL, H.mL, H.cidx, H.cpos, H.Ainv, H.cdinv,
+                                                 bL, xL, st, check_done);
+  for (int l = L - 1; l >= 0; --l) {
+    const Level& lv = H.lv[l];
+    SpmvArgs<T> a{};
+    a.rp = lv.up_rp;
+    a.col = lv.up_col;
+    if constexpr (f64) {
+      a.vals = lv.up_v64;
+      a.diag = lv.up_diag64;
+    } else {
+      a.vals = lv.up_v32;
+      a.diag = lv.up_diag32;
+    }
+    a.x = buf(lv);
+    a.y = l > 0 ? buf(H.lv[l - 1]) + H.lv[l - 1].ld : out;
+    a.n = lv.ld + lv.nc;
+    a.trim = l == 0 ? H.trim : -1;
+    a.st = st;
+    a.check_done = check_done;
+    launch_spmv<T>(lv.up, vm, a, rb, s);
+  }
+}
+
+template void apply<double>(const Hierarchy&, const double*, double*, int, DevState*, RedBuf,
+                            hipStream_t);
+template void apply<float>(const Hierarchy&, const float*, float*, int, DevState*, RedBuf,
+                           hipStream_t);
+
+}  // namespace ml
+}  // namespace isira

@@ -25,11 +25,12 @@ ISIRA_E_PRECOND = -5
 ISIRA_E_STATE = -6
 W_NONE, W_F32, W_F64 = 0, 1, 2
 FP64, FP32 = 0, 1
-PC_JACOBI, PC_LEARNED = 0, 1
+PC_JACOBI, PC_LEARNED, PC_MULTILEVEL = 0, 1, 2
 SOLVER_PCG, SOLVER_MINRES = 0, 1
 SHIFT_FIXED, SHIFT_MOVING = 0, 1
 MAX_K = 64
 STATS_MAX = 64
+ML_MAX_LEVELS = 32
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -86,12 +87,32 @@ class Info(ctypes.Structure):
     ]
 
 
+class MlOptions(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("coarse_max", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("trim_index", ctypes.c_int64)]
+
+
+class MlInfo(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32), ("rows", ctypes.c_int64 * ML_MAX_LEVELS),
+        ("offdiag_nnz", ctypes.c_int64 * ML_MAX_LEVELS), ("connected", ctypes.c_int64 * ML_MAX_LEVELS),
+        ("coarsest_dense", ctypes.c_int64), ("stored_nnz", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        L = self.levels
+        return dict(levels=L, rows=list(self.rows[:L]), offdiag_nnz=list(self.offdiag_nnz[:L]),
+                    connected=list(self.connected[:L]), coarsest_dense=self.coarsest_dense,
+                    stored_nnz=self.stored_nnz, device_bytes=self.device_bytes, setup_ms=self.setup_ms)
+
+
 EXPORTS = [
     "isira_default_options", "isira_create", "isira_destroy", "isira_get_info", "isira_solve",
     "isira_laplacian_apply", "isira_laplacian_apply_f32", "isira_time_spmv", "isira_inner_solve",
     "isira_orthonormalize", "isira_symeig", "isira_spai_nparam", "isira_spai_install",
-    "isira_spai_export", "isira_spai_loss_grad", "isira_adam_step", "isira_strerror",
-    "isira_last_error",
+    "isira_spai_export", "isira_spai_loss_grad", "isira_adam_step", "isira_ml_default_options",
+    "isira_ml_setup", "isira_ml_get_info", "isira_ml_apply", "isira_strerror", "isira_last_error",
 ]
 
 _lib = None
@@ -133,6 +154,10 @@ def load() -> ctypes.CDLL:
         "isira_spai_loss_grad": (i32, [vp, vp, dbl, i64, vp, vp, i32, vp, _c_double_p]),
         "isira_adam_step": (i32, [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, ctypes.c_float, i32]),
+        "isira_ml_default_options": (i32, [ctypes.POINTER(MlOptions)]),
+        "isira_ml_setup": (i32, [vp, ctypes.POINTER(MlOptions), ctypes.POINTER(MlInfo)]),
+        "isira_ml_get_info": (i32, [vp, ctypes.POINTER(MlInfo)]),
+        "isira_ml_apply": (i32, [vp, i32, vp, vp]),
         "isira_strerror": (ctypes.c_char_p, [i32]),
         "isira_last_error": (ctypes.c_char_p, []),
     }
@@ -337,6 +362,37 @@ class Context:
         _check(self._lib.isira_orthonormalize(self._h, _ptr(Q) if nc else None, nc, _ptr(z), _ptr(u),
                                               norms.ctypes.data_as(_c_double_p)))
         return u, norms
+
+    # ---- multilevel preconditioner ----
+    def ml_setup(self, omega: Optional[float] = None, coarse_max: Optional[int] = None,
+                 max_levels: Optional[int] = None, trim: int = -1) -> dict:
+        """Build the aggregation-multigrid hierarchy of L-hat; returns its statistics."""
+        o = MlOptions()
+        _check(self._lib.isira_ml_default_options(ctypes.byref(o)))
+        if omega is not None:
+            o.omega = float(omega)
+        if coarse_max is not None:
+            o.coarse_max = int(coarse_max)
+        if max_levels is not None:
+            o.max_levels = int(max_levels)
+        o.trim_index = int(trim)
+        inf = MlInfo()
+        _check(self._lib.isira_ml_setup(self._h, ctypes.byref(o), ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def ml_info(self) -> dict:
+        inf = MlInfo()
+        _check(self._lib.isira_ml_get_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def ml_apply(self, x, prec: int = FP64):
+        """One V-cycle on the trimmed x (CUDA float64, n); the trimmed entry of the result is 0."""
+        import torch
+
+        _require_cuda(x, torch.float64, self.n, "x")
+        y = torch.empty_like(x)
+        _check(self._lib.isira_ml_apply(self._h, int(prec), _ptr(x), _ptr(y)))
+        return y
 
     # ---- learned preconditioner ----
     def spai_install(self, params, sigma: float = 0.0, trim: int = -1):

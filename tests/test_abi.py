@@ -87,3 +87,11 @@ def test_create_rejects_bad_graphs(P):
     # two components: 0-1 and 2-3
     _bad(P, 4, [0, 1, 2, 3, 4], [1, 0, 3, 2], code=E.ISIRA_E_DISCONNECTED)
     _bad(P, 2, [0, 1, 2], [1, 0], code=E.ISIRA_E_ARG)                # n too small
+
+
+def test_multilevel_defaults(P):
+    o = P.isira.MlOptions()
+    assert P.load().isira_ml_default_options(o) == 0
+    assert abs(o.omega - 2.0 / 3.0) < 1e-15 and o.coarse_max == 512 and o.max_levels == 24
+    assert o.trim_index == -1
+    assert P.isira.PC_MULTILEVEL == 2

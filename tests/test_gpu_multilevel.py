@@ -1,0 +1,215 @@
+"""GPU parity of the multilevel preconditioner (aggregation multigrid V-cycle for L-hat)
+against the FP64 CPU oracle: the hierarchy's shape (level sizes, stored entries and vertices
+with neighbours must match exactly, since the aggregation rule involves no floating point),
+one cycle applied to seeded vectors, PCG inner solves preconditioned by it, and whole
+solves against dense eigenvalues.  Graphs cover the hub-cached product shape, rows split
+into chunks (aggregates of a few thousand vertices), vertices left without neighbours by
+trimming, and a coarsest level that is purely diagonal."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import graphgen as gg
+from oracle import isira_oracle as O
+from oracle import multilevel_oracle as ML
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1710_07080_amd as pkg
+
+    pkg.load()
+    return pkg
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _hub_graph():
+    # trimmed hub of degree 9000, vertices of degree 2000 and 1500 whose aggregates make
+    # transfer rows longer than a work unit, and a random sparse remainder
+    n = 12000
+    rng = np.random.default_rng(77)
+    u = [np.zeros(9000, dtype=np.int64), np.full(2000, 1), np.full(1500, 2)]
+    v = [np.arange(1, 9001), rng.integers(3, n, 2000), rng.integers(3, n, 1500)]
+    tree_order = rng.permutation(n)
+    parents = tree_order[(rng.random(n - 1) * np.arange(1, n)).astype(np.int64)]
+    u += [tree_order[1:], rng.integers(0, n, 20000)]
+    v += [parents, rng.integers(0, n, 20000)]
+    from graphgen.generators import _csr_from_undirected
+
+    return _csr_from_undirected(n, np.concatenate(u), np.concatenate(v), lcc=True, name="hubs")
+
+
+GRAPHS = {
+    "rmat14": (lambda: gg.rmat(14, 8, seed=9), 64),
+    "grid3d_w": (lambda: gg.grid3d(20, 17, 13, weights=(0.5, 1.5), seed=3), 32),
+    "hubs": (_hub_graph, 100),
+    "rmat17": (lambda: gg.rmat(17, 8, seed=13), 512),  # hub-cached product shape
+    "grid2d_cm0": (lambda: gg.grid2d(40, 33), 0),       # coarsest level purely diagonal
+}
+_cache = {}
+
+
+def _setup(P, name):
+    if name not in _cache:
+        _cache.clear()
+        make, cm = GRAPHS[name]
+        g = make()
+        ctx = P.Context.from_graph(g)
+        i = O.trim_index(O.degrees(g))
+        info = ctx.ml_setup(coarse_max=cm)
+        h = ML.setup(g, i, coarse_max=cm)
+        _cache[name] = (g, ctx, i, info, h, cm)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_hierarchy_shape_matches_oracle(P, name):
+    g, ctx, i, info, h, cm = _setup(P, name)
+    assert info["levels"] == len(h.A)
+    assert info["rows"] == [A.shape[0] for A in h.A]
+    assert info["offdiag_nnz"] == [A.nnz - int(np.count_nonzero(A.diagonal())) for A in h.A]
+    assert info["connected"] == [ML.connected_count(A) for A in h.A]
+    assert info["coarsest_dense"] == info["connected"][-1] <= cm
+    assert ctx.ml_info() == info
+    print(f"{name}: levels {info['rows']}, setup {info['setup_ms']:.0f} ms")
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cycle_matches_oracle(P, name, prec):
+    g, ctx, i, info, h, cm = _setup(P, name)
+    rng = np.random.default_rng(5)
+    for trial in range(2):
+        x = rng.standard_normal(g.n)
+        ref = np.insert(ML.vcycle(h, O.trim(x, i)), i, 0.0)
+        y = ctx.ml_apply(_dev(x), prec=prec).cpu().numpy()
+        assert y[i] == 0.0
+        err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+        # FP64: only the rounding of the composite transfer matrices differs;
+        # FP32: vectors and values in single precision through every level
+        assert err <= (1e-12 if prec == 0 else 3e-5), err
+        if prec == 0:
+            assert np.abs(y - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_single_level_cycle_is_exact_inverse(P):
+    g = gg.grid2d(30, 30)
+    ctx = P.Context.from_graph(g)
+    info = ctx.ml_setup(coarse_max=2048)
+    assert info["levels"] == 1
+    i = O.trim_index(O.degrees(g))
+    Lhat = O.trimmed_matrix(O.laplacian(g), i).tocsc()
+    x = np.random.default_rng(2).standard_normal(g.n)
+    y = ctx.ml_apply(_dev(x)).cpu().numpy()
+    ref = np.insert(spla.spsolve(Lhat, O.trim(x, i)), i, 0.0)
+    assert np.linalg.norm(y - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("case", [
+    dict(g="grid3d_w", c=3, sigma=0.0),
+    dict(g="rmat14", c=5, sigma=0.0),
+    dict(g="hubs", c=4, sigma="half"),
+], ids=["grid3d_c3", "rmat14_c5", "hubs_c4_shift"])
+def test_inner_solve_multilevel(P, case):
+    g, ctx, i, info, h, cm = _setup(P, case["g"])
+    L = O.laplacian(g)
+    d = O.degrees(g)
+    c = case["c"]
+    res = O.isira(g, c, 0.0, 1e-9, gg.start_block(g.n, 4, 3), inner_rtol=1e-8)
+    V = res.evecs[:, :c]
+    sigma = 0.5 * res.evals[0] if case["sigma"] == "half" else 0.0
+    delta = O.deflation_shift(d)
+    r = np.random.default_rng(4).standard_normal(g.n)
+    r -= r.mean()
+    z_ref, its_ref, _ = O.inner_solve(L, d, r, i, sigma, delta, V, 1e-12, 5000,
+                                      apply_minv_hat=lambda x: ML.vcycle(h, x))
+    z, its, rel = ctx.inner_solve(_dev(r), _dev(V.T), sigma=sigma, delta=delta, trim=i, rtol=1e-12,
+                                  max_it=5000, prec=P.isira.FP64, precond=P.isira.PC_MULTILEVEL)
+    z = z.cpu().numpy()
+    assert rel <= 1e-12
+    assert abs(its - its_ref) <= max(2, 0.05 * its_ref), (its, its_ref)
+    assert np.linalg.norm(z - z_ref) <= 1e-8 * np.linalg.norm(z_ref)
+    # the same system with Jacobi takes more iterations
+    _, its_j, _ = ctx.inner_solve(_dev(r), _dev(V.T), sigma=sigma, delta=delta, trim=i, rtol=1e-12,
+                                  max_it=5000, prec=P.isira.FP64)
+    assert its < its_j
+
+
+@pytest.mark.parametrize("case", [
+    dict(g=lambda: gg.random_connected(2500, 6000, seed=32, weights=(0.5, 1.5)), k=6, prec=0, cm=40, q=None),
+    dict(g=lambda: gg.rmat(12, 8, seed=3), k=12, prec=1, cm=64, q=16),
+    dict(g=lambda: gg.grid3d(12, 11, 10, weights=(0.5, 1.5), seed=3), k=8, prec=1, cm=0, q=None),
+    dict(g=lambda: gg.grid3d(12, 11, 10, weights=(0.5, 1.5), seed=3), k=8, prec=0, cm=100, q=None),
+], ids=["rand2500w_fp64", "rmat12_fp32_restart", "grid3d_w_fp32_cm0", "grid3d_w_fp64"])
+def test_solve_multilevel_matches_dense(P, case):
+    g = case["g"]()
+    k = case["k"]
+    Ld = O.laplacian(g).toarray()
+    lam = np.linalg.eigvalsh(Ld)
+    ctx = P.Context.from_graph(g)
+    ctx.ml_setup(coarse_max=case["cm"])
+    opts = dict(q=case["q"], m=2 * case["q"]) if case["q"] else {}
+    tol = 1e-9
+    ev, X, resid, st = ctx.solve(k, 0.0, tol, u0=gg.start_block(g.n, 4, 5), inner_prec=case["prec"],
+                                 precond=P.isira.PC_MULTILEVEL, **opts)
+    X = X.cpu().numpy()
+    assert st["n_converged"] == k
+    assert np.allclose(np.sort(ev), lam[1:k + 1], rtol=1e-9, atol=0)
+    for j in range(k):
+        assert np.linalg.norm(Ld @ X[j] - ev[j] * X[j]) <= tol
+    assert np.abs(X @ X.T - np.eye(k)).max() <= 1e-10
+    assert np.abs(X.sum(axis=1)).max() <= 1e-9
+
+
+def test_solve_multilevel_vs_oracle(P):
+    g = gg.rmat(13, 8, seed=21)
+    ctx = P.Context.from_graph(g)
+    ctx.ml_setup(coarse_max=64)
+    U0 = gg.start_block(g.n, 4, 2)
+    k = 10
+    ev, X, resid, st = ctx.solve(k, 0.0, 1e-9, u0=U0, precond=P.isira.PC_MULTILEVEL)
+    ref = O.isira(g, k, 0.0, 1e-9, U0, inner_rtol=1e-1,
+                  apply_minv_hat_factory=ML.preconditioner_factory(g, coarse_max=64))
+    assert st["n_converged"] == k
+    assert np.allclose(np.sort(ev), np.sort(ref.evals), rtol=1e-9, atol=0)
+    # same method, same preconditioner: the outer iteration counts stay close
+    outer_ref = sum(ref.outer_its)
+    assert abs(st["outer_total"] - outer_ref) <= max(3, 0.1 * outer_ref), (st["outer_total"], outer_ref)
+
+
+def test_multilevel_errors(P):
+    g = gg.grid2d(12, 12)
+    ctx = P.Context.from_graph(g)
+    with pytest.raises(P.IsiraError) as e:
+        ctx.solve(3, precond=P.isira.PC_MULTILEVEL)  # no hierarchy yet
+    assert e.value.code == P.isira.ISIRA_E_PRECOND
+    with pytest.raises(P.IsiraError) as e:
+        ctx.ml_apply(_dev(np.ones(g.n)))
+    assert e.value.code == P.isira.ISIRA_E_STATE
+    for bad in [dict(omega=0.0), dict(omega=1.0), dict(coarse_max=-1), dict(coarse_max=5000),
+                dict(max_levels=0), dict(max_levels=99)]:
+        with pytest.raises(P.IsiraError) as e:
+            ctx.ml_setup(**bad)
+        assert e.value.code == P.isira.ISIRA_E_ARG
+    with pytest.raises(P.IsiraError) as e:
+        ctx.ml_setup(coarse_max=0, max_levels=2)  # two levels cannot reach a diagonal level
+    assert e.value.code == P.isira.ISIRA_E_PRECOND
+    ctx.ml_setup(trim=5)
+    with pytest.raises(P.IsiraError) as e:
+        ctx.solve(3, precond=P.isira.PC_MULTILEVEL)  # hierarchy for another trim index
+    assert e.value.code == P.isira.ISIRA_E_PRECOND
+    with pytest.raises(P.IsiraError) as e:
+        ctx.solve(3, precond=P.isira.PC_MULTILEVEL, trim_index=5, shift_mode=P.isira.SHIFT_MOVING)
+    assert e.value.code == P.isira.ISIRA_E_PRECOND
+    ev, X, resid, st = ctx.solve(3, precond=P.isira.PC_MULTILEVEL, trim_index=5,
+                                 u0=gg.start_block(g.n, 4, 1))
+    assert st["n_converged"] == 3
