@@ -227,6 +227,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--precond", choices=["jacobi", "learned", "multilevel"], default="jacobi",
+                    help="preconditioner of the timed solve (default: the plain method's Jacobi)")
+    ap.add_argument("--inner-prec", choices=["fp64", "fp32"], default="fp64",
+                    help="precision of the timed solve's inner solves (default: the plain FP64 method)")
     ap.add_argument("--probe", action="store_true",
                     help="only a 256 MiB device copy (counter calibration) and launches of the "
                          "FP64 and FP32 products, for rocprofv3 counter runs")
@@ -274,6 +278,19 @@ def main():
         return
     u0 = gg.start_block(g.n, 4, 1)
     opts = dict(u0=u0, inner_rtol=args.inner_rtol)
+    # the timed solve: the plain FP64 method unless another form is asked for
+    main_pc = {"jacobi": P.isira.PC_JACOBI, "learned": P.isira.PC_LEARNED,
+               "multilevel": P.isira.PC_MULTILEVEL}[args.precond]
+    main_prec = P.isira.FP32 if args.inner_prec == "fp32" else P.isira.FP64
+    main_setup = {}
+    if main_pc == P.isira.PC_MULTILEVEL:
+        main_setup = ctx.ml_setup()
+        log(f"multilevel set-up: {main_setup}")
+    elif main_pc == P.isira.PC_LEARNED:
+        from paper_1710_07080_amd import spai_train
+
+        ctx.spai_install(spai_train.load(SPAI_WEIGHTS), sigma=cfg["sigma"])
+    main_opts = dict(opts, inner_prec=main_prec, precond=main_pc)
     if args.study == "trim":
         trim_study(ctx, g, cfg, opts, args)
         return
@@ -285,7 +302,7 @@ def main():
         return
     stream = torch.cuda.current_stream()
     for w in range(args.warmup):
-        ev, X, res, st = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], **opts)
+        ev, X, res, st = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], **main_opts)
         log(f"warmup {w}: {st['ms_total'] / 1e3:.3f} s, converged {st['n_converged']}")
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -294,7 +311,7 @@ def main():
     wall0 = time.perf_counter()
     stats = []
     for s in range(args.steps):
-        ev, X, res, st = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], **opts)
+        ev, X, res, st = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], **main_opts)
         stats.append(st)
         log(f"step {s}: {st['ms_total'] / 1e3:.3f} s, outer {st['outer_total']}, "
             f"inner {st['inner_total']}, converged {st['n_converged']}")
@@ -324,13 +341,13 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if main_prec == P.isira.FP64 else "f32 inner, f64 outer",
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: R-MAT scale 20, edge factor 8, LCC, unit weights"
             if args.workload == "rmat20" else args.workload,
             "n": g.n, "nnz": g.nnz, "k": cfg["k"], "sigma": cfg["sigma"], "tol": cfg["tol"],
-            "inner": "FP64 PCG, Jacobi + SMW", "inner_rtol": args.inner_rtol,
+            "inner": f"{args.inner_prec.upper()} PCG, {args.precond} + SMW", "inner_rtol": args.inner_rtol,
         },
         "converged": bool(ok),
         "max_resid": float(np.max(res)),

@@ -113,6 +113,9 @@ struct isira_ctx {
   double max_deg = 0, min_deg = 0;
   // solve workspace
   int ws_m = 0, ws_k = 0;
+  // entries past ld of the inner residual buffers ri64/ri32: the multilevel cycle runs in
+  // place there (x of its second level after the residual); ws_tail is what is allocated
+  int ri_tail = 0, ws_tail = 0;
   double *U = nullptr, *W = nullptr, *Vout = nullptr;
   double *Vin64 = nullptr, *Y64 = nullptr;
   float *Vin32 = nullptr, *Y32 = nullptr;
@@ -270,7 +273,7 @@ static void free_workspace(isira_ctx* c) {
 }
 
 static int ensure_workspace(isira_ctx* c, int m, int kmax) {
-  if (c->ws_m >= m && c->ws_k >= kmax && c->r64) return ISIRA_OK;
+  if (c->ws_m >= m && c->ws_k >= kmax && c->ws_tail >= c->ri_tail && c->r64) return ISIRA_OK;
   free_workspace(c);
   const size_t ld = (size_t)c->ld;
   int rc;
@@ -288,11 +291,14 @@ static int ensure_workspace(isira_ctx* c, int m, int kmax) {
   CKH(hipMemset(c->Y64, 0, ld * kpad * sizeof(double)));
   CKH(hipMemset(c->Vin32, 0, ld * kpad * sizeof(float)));
   CKH(hipMemset(c->Y32, 0, ld * kpad * sizeof(float)));
-  for (double** p : {&c->r64, &c->z64, &c->tmp64, &c->x64, &c->ri64, &c->p64, &c->q64,
+  for (double** p : {&c->r64, &c->z64, &c->tmp64, &c->x64, &c->p64, &c->q64,
                      &c->dinv64, &c->y64, &c->wa64, &c->wb64})
     if ((rc = dalloc(p, ld))) return rc;
-  for (float** p : {&c->x32, &c->ri32, &c->p32, &c->q32, &c->dinv32, &c->y32, &c->wa32, &c->wb32})
+  for (float** p : {&c->x32, &c->p32, &c->q32, &c->dinv32, &c->y32, &c->wa32, &c->wb32})
     if ((rc = dalloc(p, ld))) return rc;
+  if ((rc = dalloc(&c->ri64, ld + c->ri_tail))) return rc;
+  if ((rc = dalloc(&c->ri32, ld + c->ri_tail))) return rc;
+  c->ws_tail = c->ri_tail;
   c->ws_m = m;
   c->ws_k = kmax;
   return ISIRA_OK;
@@ -659,6 +665,7 @@ struct InnerCfg {
   double sigma, delta, rtol;
   int trim;     // internal index
   int maxit, check_every;
+  int first_batch = 0;  // iterations queued with the set-up (0: check_every)
   bool rank_one = true;  // the (sigma/n) 1-hat 1-hat^T term of eq. (2.15) in the operator
   int solver = ISIRA_SOLVER_PCG;
 };
@@ -789,7 +796,7 @@ void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
       // y = cycle(r) with the dots V-hat^T y and r^T y, then eq. (3.5)
       launch_pcg_update1_plain<T>(n, b.x, b.r, b.p, b.q, b.V, c->ld, nc, cfg.delta, cfg.trim,
                                   sig_over_n, first, c->st, c->rb, s);
-      ml::apply<T>(c->ml, b.r, b.y, 1, c->st, c->rb, s);
+      ml::apply<T>(c->ml, b.r, b.y, 1, c->st, c->rb, s, /*in_place=*/true);
       launch_multidot<T>(n, b.V, c->ld, nc, b.r, c->ld, 1, b.y, nullptr, 0, 0, c->st->t2, c->rb, s);
       launch_spai_finish_rho(nc, c->Ginv, cfg.delta, first, c->st, s);
       launch_pcg_update2_learned<T>(n, b.y, b.p, b.Y, c->ld, nc, b.V, cfg.delta, first, c->st,
@@ -810,11 +817,12 @@ void inner_pcg_start(isira_ctx* c, const InnerCfg& cfg, const double* r64, doubl
   const PcgBufs<T> b = pcg_bufs<T>(c);
   launch_pcg_reset(c->st, cfg.rtol * cfg.rtol, cfg.maxit, c->stream);
   launch_rhs_prep<T>(n, r64, mean, mean_sum, 1.0 / (double)n, cfg.trim, b.r, b.x, c->stream);
+  const int first = cfg.first_batch > 0 ? cfg.first_batch : cfg.check_every;
   if (cfg.solver == ISIRA_SOLVER_MINRES) {
-    minres_batch<T>(c, cfg, nc, cfg.check_every, 1, 1);
-    c->minres_next = 1 + cfg.check_every;
+    minres_batch<T>(c, cfg, nc, first, 1, 1);
+    c->minres_next = 1 + first;
   } else {
-    pcg_batch<T>(c, cfg, nc, 1 + cfg.check_every, 1);
+    pcg_batch<T>(c, cfg, nc, 1 + first, 1);
   }
 }
 
@@ -1073,6 +1081,9 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     return ISIRA_OK;
   };
 
+  int recent_its[4];
+  std::fill(recent_its, recent_its + 4, cfg.check_every);
+  int n_inner = 0;
   auto start_inner = [&]() {
     // the right-hand side is the Ritz residual in r64; its sum is st->red[1]
     if (cfg.prec == ISIRA_FP64) {
@@ -1213,6 +1224,12 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
       rc = inner_pcg_finish<float>(c, cfg, nconv, true, &its, &status, &rel);
     }
     if (rc) return rc;
+    // the next inner solve queues as many iterations with its set-up as the most any of
+    // the last four took: launches past convergence return at once, each round trip
+    // to the host for another batch costs a wait
+    recent_its[n_inner++ & 3] = its;
+    cfg.first_batch = std::max(1, std::min(cfg.check_every,
+                                           *std::max_element(recent_its, recent_its + 4)));
     if (status == kPcgBreakdown) S.inner_fallbacks++;
     if (status == kPcgCapped) S.inner_capped++;
     S.inner_total += its;
@@ -1494,6 +1511,9 @@ extern "C" int isira_ml_setup(isira_ctx* c, const isira_ml_options* opt, isira_m
   const int rc = ml::setup(c->ml, n, rp.data(), col.data(), w.empty() ? nullptr : w.data(),
                            c->perm.data(), trim, prm);
   if (rc) return rc;
+  // the in-place cycle needs room for the second level after the inner residual
+  c->ri_tail = c->ml.lv.empty() ? 0 : c->ml.lv[0].nc;
+  if (c->ws_tail < c->ri_tail) free_workspace(c);
   if (info) fill_ml_info(c->ml, info);
   return ISIRA_OK;
 }

@@ -63,9 +63,12 @@ void release(Hierarchy& H);
 
 // out = cycle(in) on internal vectors of length n (in's trimmed entry is ignored, out's is
 // 0).  check_done: every launch returns at once when st->done is set (inside PCG).
+// in_place: `in` serves as the finest level's buffer, so it must have room for the second
+// level's vector at [lv[0].ld, lv[0].ld + lv[0].nc), which the cycle overwrites; otherwise
+// `in` is copied into the level's own buffer first.
 template <typename T>
 void apply(const Hierarchy& H, const T* in, T* out, int check_done, DevState* st, RedBuf rb,
-           hipStream_t s);
+           hipStream_t s, bool in_place = false);
 
 }  // namespace ml
 }  // namespace isira

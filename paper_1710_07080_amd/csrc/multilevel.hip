@@ -514,17 +514,27 @@ int setup(Hierarchy& H, int n, const int32_t* rp, const int32_t* col, const doub
 
 template <typename T>
 void apply(const Hierarchy& H, const T* in, T* out, int check_done, DevState* st, RedBuf rb,
-           hipStream_t s) {
+           hipStream_t s, bool in_place) {
   constexpr bool f64 = sizeof(T) == 8;
   const int L = (int)H.lv.size();
-  auto buf = [&](const Level& l) -> T* {
-    if constexpr (f64) return l.buf64; else return l.buf32;
-  };
   T* bL;
   if constexpr (f64) bL = H.bufL64; else bL = H.bufL32;
-  const int n0 = L ? H.lv[0].n : H.nL;
-  T* b0 = L ? buf(H.lv[0]) : bL;
-  (void)hipMemcpyAsync(b0, in, (size_t)n0 * sizeof(T), hipMemcpyDeviceToDevice, s);
+  // b0: the finest level's buffer (b_0, then x_1 at ld)
+  T* b0;
+  if (L == 0) {
+    b0 = bL;
+  } else if (in_place) {
+    b0 = const_cast<T*>(in);
+  } else {
+    if constexpr (f64) b0 = H.lv[0].buf64; else b0 = H.lv[0].buf32;
+  }
+  if (b0 != in)
+    (void)hipMemcpyAsync(b0, in, (size_t)(L ? H.lv[0].n : H.nL) * sizeof(T),
+                         hipMemcpyDeviceToDevice, s);
+  auto buf = [&](int l) -> T* {
+    if (l == 0) return b0;
+    if constexpr (f64) return H.lv[l].buf64; else return H.lv[l].buf32;
+  };
   const int vm = f64 ? kF64Pos : kF32Pos;
   for (int l = 0; l < L; ++l) {
     const Level& lv = H.lv[l];
@@ -538,15 +548,15 @@ void apply(const Hierarchy& H, const T* in, T* out, int check_done, DevState* st
       a.vals = lv.down_v32;
       a.diag = H.zero32;
     }
-    a.x = buf(lv);
-    a.y = l + 1 < L ? buf(H.lv[l + 1]) : bL;
-    a.n = lv.n;  // length of x (bounds the hub copy)
+    a.x = buf(l);
+    a.y = l + 1 < L ? buf(l + 1) : bL;
+    a.n = lv.n;  // length of x read by the products (bounds the hub copy)
     a.trim = -1;
     a.st = st;
     a.check_done = check_done;
     launch_spmv<T>(lv.down, vm, a, rb, s);
   }
-  T* xL = L ? buf(H.lv[L - 1]) + H.lv[L - 1].ld : out;
+  T* xL = L ? buf(L - 1) + H.lv[L - 1].ld : out;
   k_ml_coarse<T><<<(H.nL + 3) / 4, 256, 0, s>>>(H.nL, H.mL, H.cidx, H.cpos, H.Ainv, H.cdinv,
                                                  bL, xL, st, check_done);
   for (int l = L - 1; l >= 0; --l) {
@@ -561,8 +571,8 @@ void apply(const Hierarchy& H, const T* in, T* out, int check_done, DevState* st
       a.vals = lv.up_v32;
       a.diag = lv.up_diag32;
     }
-    a.x = buf(lv);
-    a.y = l > 0 ? buf(H.lv[l - 1]) + H.lv[l - 1].ld : out;
+    a.x = buf(l);
+    a.y = l > 0 ? buf(l - 1) + H.lv[l - 1].ld : out;
     a.n = lv.ld + lv.nc;
     a.trim = l == 0 ? H.trim : -1;
     a.st = st;
@@ -572,9 +582,9 @@ void apply(const Hierarchy& H, const T* in, T* out, int check_done, DevState* st
 }
 
 template void apply<double>(const Hierarchy&, const double*, double*, int, DevState*, RedBuf,
-                            hipStream_t);
+                            hipStream_t, bool);
 template void apply<float>(const Hierarchy&, const float*, float*, int, DevState*, RedBuf,
-                           hipStream_t);
+                           hipStream_t, bool);
 
 }  // namespace ml
 }  // namespace isira

@@ -4,7 +4,10 @@ The reference eigenvalues come from the FP64 oracle (``tests/golden/make_golden.
 calls nothing but ``oracle/``) on the same seeded graphs with the same start block.  Checks:
 eigenvalues within 1e-9 relative of the oracle's, true residuals ||Lx - lambda x||_2 formed
 by the oracle's own sparse Laplacian on the CPU (below tol, hence below 1e-8 ||L||_1),
-orthonormality, x orthogonal to 1, and the sign convention.
+orthonormality, x orthogonal to 1, and the sign convention.  The eigenpairs do not depend
+on the inner preconditioner, so the multilevel solves are checked against the same
+references; the multilevel hierarchy and one cycle are also compared with the oracle's at
+full size (its set-up takes up to a minute on the host).
 """
 import json
 import os
@@ -14,6 +17,7 @@ import pytest
 
 import graphgen as gg
 from oracle import isira_oracle as O
+from oracle import multilevel_oracle as ML
 
 pytestmark = pytest.mark.gpu
 
@@ -53,17 +57,21 @@ def _setup(P, name):
     return _cache[name]
 
 
-@pytest.mark.parametrize("name,prec", [("rmat20", 0), ("rmat20", 1), ("grid128w", 1), ("grid128w", 0)])
-def test_fullsize_matches_oracle(P, name, prec):
+@pytest.mark.parametrize("name,prec,pc", [("rmat20", 0, 0), ("rmat20", 1, 0), ("rmat20", 0, 2),
+                                         ("grid128w", 1, 0), ("grid128w", 0, 0), ("grid128w", 1, 2)])
+def test_fullsize_matches_oracle(P, name, prec, pc):
     gold, g, ctx, L = _setup(P, name)
     k, tol = gold["k"], gold["tol"]
-    ev, X, res, st = ctx.solve(k, gold["sigma"], tol, u0=gg.start_block(g.n, 4, 1), inner_prec=prec)
+    if pc == P.isira.PC_MULTILEVEL:
+        ctx.ml_setup()
+    ev, X, res, st = ctx.solve(k, gold["sigma"], tol, u0=gg.start_block(g.n, 4, 1), inner_prec=prec,
+                               precond=pc)
     assert st["n_converged"] == k
     order = np.argsort(ev)
     ev = ev[order]
     ref = np.array(gold["evals_sorted"])
     rel = np.abs(ev - ref) / ref
-    print(f"{name} prec={prec}: per-pair relative error vs oracle: {np.array2string(rel, precision=2)}")
+    print(f"{name} prec={prec} precond={pc}: per-pair relative error vs oracle: {np.array2string(rel, precision=2)}")
     assert rel.max() <= 1e-9
     Xh = X.cpu().numpy()[order]
     norm1 = 2.0 * O.degrees(g).max()
@@ -78,3 +86,27 @@ def test_fullsize_matches_oracle(P, name, prec):
     G = Xh @ Xh.T
     assert np.abs(G - np.eye(k)).max() <= 1e-10
     assert np.abs(Xh.sum(axis=1)).max() <= 1e-8 * np.sqrt(g.n)
+
+
+
+@pytest.mark.parametrize("name", ["rmat20", "grid128w"])
+def test_fullsize_multilevel_cycle(P, name):
+    """Hierarchy shape (exact) and one cycle in FP64 and FP32 against the oracle's, on the
+    benchmark graphs with the default set-up (coarse_max 512, omega 2/3)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _cache.clear()
+    g = WORKLOADS[name]()
+    ctx = P.Context.from_graph(g)
+    i = O.trim_index(O.degrees(g))
+    info = ctx.ml_setup()
+    h = ML.setup(g, i, coarse_max=512)
+    assert info["rows"] == [A.shape[0] for A in h.A]
+    assert info["connected"] == [ML.connected_count(A) for A in h.A]
+    x = np.random.default_rng(6).standard_normal(g.n)
+    ref = np.insert(ML.vcycle(h, O.trim(x, i)), i, 0.0)
+    for prec, bound in [(0, 1e-12), (1, 3e-5)]:
+        y = ctx.ml_apply(torch.as_tensor(x, device="cuda"), prec=prec).cpu().numpy()
+        err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+        print(f"{name} cycle prec={prec}: relative error {err:.2e}, levels {info['rows']}")
+        assert err <= bound
