@@ -797,7 +797,8 @@ void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
       launch_pcg_update1_plain<T>(n, b.x, b.r, b.p, b.q, b.V, c->ld, nc, cfg.delta, cfg.trim,
                                   sig_over_n, first, c->st, c->rb, s);
       ml::apply<T>(c->ml, b.r, b.y, 1, c->st, c->rb, s, /*in_place=*/true);
-      launch_multidot<T>(n, b.V, c->ld, nc, b.r, c->ld, 1, b.y, nullptr, 0, 0, c->st->t2, c->rb, s);
+      launch_multidot<T>(n, b.V, c->ld, nc, b.r, c->ld, 1, b.y, nullptr, 0, 0, c->st->t2, c->rb, s,
+                         c->st);
       launch_spai_finish_rho(nc, c->Ginv, cfg.delta, first, c->st, s);
       launch_pcg_update2_learned<T>(n, b.y, b.p, b.Y, c->ld, nc, b.V, cfg.delta, first, c->st,
                                     c->rb, s);

@@ -206,11 +206,12 @@ template <typename T>
 void launch_enlarge(int n, const T* x, double* z, DevState* st, RedBuf rb, hipStream_t s);
 
 // Column dots h_j = sum_l A[l,j] * (w_l * z_l), j < na, then B, then (optional) sum z,
-// then (optional) z^T z.  Result into h (device).
+// then (optional) z^T z.  Result into h (device).  skip_if_done: inside an inner solve,
+// both dispatches return at once once skip_if_done->done is set.
 template <typename T>
 void launch_multidot(int n, const T* A, int64_t lda, int na, const T* B, int64_t ldb, int nb,
                      const T* z, const T* wz, int with_sum, int with_self, double* h,
-                     RedBuf rb, hipStream_t s);
+                     RedBuf rb, hipStream_t s, const DevState* skip_if_done = nullptr);
 // z -= A hA + B hB + (with_sum ? h_sum/n : 0); optional ||z||^2 into st->red[2].
 void launch_gemv_sub(int n, const double* A, int64_t lda, int na, const double* B,
                      int64_t ldb, int nb, const double* h, int with_sum, double* z,

@@ -1313,7 +1313,8 @@ __global__ __launch_bounds__(kBlock) void k_multidot(int n, const T* __restrict_
                                                      int nb, const T* __restrict__ z,
                                                      const T* __restrict__ wz, int with_sum,
                                                      int with_self, double* h,
-                                                     double* partials) {
+                                                     double* partials, const DevState* skip) {
+  if (skip && skip->done) return;
   __shared__ T zt[kTile];
   __shared__ double acc[kMaxCols];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1378,7 +1379,8 @@ __global__ __launch_bounds__(kBlock) void k_multidot(int n, const T* __restrict_
 
 // h[v] = sum over workgroups of partials[v * nblk + b]; one wave per value, fixed order.
 __global__ __launch_bounds__(64) void k_values_fin(int nv, int nblk, const double* partials,
-                                                   double* h) {
+                                                   double* h, const DevState* skip = nullptr) {
+  if (skip && skip->done) return;
   const int v = blockIdx.x;
   if (v >= nv) return;
   const double* pv = partials + (size_t)v * nblk;
@@ -1399,21 +1401,21 @@ __global__ __launch_bounds__(64) void k_values_fin(int nv, int nblk, const doubl
 template <typename T>
 void launch_multidot(int n, const T* A, int64_t lda, int na, const T* B, int64_t ldb, int nb,
                      const T* z, const T* wz, int with_sum, int with_self, double* h, RedBuf rb,
-                     hipStream_t s) {
+                     hipStream_t s, const DevState* skip_if_done) {
   int grid = (n + kTile - 1) / kTile;
   if (grid > kStreamGrid) grid = kStreamGrid;
   k_multidot<T><<<grid, kBlock, 0, s>>>(n, A, lda, na, B, ldb, nb, z, wz, with_sum, with_self,
-                                        h, rb.partials);
+                                        h, rb.partials, skip_if_done);
   const int nv = na + nb + with_sum + with_self;
-  k_values_fin<<<nv, 64, 0, s>>>(nv, grid, rb.partials, h);
+  k_values_fin<<<nv, 64, 0, s>>>(nv, grid, rb.partials, h, skip_if_done);
   HIP_LAUNCH_CHECK();
 }
 template void launch_multidot<double>(int, const double*, int64_t, int, const double*, int64_t,
                                       int, const double*, const double*, int, int, double*,
-                                      RedBuf, hipStream_t);
+                                      RedBuf, hipStream_t, const DevState*);
 template void launch_multidot<float>(int, const float*, int64_t, int, const float*, int64_t, int,
                                      const float*, const float*, int, int, double*, RedBuf,
-                                     hipStream_t);
+                                     hipStream_t, const DevState*);
 
 // z -= A hA + B hB (+ h_sum / n); optional ||z||^2 -> st->red[2].
 __global__ __launch_bounds__(kBlock) void k_gemv_sub(int n, const double* __restrict__ A,

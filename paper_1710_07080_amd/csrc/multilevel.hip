@@ -346,7 +346,8 @@ int build_coarsest(const HostLevel& A, HostCoarsest& C) {
 }
 
 // All levels on the host: lev[0] = L-hat in internal indices (trimmed row empty and
-// inactive), aggs[l] the aggregation of level l, mats[l] its transfer products.
+// inactive), aggs[l] the aggregation of level l in device numbering of level l+1, mats[l]
+// its transfer products.
 int build_host(int n, const int32_t* rp, const int32_t* col, const double* w,
                const int32_t* perm, int trim, const Params& prm, std::vector<HostLevel>& lev,
                std::vector<std::vector<int32_t>>& aggs, std::vector<HostMats>& mats,
@@ -387,13 +388,24 @@ int build_host(int n, const int32_t* rp, const int32_t* col, const double* w,
     if ((int)lev.size() >= prm.max_levels)
       return err(ISIRA_E_PRECOND, "multilevel hierarchy: coarsest level still above coarse_max at max_levels");
     std::vector<int32_t> agg;
-    const int nc = aggregate(A, by_key, agg);
+    const int nc = aggregate(A, by_key, agg);  // ids in creation order (the rule's ids)
+    // device numbering of the coarse level: aggregates in the order of their first member
+    // on this level, so that neighbouring rows of this level's products touch neighbouring
+    // coarse entries; the rule's ids stay the tie-break keys of the next aggregation
+    std::vector<int32_t> first(nc, A.n), dev(nc);
+    for (int i = 0; i < A.n; ++i)
+      if (agg[i] >= 0) first[agg[i]] = std::min(first[agg[i]], i);
+    std::vector<int32_t> byfirst(nc);
+    for (int a = 0; a < nc; ++a) byfirst[a] = a;
+    std::sort(byfirst.begin(), byfirst.end(), [&](int x, int y) { return first[x] < first[y]; });
+    for (int r = 0; r < nc; ++r) dev[byfirst[r]] = r;
+    for (int i = 0; i < A.n; ++i)
+      if (agg[i] >= 0) agg[i] = dev[agg[i]];
     HostLevel C = coarsen(A, agg, nc);
     mats.push_back(build_level_mats(A, agg, nc, prm.omega));
     aggs.push_back(std::move(agg));
     lev.push_back(std::move(C));
-    by_key.resize(nc);
-    for (int i = 0; i < nc; ++i) by_key[i] = i;
+    by_key = dev;  // device index of the aggregate with rule id 0, 1, ...
   }
   return build_coarsest(lev.back(), co);
 }

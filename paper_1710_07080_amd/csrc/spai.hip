@@ -47,7 +47,7 @@ void apply(SpaiWork& w, const SpmvPlan& plan, const int32_t* rp, const int32_t* 
   a.check_done = 1;
   launch_spmv<T>(plan, kF32Pos, a, rb, s);
   // [V-hat^T y, x^T y] -> st->t2[0..c]
-  launch_multidot<T>(n, V, ldv, c, x, ldv, 1, y, nullptr, 0, 0, st->t2, rb, s);
+  launch_multidot<T>(n, V, ldv, c, x, ldv, 1, y, nullptr, 0, 0, st->t2, rb, s, st);
 }
 
 template <typename T>

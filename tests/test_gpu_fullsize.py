@@ -105,8 +105,14 @@ def test_fullsize_multilevel_cycle(P, name):
     assert info["connected"] == [ML.connected_count(A) for A in h.A]
     x = np.random.default_rng(6).standard_normal(g.n)
     ref = np.insert(ML.vcycle(h, O.trim(x, i)), i, 0.0)
-    for prec, bound in [(0, 1e-12), (1, 3e-5)]:
+    # The coarse matrices are Galerkin sums of many fine weights, added in another order on
+    # each side, so their entries differ in the last few bits; the exact coarsest solve
+    # turns a relative perturbation u of its matrix into up to kappa(A_L) u in the cycle.
+    ev = np.linalg.eigvalsh(h.A[-1].toarray()) if h.A[-1].shape[0] > 1 else np.ones(1)
+    kappa = ev[-1] / ev[0]
+    for prec, bound in [(0, 1e-12 + 64 * 2.0 ** -53 * kappa), (1, 3e-5)]:
         y = ctx.ml_apply(torch.as_tensor(x, device="cuda"), prec=prec).cpu().numpy()
         err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
-        print(f"{name} cycle prec={prec}: relative error {err:.2e}, levels {info['rows']}")
+        print(f"{name} cycle prec={prec}: relative error {err:.2e} (bound {bound:.1e}, coarsest "
+              f"condition {kappa:.2e}), levels {info['rows']}")
         assert err <= bound

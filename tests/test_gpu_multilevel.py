@@ -88,6 +88,10 @@ def test_hierarchy_shape_matches_oracle(P, name):
 def test_cycle_matches_oracle(P, name, prec):
     g, ctx, i, info, h, cm = _setup(P, name)
     rng = np.random.default_rng(5)
+    # exact coarsest solve: a relative perturbation u of its matrix (Galerkin sums added in
+    # another order) moves the cycle by up to kappa(A_L) u
+    ev = np.linalg.eigvalsh(h.A[-1].toarray()) if h.A[-1].shape[0] > 1 else np.ones(1)
+    bound64 = 1e-12 + 64 * 2.0 ** -53 * ev[-1] / ev[0]
     for trial in range(2):
         x = rng.standard_normal(g.n)
         ref = np.insert(ML.vcycle(h, O.trim(x, i)), i, 0.0)
@@ -96,9 +100,9 @@ def test_cycle_matches_oracle(P, name, prec):
         err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
         # FP64: only the rounding of the composite transfer matrices differs;
         # FP32: vectors and values in single precision through every level
-        assert err <= (1e-12 if prec == 0 else 3e-5), err
+        assert err <= (bound64 if prec == 0 else 3e-5), err
         if prec == 0:
-            assert np.abs(y - ref).max() <= 1e-11 * np.abs(ref).max()
+            assert np.abs(y - ref).max() <= 10 * bound64 * np.abs(ref).max()
 
 
 def test_single_level_cycle_is_exact_inverse(P):
