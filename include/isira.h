@@ -243,7 +243,7 @@ int isira_adam_step(isira_ctx* ctx, float* param, const float* grad, float* m, f
  * two sparse products; it replaces any previous hierarchy of the context. */
 #define ISIRA_ML_MAX_LEVELS 32
 typedef struct {
-  double omega;        /* smoothing weight, 0 < omega < 1; default 2/3 */
+  double omega;        /* smoothing weight, 0 < omega < 1; default 0.9 */
   int32_t coarse_max;  /* 0..2048; default 512 (0: coarsen until no vertex has a neighbour) */
   int32_t max_levels;  /* 1..ISIRA_ML_MAX_LEVELS; default 24 (E_PRECOND if not enough) */
   int64_t trim_index;  /* caller label of the trimmed vertex; -1 = the default trim vertex */

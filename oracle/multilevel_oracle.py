@@ -121,7 +121,7 @@ class Hierarchy:
     trim: int                # trimmed vertex of the graph (caller label)
 
 
-def setup(g, trim: int, omega: float = 2.0 / 3.0, coarse_max: int = 1024,
+def setup(g, trim: int, omega: float = 0.9, coarse_max: int = 512,
           max_levels: int = 16) -> Hierarchy:
     """Hierarchy of A_0 = L-hat (vertex ``trim`` deleted) as defined above."""
     L = O.laplacian(g)
@@ -155,7 +155,7 @@ def vcycle(h: Hierarchy, b: np.ndarray, level: int = 0) -> np.ndarray:
     return x
 
 
-def preconditioner_factory(g, omega: float = 2.0 / 3.0, coarse_max: int = 1024,
+def preconditioner_factory(g, omega: float = 0.9, coarse_max: int = 512,
                            max_levels: int = 16) -> Callable:
     """For ``isira_oracle.isira(apply_minv_hat_factory=...)``: (trim, sigma) -> the V-cycle
     acting on trimmed (n-1)-vectors (the shift is not part of the hierarchy)."""

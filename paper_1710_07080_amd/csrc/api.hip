@@ -1467,7 +1467,7 @@ extern "C" int isira_orthonormalize(isira_ctx* c, const double* Q, int32_t ncols
 extern "C" int isira_ml_default_options(isira_ml_options* o) {
   if (!o) return fail(ISIRA_E_ARG, "NULL argument");
   std::memset(o, 0, sizeof(*o));
-  o->omega = 2.0 / 3.0;
+  o->omega = 0.9;
   o->coarse_max = 512;
   o->max_levels = 24;
   o->trim_index = -1;

@@ -92,6 +92,6 @@ def test_create_rejects_bad_graphs(P):
 def test_multilevel_defaults(P):
     o = P.isira.MlOptions()
     assert P.load().isira_ml_default_options(o) == 0
-    assert abs(o.omega - 2.0 / 3.0) < 1e-15 and o.coarse_max == 512 and o.max_levels == 24
+    assert o.omega == 0.9 and o.coarse_max == 512 and o.max_levels == 24
     assert o.trim_index == -1
     assert P.isira.PC_MULTILEVEL == 2

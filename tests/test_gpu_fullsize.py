@@ -92,7 +92,7 @@ def test_fullsize_matches_oracle(P, name, prec, pc):
 @pytest.mark.parametrize("name", ["rmat20", "grid128w"])
 def test_fullsize_multilevel_cycle(P, name):
     """Hierarchy shape (exact) and one cycle in FP64 and FP32 against the oracle's, on the
-    benchmark graphs with the default set-up (coarse_max 512, omega 2/3)."""
+    benchmark graphs with the default set-up (coarse_max 512, omega 0.9)."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     _cache.clear()

@@ -202,15 +202,19 @@ def test_inner_solve_fp32_accuracy(P):
     assert np.linalg.norm(Lt - r) <= 2e-3 * np.linalg.norm(r)
 
 
-def test_orthonormalize(P):
+# from no basis column to the widest basis of a k = 64 solve; the graph size is not a
+# multiple of the 512-row tile of the column dots
+@pytest.mark.parametrize("ncols", [0, 3, 12, 127, 128, 129, 190])
+def test_orthonormalize(P, ncols):
     g = GRAPHS["rmat14"]()
+    assert g.n % 64 != 0
     ctx = P.Context.from_graph(g)
-    rng = np.random.default_rng(6)
-    Q = np.linalg.qr(rng.standard_normal((g.n, 12)))[0]
+    rng = np.random.default_rng(6 + ncols)
+    Q = np.linalg.qr(rng.standard_normal((g.n, max(ncols, 1))))[0][:, :ncols]
     Q -= Q.mean(axis=0)
-    Q = np.linalg.qr(Q)[0]
-    z = rng.standard_normal(g.n) + Q @ rng.standard_normal(12) * 100 + 50.0
-    u, norms = ctx.orthonormalize(_dev(Q.T), _dev(z))
+    Q = np.linalg.qr(Q)[0] if ncols else Q
+    z = rng.standard_normal(g.n) + Q @ rng.standard_normal(ncols) * 100 + 50.0
+    u, norms = ctx.orthonormalize(_dev(Q.T) if ncols else None, _dev(z))
     u = u.cpu().numpy()
     Qo = np.column_stack([Q, np.ones(g.n) / math.sqrt(g.n)])
     ref, before, after = O.cgs2(Qo, z)
