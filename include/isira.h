@@ -194,6 +194,13 @@ int isira_orthonormalize(isira_ctx* ctx, const double* Q, int32_t ncols, const d
  * -- the Rayleigh-Ritz step of Algorithm 3.2.  Householder tridiagonalization followed
  * by the implicit QL iteration.  No GPU needed. */
 int isira_symeig(int32_t k, const double* H, double* theta, double* S);
+/* Host-only: all eigenvalues of the same kind of matrix (theta, k, ascending) and a unit
+ * eigenvector s1 (k) of the smallest -- what an outer iteration of Algorithm 3.2 needs when
+ * no pair is locked and no restart follows.  The same tridiagonalization, the QL iteration
+ * without eigenvectors, then inverse iteration with the tridiagonal matrix shifted by
+ * theta[0] (Gaussian elimination with partial pivoting), mapped back through the
+ * Householder reflections.  No GPU needed. */
+int isira_symeig_lowest(int32_t k, const double* H, double* theta, double* s1);
 
 /* ---- learned sparse approximate inverse (SPAI) preconditioner ---- */
 /* The network maps per-vertex features through a vertex MLP, one mean-aggregation over

@@ -1101,15 +1101,26 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     }
     outer++;
     its_pair++;
-    // ---- Rayleigh-Ritz: all eigenpairs of H, ascending
+    // ---- Rayleigh-Ritz: the eigenvalues of H (ascending) and the eigenvector of the
+    // smallest; all eigenvectors only when a pair is locked or the basis restarts
     double t0 = now_ms();
     Hk.assign((size_t)kk * kk, 0.0);
     for (int j = 0; j < kk; ++j)
       for (int i = 0; i < kk; ++i) Hk[i + (size_t)j * kk] = H[i + (size_t)j * m];
     theta.assign(kk, 0.0);
     Sm.assign((size_t)kk * kk, 0.0);
-    if ((rc = isira_symeig(kk, Hk.data(), theta.data(), Sm.data())))
+    if ((rc = isira_symeig_lowest(kk, Hk.data(), theta.data(), Sm.data())))
       return fail(rc, "Rayleigh-Ritz eigensolver did not converge");
+    bool all_vectors = false;
+    auto rayleigh_ritz_all = [&]() -> int {
+      if (all_vectors) return ISIRA_OK;
+      const double t1 = now_ms();
+      const int r2 = isira_symeig(kk, Hk.data(), theta.data(), Sm.data());
+      S.ms_rr_host += now_ms() - t1;
+      if (r2) return fail(r2, "Rayleigh-Ritz eigensolver did not converge");
+      all_vectors = true;
+      return ISIRA_OK;
+    };
     S.ms_rr_host += now_ms() - t0;
     // ---- Ritz residual r = W s1 - theta1 U s1.  The inner solve for it is queued at once,
     // behind the same wait: when the pair turns out converged that work is simply dropped.
@@ -1121,7 +1132,10 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     const double rn = std::sqrt(std::max(0.0, c->st_host->red[0]));
     S.ms_residual += now_ms() - t0;
     if (rn < tol) {
-      // fresh FP64 residual of the Ritz pair before locking
+      // the lock purges with S(:, 2:kk), so the locked vector is taken from the same full
+      // decomposition; its fresh FP64 residual decides
+      if ((rc = rayleigh_ritz_all())) return rc;
+      if ((rc = upload(c, c->svec, Sm.data(), kk * 8))) return rc;
       double* v = c->Vout + (size_t)nconv * ld;
       launch_ritz_vector(n, c->U, ld, kk, c->svec, v, s);
       spmv64(c, v, c->tmp64, nullptr, 0, nullptr, 0.0, 2, theta[0]);
@@ -1202,6 +1216,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     if (kk == m) {
       // subspace restart: U <- U S(:, 1:q), W <- W S(:, 1:q), H <- diag(theta_1..theta_q)
       // (the queued inner solve reads neither U nor W)
+      if ((rc = rayleigh_ritz_all())) return rc;
       t0 = now_ms();
       S.restarts++;
       Spack.assign((size_t)kk * q, 0.0);

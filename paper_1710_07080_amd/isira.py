@@ -110,7 +110,7 @@ class MlInfo(ctypes.Structure):
 EXPORTS = [
     "isira_default_options", "isira_create", "isira_destroy", "isira_get_info", "isira_solve",
     "isira_laplacian_apply", "isira_laplacian_apply_f32", "isira_time_spmv", "isira_inner_solve",
-    "isira_orthonormalize", "isira_symeig", "isira_spai_nparam", "isira_spai_install",
+    "isira_orthonormalize", "isira_symeig", "isira_symeig_lowest", "isira_spai_nparam", "isira_spai_install",
     "isira_spai_export", "isira_spai_loss_grad", "isira_adam_step", "isira_ml_default_options",
     "isira_ml_setup", "isira_ml_get_info", "isira_ml_apply", "isira_strerror", "isira_last_error",
 ]
@@ -148,6 +148,7 @@ def load() -> ctypes.CDLL:
                                     _c_int32_p, _c_double_p]),
         "isira_orthonormalize": (i32, [vp, vp, i32, vp, vp, _c_double_p]),
         "isira_symeig": (i32, [i32, vp, vp, vp]),
+        "isira_symeig_lowest": (i32, [i32, vp, vp, vp]),
         "isira_spai_nparam": (i32, []),
         "isira_spai_install": (i32, [vp, vp, dbl, i64]),
         "isira_spai_export": (i32, [vp, vp, vp]),
@@ -208,6 +209,17 @@ def symeig(H: np.ndarray):
     S = np.zeros((k, k), order="F")
     _check(load().isira_symeig(k, _ptr(H), _ptr(theta), _ptr(S)))
     return theta, S
+
+
+def symeig_lowest(H: np.ndarray):
+    """All eigenvalues and a unit eigenvector of the smallest, with the library's host
+    routine for outer iterations that lock nothing."""
+    H = np.asfortranarray(H, dtype=np.float64)
+    k = H.shape[0]
+    theta = np.zeros(k)
+    s1 = np.zeros(k)
+    _check(load().isira_symeig_lowest(k, _ptr(H), _ptr(theta), _ptr(s1)))
+    return theta, s1
 
 
 def current_stream() -> int:

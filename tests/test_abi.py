@@ -95,3 +95,52 @@ def test_multilevel_defaults(P):
     assert o.omega == 0.9 and o.coarse_max == 512 and o.max_levels == 24
     assert o.trim_index == -1
     assert P.isira.PC_MULTILEVEL == 2
+
+
+@pytest.mark.parametrize("case", ["random7", "random60", "random192", "clustered", "diagonal",
+                                  "k1", "k2", "graded", "rayleigh_ritz"])
+def test_host_symeig_lowest(P, case):
+    """Eigenvalues and the lowest eigenvector against numpy's LAPACK eigensolver."""
+    rng = np.random.default_rng(len(case))
+    if case.startswith("random"):
+        k = int(case[6:])
+        H = rng.standard_normal((k, k))
+        H = H + H.T
+    elif case == "clustered":  # the two smallest eigenvalues 1e-13 apart
+        k = 40
+        Q = np.linalg.qr(rng.standard_normal((k, k)))[0]
+        lam = np.concatenate([[1.0, 1.0 + 1e-13], np.linspace(2.0, 9.0, k - 2)])
+        H = (Q * lam) @ Q.T
+    elif case == "diagonal":
+        H = np.diag([3.0, 1.0, 2.0, 5.0, 0.5])
+    elif case == "k1":
+        H = np.array([[2.5]])
+    elif case == "k2":
+        H = np.array([[2.0, 1.0], [1.0, 2.0]])
+    elif case == "graded":  # eigenvalues spanning twelve orders of magnitude
+        k = 30
+        Q = np.linalg.qr(rng.standard_normal((k, k)))[0]
+        H = (Q * np.logspace(-8, 4, k)) @ Q.T
+    else:  # the projected matrix of a Laplacian on an orthonormal block orthogonal to 1
+        import scipy.sparse as sp
+        g = gg.rmat(10, 8, seed=3)
+        A = sp.csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n))
+        L = sp.diags(np.asarray(A.sum(axis=1)).ravel()) - A
+        U = rng.standard_normal((g.n, 60))
+        U -= U.mean(axis=0)
+        U = np.linalg.qr(U)[0]
+        H = U.T @ (L @ U)
+        H = 0.5 * (H + H.T)
+    theta, s1 = P.isira.symeig_lowest(H)
+    lam, V = np.linalg.eigh(H)
+    scale = max(1.0, np.abs(lam).max())
+    assert np.abs(theta - lam).max() <= 1e-13 * scale
+    assert abs(np.linalg.norm(s1) - 1.0) <= 1e-14
+    # an eigenvector of the smallest eigenvalue (within the cluster when it is not simple)
+    assert np.linalg.norm(H @ s1 - theta[0] * s1) <= 1e-13 * scale
+    # the angle to numpy's eigenvector within the Davis-Kahan bound eps ||H|| / gap
+    gap = lam[1] - lam[0] if len(lam) > 1 else np.inf
+    if gap > 1e-6 * scale:
+        v0 = V[:, 0]
+        sin = np.linalg.norm(s1 - (s1 @ v0) * v0)  # the part of s1 orthogonal to v0
+        assert sin <= 64 * 2.0 ** -53 * scale / gap + 1e-14
