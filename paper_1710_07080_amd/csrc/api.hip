@@ -1097,6 +1097,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
   int recent_its[4];
   std::fill(recent_its, recent_its + 4, cfg.check_every);
   int n_inner = 0;
+  double prev_rn = 0.0;  // residual norm of the previous outer iteration
   auto start_inner = [&]() {
     // the right-hand side is the Ritz residual in r64; its sum is st->red[1]
     if (cfg.prec == ISIRA_FP64) {
@@ -1145,10 +1146,11 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     // common case), so that an outer iteration waits once; otherwise its results, written
     // only to the unused column kk of U and W and to scratch, are dropped and it is redone.
     // Only while the last four inner solves stopped within fewer iterations than a batch
-    // holds (the first batch is then likely to finish this one too), and not when the
+    // holds (the first batch is then likely to finish this one too) and the previous
+    // residual of this pair was above 10 tol (a lock is then unlikely), and not when the
     // basis is full (the restart comes first) or inner solutions are captured.
     const bool capturing = opt.capture_r && opt.capture_z && opt.capture_count && capture_count < opt.capture_cap;
-    const bool speculative = kk < m && !capturing &&
+    const bool speculative = kk < m && !capturing && prev_rn > 10.0 * tol &&
                              *std::max_element(recent_its, recent_its + 4) < cfg.check_every;
     if (speculative) {
       if (cfg.prec == ISIRA_FP64) launch_enlarge<double>(n, c->x64, c->z64, c->st, c->rb, s);
@@ -1157,6 +1159,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     }
     if ((rc = sync_state(c))) return rc;
     const double rn = std::sqrt(std::max(0.0, c->st_host->red[0]));
+    prev_rn = rn;
     const bool inner_done_at_wait = c->st_host->done != 0;
     S.ms_residual += now_ms() - t0;
     if (rn < tol) {
