@@ -270,6 +270,14 @@ int isira_ml_default_options(isira_ml_options* opt);
  * NULL.  E_ARG for options out of range, E_PRECOND if max_levels does not suffice. */
 int isira_ml_setup(isira_ctx* ctx, const isira_ml_options* opt, isira_ml_info* info);
 int isira_ml_get_info(const isira_ctx* ctx, isira_ml_info* info);
+/* Host-only: the shape (levels, rows, stored entries, connected vertices, coarsest dense
+ * order, transfer-matrix entries) of the hierarchy that isira_ml_setup builds, for host CSR
+ * arrays in the caller's labels (no relabelling; the rule breaks ties by label either way),
+ * off-diagonal weights w (n nnz doubles, or NULL for unit weights) and the trimmed vertex
+ * trim (caller label); opt must be given.  No GPU is touched; device_bytes and setup_ms
+ * stay 0. */
+int isira_ml_shape(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* w,
+                   int64_t trim, const isira_ml_options* opt, isira_ml_info* info);
 /* y = cycle(x-hat) enlarged by a zero at the trimmed vertex; x, y device n FP64, caller
  * labels (x's trimmed entry is ignored).  prec: ISIRA_FP64, or ISIRA_FP32 (the cycle in
  * FP32 vectors and matrix values, as inside FP32 inner solves).  E_STATE before set-up. */

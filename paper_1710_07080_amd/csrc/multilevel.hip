@@ -593,6 +593,46 @@ void apply(const Hierarchy& H, const T* in, T* out, int check_done, DevState* st
   }
 }
 
+}  // namespace ml
+}  // namespace isira
+
+// Host-only: the hierarchy's shape for a caller CSR (caller labels, no relabelling), as
+// isira_ml_setup would build it; no GPU is touched.
+extern "C" int isira_ml_shape(int64_t n, const int32_t* row_ptr, const int32_t* col,
+                              const double* w, int64_t trim, const isira_ml_options* opt,
+                              isira_ml_info* info) {
+  using namespace isira::ml;
+  if (n < 3 || !row_ptr || !col || !opt || !info) return isira::set_error(ISIRA_E_ARG, "bad argument");
+  if (trim < 0 || trim >= n) return isira::set_error(ISIRA_E_ARG, "trim out of range");
+  if (!(opt->omega > 0.0 && opt->omega < 1.0) || opt->coarse_max < 0 || opt->coarse_max > 2048 ||
+      opt->max_levels < 1 || opt->max_levels > ISIRA_ML_MAX_LEVELS)
+    return isira::set_error(ISIRA_E_ARG, "options out of range");
+  std::vector<int32_t> perm((size_t)n);
+  for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+  std::vector<HostLevel> lev;
+  std::vector<std::vector<int32_t>> aggs;
+  std::vector<HostMats> mats;
+  HostCoarsest co;
+  Params prm{opt->omega, opt->coarse_max, opt->max_levels};
+  const int rc = build_host((int)n, row_ptr, col, w, perm.data(), (int)trim, prm, lev, aggs, mats, co);
+  if (rc) return rc;
+  std::memset(info, 0, sizeof(*info));
+  info->levels = (int32_t)lev.size();
+  for (size_t l = 0; l < lev.size() && l < ISIRA_ML_MAX_LEVELS; ++l) {
+    int64_t conn = 0;
+    for (int i = 0; i < lev[l].n; ++i) conn += lev[l].rowlen(i) > 0;
+    info->rows[l] = l == 0 ? lev[l].n - 1 : lev[l].n;
+    info->offdiag_nnz[l] = (int64_t)lev[l].col.size();
+    info->connected[l] = conn;
+  }
+  info->coarsest_dense = co.m;
+  for (const HostMats& M : mats) info->stored_nnz += (int64_t)M.dcol.size() + (int64_t)M.ucol.size();
+  return ISIRA_OK;
+}
+
+namespace isira {
+namespace ml {
+
 template void apply<double>(const Hierarchy&, const double*, double*, int, DevState*, RedBuf,
                             hipStream_t, bool);
 template void apply<float>(const Hierarchy&, const float*, float*, int, DevState*, RedBuf,

@@ -112,7 +112,8 @@ EXPORTS = [
     "isira_laplacian_apply", "isira_laplacian_apply_f32", "isira_time_spmv", "isira_inner_solve",
     "isira_orthonormalize", "isira_symeig", "isira_symeig_lowest", "isira_spai_nparam", "isira_spai_install",
     "isira_spai_export", "isira_spai_loss_grad", "isira_adam_step", "isira_ml_default_options",
-    "isira_ml_setup", "isira_ml_get_info", "isira_ml_apply", "isira_strerror", "isira_last_error",
+    "isira_ml_setup", "isira_ml_get_info", "isira_ml_apply", "isira_ml_shape", "isira_strerror",
+    "isira_last_error",
 ]
 
 _lib = None
@@ -159,6 +160,7 @@ def load() -> ctypes.CDLL:
         "isira_ml_setup": (i32, [vp, ctypes.POINTER(MlOptions), ctypes.POINTER(MlInfo)]),
         "isira_ml_get_info": (i32, [vp, ctypes.POINTER(MlInfo)]),
         "isira_ml_apply": (i32, [vp, i32, vp, vp]),
+        "isira_ml_shape": (i32, [i64, vp, vp, vp, i64, ctypes.POINTER(MlOptions), ctypes.POINTER(MlInfo)]),
         "isira_strerror": (ctypes.c_char_p, [i32]),
         "isira_last_error": (ctypes.c_char_p, []),
     }
@@ -209,6 +211,20 @@ def symeig(H: np.ndarray):
     S = np.zeros((k, k), order="F")
     _check(load().isira_symeig(k, _ptr(H), _ptr(theta), _ptr(S)))
     return theta, S
+
+
+def ml_shape(g, trim: int, omega: float = 0.9, coarse_max: int = 512, max_levels: int = 24) -> dict:
+    """Host-only shape of the multilevel hierarchy for graph g (caller labels)."""
+    o = MlOptions()
+    o.omega, o.coarse_max, o.max_levels, o.trim_index = float(omega), int(coarse_max), int(max_levels), int(trim)
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    w = None if g.w is None else np.ascontiguousarray(g.w, dtype=np.float64)
+    inf = MlInfo()
+    _check(load().isira_ml_shape(int(g.n), rp.ctypes.data, col.ctypes.data,
+                                 None if w is None else w.ctypes.data, int(trim), ctypes.byref(o),
+                                 ctypes.byref(inf)))
+    return inf.as_dict()
 
 
 def symeig_lowest(H: np.ndarray):
