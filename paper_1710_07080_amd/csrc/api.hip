@@ -1049,47 +1049,35 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     return upload(c, c->Ginv, Gi.data(), Gi.size() * 8);
   };
 
-  // Expansion: orthonormalize z against [U V 1] and append u = U(:, kk),
-  // w = (L + delta V V^T) u = W(:, kk) and the new column of H.  queue_expansion only
-  // queues the work (its results are read at the next wait); commit_expansion, after that
-  // wait, appends the column, or returns false on a CGS2 breakdown (nothing appended).
-  auto queue_expansion = [&](double* z) -> int {
+  auto expand_with = [&](double* z) -> int {
+    // orthonormalize z against [U V 1] and append u, w = (L + delta V V^T) u and the new
+    // column of H.  Everything is queued behind one wait; on a CGS2 breakdown (rare) the
+    // queued results are discarded and a replacement vector is expanded instead.
+    double nrm[2];
     int r2;
+    double t0 = now_ms();
     double* u = c->U + (size_t)kk * ld;
     double* w = c->W + (size_t)kk * ld;
-    if ((r2 = cgs2_queue(c, c->U, kk, c->Vout, nconv, z))) return r2;
-    launch_scale_dev(n, z, c->st->red + 2, u, s);
-    if (nconv > 0)
-      launch_multidot<double>(n, c->Vout, ld, nconv, nullptr, ld, 0, u, nullptr, 0, 0, c->hbuf, c->rb, s);
-    spmv64(c, u, w, c->Vout, nconv, c->hbuf, delta, 0, 0.0);
-    launch_multidot<double>(n, c->U, ld, kk + 1, nullptr, ld, 0, w, nullptr, 0, 0, c->hbuf, c->rb, s);
-    return read_h(c, kk + 1);
-  };
-  auto commit_expansion = [&]() -> bool {
-    double nrm[2];
-    S.spmv_total++;
-    cgs2_norms(c, kk + nconv, nrm);
-    if (!(nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0)) {
+    for (;;) {
+      if ((r2 = cgs2_queue(c, c->U, kk, c->Vout, nconv, z))) return r2;
+      launch_scale_dev(n, z, c->st->red + 2, u, s);
+      if (nconv > 0)
+        launch_multidot<double>(n, c->Vout, ld, nconv, nullptr, ld, 0, u, nullptr, 0, 0, c->hbuf, c->rb, s);
+      spmv64(c, u, w, c->Vout, nconv, c->hbuf, delta, 0, 0.0);
+      launch_multidot<double>(n, c->U, ld, kk + 1, nullptr, ld, 0, w, nullptr, 0, 0, c->hbuf, c->rb, s);
+      if ((r2 = read_h(c, kk + 1))) return r2;
+      if ((r2 = sync_state(c))) return r2;
+      S.spmv_total++;
+      cgs2_norms(c, kk + nconv, nrm);
+      if (nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0) break;
       S.breakdowns++;
-      return false;
+      launch_fill_replacement(n, opt.seed, draws++, c->d_perm, z, s);
     }
     for (int i = 0; i <= kk; ++i) {
       H[i + (size_t)kk * m] = c->hbuf_host[i];
       H[kk + (size_t)i * m] = c->hbuf_host[i];
     }
     kk += 1;
-    return true;
-  };
-  auto expand_with = [&](double* z) -> int {
-    // on a CGS2 breakdown (rare) a replacement vector is expanded instead
-    int r2;
-    double t0 = now_ms();
-    for (;;) {
-      if ((r2 = queue_expansion(z))) return r2;
-      if ((r2 = sync_state(c))) return r2;
-      if (commit_expansion()) break;
-      launch_fill_replacement(n, opt.seed, draws++, c->d_perm, z, s);
-    }
     S.ms_ortho += now_ms() - t0;
     return ISIRA_OK;
   };
@@ -1097,7 +1085,6 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
   int recent_its[4];
   std::fill(recent_its, recent_its + 4, cfg.check_every);
   int n_inner = 0;
-  double prev_rn = 0.0;  // residual norm of the previous outer iteration
   auto start_inner = [&]() {
     // the right-hand side is the Ritz residual in r64; its sum is st->red[1]
     if (cfg.prec == ISIRA_FP64) {
@@ -1141,26 +1128,8 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     if ((rc = upload(c, c->svec, Sm.data(), kk * 8))) return rc;
     launch_ritz_residual(n, c->U, c->W, ld, kk, c->svec, theta[0], c->r64, c->st, c->rb, s);
     start_inner();
-    // The expansion by the inner solution is queued too, behind the same wait: it is used
-    // when the inner solve has stopped within its first batch and no pair is locked (the
-    // common case), so that an outer iteration waits once; otherwise its results, written
-    // only to the unused column kk of U and W and to scratch, are dropped and it is redone.
-    // Only while the last four inner solves stopped within fewer iterations than a batch
-    // holds (the first batch is then likely to finish this one too) and the previous
-    // residual of this pair was above 10 tol (a lock is then unlikely), and not when the
-    // basis is full (the restart comes first) or inner solutions are captured.
-    const bool capturing = opt.capture_r && opt.capture_z && opt.capture_count && capture_count < opt.capture_cap;
-    const bool speculative = kk < m && !capturing && prev_rn > 10.0 * tol &&
-                             *std::max_element(recent_its, recent_its + 4) < cfg.check_every;
-    if (speculative) {
-      if (cfg.prec == ISIRA_FP64) launch_enlarge<double>(n, c->x64, c->z64, c->st, c->rb, s);
-      else launch_enlarge<float>(n, c->x32, c->z64, c->st, c->rb, s);
-      if ((rc = queue_expansion(c->z64))) return rc;
-    }
     if ((rc = sync_state(c))) return rc;
     const double rn = std::sqrt(std::max(0.0, c->st_host->red[0]));
-    prev_rn = rn;
-    const bool inner_done_at_wait = c->st_host->done != 0;
     S.ms_residual += now_ms() - t0;
     if (rn < tol) {
       // the lock purges with S(:, 2:kk), so the locked vector is taken from the same full
@@ -1282,14 +1251,6 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     S.inner_total += its;
     S.spmv_total += its;
     inner_pair += its;
-    if (speculative && inner_done_at_wait) {
-      // the expansion queued with the inner solve used its final solution
-      S.ms_inner += now_ms() - t0;
-      if (commit_expansion()) continue;
-      launch_fill_replacement(n, opt.seed, draws++, c->d_perm, c->z64, s);
-      if ((rc = expand_with(c->z64))) return rc;
-      continue;
-    }
     if (cfg.prec == ISIRA_FP64) {
       launch_enlarge<double>(n, c->x64, c->z64, c->st, c->rb, s);
     } else {
