@@ -18,6 +18,10 @@ Features f_i = [1, log d_i, log n_i, mean_j log d_j, max_j log d_j, sigma/d_i, 1
 Loss over samples (r_s, z_s):  (1/S) sum_s ||M r_s - z_s||^2 / ||z_s||^2, with the row of the
 trimmed vertex of M r forced to 0.  The backward pass below is written out by hand and is
 pinned by central finite differences in the tests.
+Pruning (optional, after the forward pass): an off-diagonal m_ij is kept when it is nonzero
+and |m_ij| >= tau sqrt(M_ii M_jj); the others become 0.  The rule is symmetric in (i, j) and
+only removes off-diagonal weight, so the pruned M stays symmetric and strictly diagonally
+dominant with a positive diagonal, hence SPD.
 """
 from __future__ import annotations
 
@@ -152,6 +156,16 @@ def apply(g, diag, offd, trim: int, X: np.ndarray) -> np.ndarray:
     np.add.at(Y, rows, offd[:, None] * X2[col])
     Y[trim] = 0.0
     return Y if X.ndim == 2 else Y[:, 0]
+
+
+def prune(g, diag, offd, tau: float) -> np.ndarray:
+    """Off-diagonal values after pruning with threshold tau (rule in the module docstring),
+    in the CSR order of g; the decision is taken in FP64 from the values given."""
+    rp, col, rows, w, d, cnt = _graph_arrays(g)
+    diag = np.asarray(diag, dtype=np.float64)
+    offd = np.asarray(offd, dtype=np.float64)
+    keep = (offd != 0.0) & (np.abs(offd) >= tau * np.sqrt(diag[rows] * diag[col]))
+    return np.where(keep, offd, 0.0)
 
 
 def dense_M(g, diag, offd) -> np.ndarray:

@@ -1,11 +1,16 @@
 """Pins of the SPAI network oracle: central finite differences of its hand-written
 backward pass, the SPD construction, BF16 rounding, and the Jacobi special case."""
+import pathlib
+
 import numpy as np
 import pytest
 
 import graphgen as gg
 from oracle import spai_oracle as SO
 from oracle import isira_oracle as O
+
+# trained network weights shipped with the package (plain FP32 array, no pickle)
+WEIGHTS = pathlib.Path(__file__).resolve().parents[1] / "paper_1710_07080_amd" / "weights" / "spai_rmat_h16.npy"
 
 
 def _samples(g, trim, S, seed):
@@ -77,3 +82,59 @@ def test_zero_network_is_jacobi():
     ref[trim] = 0.0
     assert np.allclose(fw["diag"], ref, rtol=1e-14)
     assert np.all(fw["offd"] == 0.0)
+
+
+def test_prune_by_hand():
+    # path 0-1-2 with M_00 = 4, M_11 = 1, M_22 = 9 and m_01 = 0.5, m_12 = -1.2:
+    # sqrt(M_00 M_11) = 2, sqrt(M_11 M_22) = 3; tau = 0.2 keeps |0.5| >= 0.4 and
+    # |-1.2| >= 0.6; tau = 0.3 drops m_01 (0.5 < 0.6) and keeps m_12 (1.2 >= 0.9); tau = 0.25
+    # keeps m_01 at equality (0.5 >= 0.5)
+    g = gg.path_graph(3)
+    diag = np.array([4.0, 1.0, 9.0])
+    # CSR order: row 0: (0,1); row 1: (1,0), (1,2); row 2: (2,1)
+    offd = np.array([0.5, 0.5, -1.2, -1.2])
+    assert g.col.tolist() == [1, 0, 2, 1]
+    assert SO.prune(g, diag, offd, 0.2).tolist() == [0.5, 0.5, -1.2, -1.2]
+    assert SO.prune(g, diag, offd, 0.3).tolist() == [0.0, 0.0, -1.2, -1.2]
+    assert SO.prune(g, diag, offd, 0.25).tolist() == [0.5, 0.5, -1.2, -1.2]
+    assert SO.prune(g, diag, offd, 0.5).tolist() == [0.0] * 4
+
+
+def test_prune_keeps_spd_and_nests():
+    g = gg.rmat(9, 8, seed=6)
+    trim = O.trim_index(O.degrees(g))
+    params = np.load(WEIGHTS)
+    fw = SO.forward(g, params, 0.0, trim)
+    keep = np.array([i for i in range(g.n) if i != trim])
+    prev = None
+    for tau in [0.0, 0.01, 0.03, 0.1, 0.3]:
+        off = SO.prune(g, fw["diag"], fw["offd"], tau)
+        if tau == 0.0:
+            assert np.array_equal(off, fw["offd"])  # every nonzero is kept
+        kept = off != 0.0
+        assert np.array_equal(off[kept], fw["offd"][kept])  # kept values are unchanged
+        if prev is not None:
+            assert not np.any(kept & ~prev)  # a larger threshold keeps a subset
+        prev = kept
+        M = SO.dense_M(g, fw["diag"], off)[np.ix_(keep, keep)]
+        assert np.array_equal(M, M.T)
+        offsum = np.abs(M).sum(axis=1) - np.diag(M)
+        assert np.all(offsum < np.diag(M))
+        assert np.linalg.eigvalsh(M).min() > 0
+    assert 0 < int(prev.sum()) < fw["offd"].size
+
+
+def test_isira_with_pruned_learned_matches_dense():
+    g = gg.rmat(9, 8, seed=11)
+    k = 6
+    params = np.load(WEIGHTS)
+
+    def factory(trim, sigma):
+        fw = SO.forward(g, params, sigma, trim)
+        off = SO.prune(g, fw["diag"], fw["offd"], 0.02)
+        return lambda x: O.trim(SO.apply(g, fw["diag"], off, trim, np.insert(x, trim, 0.0)), trim)
+
+    res = O.isira(g, k, 0.0, 1e-10, gg.start_block(g.n, 4, 1), inner_rtol=1e-1,
+                  apply_minv_hat_factory=factory)
+    ref, _ = O.smallest_positive_eigenpairs_dense(g, k)
+    assert np.allclose(np.sort(res.evals), ref, rtol=1e-9, atol=0)
