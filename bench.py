@@ -53,6 +53,9 @@ def workload(name):
 
 SPAI_WEIGHTS = os.path.join(HERE, "paper_1710_07080_amd", "weights", "spai_rmat_h16.npy")
 CAL_BYTES = 256 << 20  # size of the calibration copy in --probe runs
+# pruning threshold of the learned M's variant: keeps off-diagonals with
+# |m_ij| >= tau sqrt(M_ii M_jj), a few percent of them for the trained network
+PRUNE_TAU = 0.02
 # HBM traffic of the dominant kernel from rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE),
 # with the sources it was measured on; it is reported only while those sources are unchanged.
 TRAFFIC_SUMMARY = os.path.join(HERE, "profiles", "k_spmv_fp64_rmat20_traffic.md")
@@ -228,6 +231,14 @@ def shift_study(ctx, g, cfg, opts, args, P):
                       "tol": cfg["tol"], "rows": rows}), flush=True)
 
 
+def prune_setup(ctx) -> dict:
+    """Prunes the installed learned M with PRUNE_TAU; the set-up's own cost, reported."""
+    t = time.perf_counter()
+    kept = ctx.spai_prune(PRUNE_TAU)
+    return {"prune_tau": PRUNE_TAU, "kept_offdiag": kept, "kept_frac": kept / ctx.nnz,
+            "prune_setup_s": time.perf_counter() - t}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,7 +249,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--precond", choices=["jacobi", "learned", "multilevel"], default="jacobi",
+    ap.add_argument("--precond", choices=["jacobi", "learned", "learned_pruned", "multilevel"],
+                    default="jacobi",
                     help="preconditioner of the timed solve (default: the plain method's Jacobi)")
     ap.add_argument("--inner-prec", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the timed solve's inner solves (default: the plain FP64 method)")
@@ -291,6 +303,7 @@ def main():
     opts = dict(u0=u0, inner_rtol=args.inner_rtol)
     # the timed solve: the plain FP64 method unless another form is asked for
     main_pc = {"jacobi": P.isira.PC_JACOBI, "learned": P.isira.PC_LEARNED,
+               "learned_pruned": P.isira.PC_LEARNED,
                "multilevel": P.isira.PC_MULTILEVEL}[args.precond]
     main_prec = P.isira.FP32 if args.inner_prec == "fp32" else P.isira.FP64
     main_setup = {}
@@ -301,6 +314,9 @@ def main():
         from paper_1710_07080_amd import spai_train
 
         ctx.spai_install(spai_train.load(SPAI_WEIGHTS), sigma=cfg["sigma"])
+        if args.precond == "learned_pruned":
+            main_setup = prune_setup(ctx)
+            log(f"pruned learned M: {main_setup}")
     main_opts = dict(opts, inner_prec=main_prec, precond=main_pc)
     if args.study == "trim":
         trim_study(ctx, g, cfg, opts, args)
@@ -383,23 +399,28 @@ def main():
         # the same solve with FP32 inner solves, Jacobi and learned preconditioner
         # and the purge step's moving shift (sigma <- theta_2, MINRES inner solves)
         fixed, moving = P.isira.SHIFT_FIXED, P.isira.SHIFT_MOVING
-        variants = [("fp32_jacobi", P.isira.FP32, P.isira.PC_JACOBI, fixed)]
+        # (name, inner precision, preconditioner, shift mode, set-up run before its solves)
+        variants = [("fp32_jacobi", P.isira.FP32, P.isira.PC_JACOBI, fixed, None)]
         if os.path.exists(SPAI_WEIGHTS):
             from paper_1710_07080_amd import spai_train
 
             ctx.spai_install(spai_train.load(SPAI_WEIGHTS), sigma=cfg["sigma"])
-            variants.append(("fp32_learned", P.isira.FP32, P.isira.PC_LEARNED, fixed))
-        variants += [("moving_shift_fp64", P.isira.FP64, P.isira.PC_JACOBI, moving),
-                     ("moving_shift_fp32", P.isira.FP32, P.isira.PC_JACOBI, moving)]
+            variants.append(("fp32_learned", P.isira.FP32, P.isira.PC_LEARNED, fixed, None))
+            # the same M pruned to its largest off-diagonal entries (set-up timed on its own)
+            variants.append(("fp32_learned_pruned", P.isira.FP32, P.isira.PC_LEARNED, fixed,
+                             lambda: prune_setup(ctx)))
+        variants += [("moving_shift_fp64", P.isira.FP64, P.isira.PC_JACOBI, moving, None),
+                     ("moving_shift_fp32", P.isira.FP32, P.isira.PC_JACOBI, moving, None)]
         # multilevel preconditioner (aggregation multigrid for L-hat): set-up once per
         # graph and trim index, outside the timed solves, reported on its own
         mlinfo = ctx.ml_setup()
         out["multilevel_setup"] = {k: mlinfo[k] for k in ("levels", "rows", "connected", "coarsest_dense",
                                                           "stored_nnz", "device_bytes", "setup_ms")}
         log(f"multilevel set-up: {out['multilevel_setup']}")
-        variants += [("multilevel_fp64", P.isira.FP64, P.isira.PC_MULTILEVEL, fixed),
-                     ("multilevel_fp32", P.isira.FP32, P.isira.PC_MULTILEVEL, fixed)]
-        for name, prec, pc, mode in variants:
+        variants += [("multilevel_fp64", P.isira.FP64, P.isira.PC_MULTILEVEL, fixed, None),
+                     ("multilevel_fp32", P.isira.FP32, P.isira.PC_MULTILEVEL, fixed, None)]
+        for name, prec, pc, mode, prep in variants:
+            extra = prep() if prep is not None else {}
             best = None
             for _ in range(max(1, args.steps)):
                 evv, Xv, resv, stv = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], inner_prec=prec,
@@ -410,7 +431,7 @@ def main():
             row = {"s": stv["ms_total"] / 1e3, "converged": stv["n_converged"],
                    "outer_total": stv["outer_total"], "inner_total": stv["inner_total"],
                    "max_resid": float(np.max(resv)) if len(resv) else None,
-                   "speedup_vs_plain_fp64": (st["ms_total"] / stv["ms_total"])}
+                   "speedup_vs_plain_fp64": (st["ms_total"] / stv["ms_total"]), **extra}
             if gold is not None:
                 row[ref_key(args.workload)] = rel_err(evv, gold)
             a, b = np.sort(evv), np.sort(ev)

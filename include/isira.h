@@ -215,6 +215,19 @@ int32_t isira_spai_nparam(void);
 /* Compute M for (graph, sigma, trim) from params (device FP32) and install it in the
  * context as the ISIRA_PC_LEARNED preconditioner. */
 int isira_spai_install(isira_ctx* ctx, const float* params, double sigma, int64_t trim);
+/* Prune the installed M: an off-diagonal m_ij is kept when it is nonzero and
+ * |m_ij| >= tau * sqrt(M_ii * M_jj) (decided in FP64 from the stored FP32 values); the
+ * others become 0.  The rule is symmetric in (i, j) and removes only off-diagonal weight,
+ * so M stays symmetric and strictly diagonally dominant with a positive diagonal (SPD), a
+ * valid M-hat_sigma for Remark 3.2.  tau = 0 keeps every nonzero.  Afterwards every apply
+ * of M (inner PCG, the Y = M V-hat columns of eq. (3.5), isira_spai_export) uses the pruned
+ * matrix; the PCG step then applies it by one thread per row, fused with the dots of the
+ * Jacobi form, which pays off when few entries per row are kept (tau around 0.01-0.1 for
+ * the trained network).  Install again to undo.  *kept (host, may be NULL): the number of
+ * stored off-diagonal entries kept.  Host memory of about 13 bytes per stored entry is
+ * used while it runs.  Errors: ISIRA_E_ARG (tau < 0 or not finite), ISIRA_E_PRECOND (no
+ * learned M installed, or values found not symmetric), ISIRA_E_HIP. */
+int isira_spai_prune(isira_ctx* ctx, double tau, int64_t* kept);
 /* Export the installed M: diag (device n FP32, caller labels) and off-diagonal values
  * (device nnz FP32) in the caller's CSR order. */
 int isira_spai_export(isira_ctx* ctx, float* diag, float* offd);

@@ -783,7 +783,16 @@ void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
   for (int it = 0; it < iters; ++it) {
     const int first = init && it == 0;
     if (!first) launch_spmv<T>(c->plan, vm, a, c->rb, s);
-    if (learned) {
+    if (learned && c->spw.pruned) {
+      // pruned M: the residual update, then u = M r with the dots of the Jacobi form and its
+      // finishing dispatch (eq. (3.5)), then z = u - delta Y g and the new direction
+      launch_pcg_update1_plain<T>(n, b.x, b.r, b.p, b.q, b.V, c->ld, nc, cfg.delta, cfg.trim,
+                                  sig_over_n, first, c->st, c->rb, s, /*with_fin=*/false);
+      spai::sparse_step<T>(c->spw, n, b.r, b.y, b.V, c->ld, nc, c->Ginv, cfg.delta, first, c->st,
+                           c->rb, s);
+      launch_pcg_update2_learned<T>(n, b.y, b.p, b.Y, c->ld, nc, b.V, cfg.delta, first, c->st,
+                                    c->rb, s);
+    } else if (learned) {
       // y = M r with the dots V-hat^T y and r^T y, then eq. (3.5)
       launch_pcg_update1_plain<T>(n, b.x, b.r, b.p, b.q, b.V, c->ld, nc, cfg.delta, cfg.trim,
                                   sig_over_n, first, c->st, c->rb, s);
@@ -1585,9 +1594,85 @@ extern "C" int isira_spai_install(isira_ctx* c, const float* params, double sigm
                     c->stream))
     return fail(ISIRA_E_HIP, "SPAI forward failed");
   SYNC_OR_RETURN(c);
+  spai::free_pruned(c->spw);  // new values: any earlier pruning is void
   c->has_learned = true;
   c->spai_sigma = sigma;
   c->spai_trim = t;
+  return ISIRA_OK;
+}
+
+extern "C" int isira_spai_prune(isira_ctx* c, double tau, int64_t* kept) {
+  if (!c) return fail(ISIRA_E_ARG, "NULL context");
+  if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(ISIRA_E_ARG, "need a finite tau >= 0");
+  if (!c->has_learned) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
+  const int64_t n = c->n, nnz = c->nnz;
+  std::vector<int32_t> rp((size_t)n + 1), col((size_t)nnz);
+  std::vector<float> off((size_t)nnz), dg((size_t)n);
+  CKH(hipStreamSynchronize(c->stream));
+  CKH(hipMemcpy(rp.data(), c->rp, rp.size() * 4, hipMemcpyDeviceToHost));
+  CKH(hipMemcpy(col.data(), c->col, col.size() * 4, hipMemcpyDeviceToHost));
+  CKH(hipMemcpy(off.data(), c->spw.offd, off.size() * 4, hipMemcpyDeviceToHost));
+  CKH(hipMemcpy(dg.data(), c->spw.diag32, dg.size() * 4, hipMemcpyDeviceToHost));
+  // keep m_ij when nonzero and |m_ij| >= tau sqrt(M_ii M_jj), decided in FP64 from the
+  // stored FP32 values; symmetric in (i, j) because m_ij and m_ji are equal
+  std::vector<uint8_t> keep((size_t)nnz);
+  std::vector<int32_t> cnt((size_t)n);
+  std::atomic<int> asym{0};
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) {
+      int k = 0;
+      for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
+        const double m = (double)off[j];
+        const bool kp = m != 0.0 && std::fabs(m) >= tau * std::sqrt((double)dg[i] * (double)dg[col[j]]);
+        keep[j] = kp;
+        k += kp;
+        if (kp) {  // the transposed entry must carry the same value
+          const int32_t o = col[j];
+          const int32_t* f = std::lower_bound(col.data() + rp[o], col.data() + rp[o + 1], (int32_t)i);
+          if (f == col.data() + rp[o + 1] || *f != (int32_t)i || off[f - col.data()] != off[j]) asym = 1;
+        }
+      }
+      cnt[i] = k;
+    }
+  });
+  if (asym) return fail(ISIRA_E_PRECOND, "learned values are not symmetric");
+  std::vector<int32_t> prp((size_t)n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) prp[i + 1] = prp[i] + cnt[i];
+  const int64_t pnnz = prp[n];
+  std::vector<int32_t> pcol((size_t)pnnz);
+  std::vector<float> pval((size_t)pnnz);
+  parallel_for(n, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) {
+      int32_t o = prp[i];
+      for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
+        if (keep[j]) {
+          pcol[o] = col[j];
+          pval[o] = off[j];
+          ++o;
+        } else {
+          off[j] = 0.0f;
+        }
+      }
+    }
+  });
+  spai::free_pruned(c->spw);
+  int rc;
+  auto undo = [&](int code) {
+    spai::free_pruned(c->spw);
+    return code;
+  };
+  if ((rc = dalloc(&c->spw.prp, (size_t)n + 1))) return undo(rc);
+  if ((rc = dalloc(&c->spw.pcol, (size_t)pnnz))) return undo(rc);
+  if ((rc = dalloc(&c->spw.pval, (size_t)pnnz))) return undo(rc);
+  hipError_t e = hipMemcpy(c->spw.prp, prp.data(), prp.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && pnnz > 0) e = hipMemcpy(c->spw.pcol, pcol.data(), pcol.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && pnnz > 0) e = hipMemcpy(c->spw.pval, pval.data(), pval.size() * 4, hipMemcpyHostToDevice);
+  // the full-pattern values follow the pruning too (export, and any product on the pattern)
+  if (e == hipSuccess) e = hipMemcpy(c->spw.offd, off.data(), off.size() * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return undo(fail(ISIRA_E_HIP, std::string("isira_spai_prune upload: ") + hipGetErrorString(e)));
+  c->spw.pruned = true;
+  c->spw.pnnz = pnnz;
+  if (kept) *kept = pnnz;
   return ISIRA_OK;
 }
 
@@ -1611,6 +1696,7 @@ extern "C" int isira_spai_loss_grad(isira_ctx* c, const float* params, double si
   const void* wts = c->wdt == ISIRA_W_NONE ? nullptr : (const void*)c->w32;
   const int wdt = c->wdt == ISIRA_W_NONE ? ISIRA_W_NONE : ISIRA_W_F32;
   c->has_learned = false;  // the forward pass below overwrites the installed values
+  spai::free_pruned(c->spw);
   if (spai::loss_grad(c->spw, c->rp, c->col, wts, wdt, c->deg, (int)c->n, c->nnz, sigma, t, params,
                       c->d_perm, r, z, S, grad, loss, c->rb, c->stream))
     return fail(ISIRA_E_HIP, "SPAI loss/gradient failed");

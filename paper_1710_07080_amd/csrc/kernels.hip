@@ -1175,7 +1175,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update2_learned(
 template <typename T>
 void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, const T* V,
                               int64_t ldv, int c, double delta, int trim, double sig_over_n,
-                              int init, DevState* st, RedBuf rb, hipStream_t s) {
+                              int init, DevState* st, RedBuf rb, hipStream_t s, bool with_fin) {
   const int grid = stream_grid(n);
 #define ISIRA_UPD1P(CMV)                                                                  \
   k_pcg_update1_plain<T, CMV><<<grid, kBlock, 0, s>>>(n, x, r, p, q, V, ldv, c, delta, trim, \
@@ -1184,9 +1184,99 @@ void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, const T
     ISIRA_CM_CASES(ISIRA_UPD1P)
   }
 #undef ISIRA_UPD1P
-  k_pcg_fin1_plain<<<1, kFin, 0, s>>>(grid, rb.partials, init, st);
+  if (with_fin) k_pcg_fin1_plain<<<1, kFin, 0, s>>>(grid, rb.partials, init, st);
   HIP_LAUNCH_CHECK();
 }
+
+// Pruned learned M = diag(mdiag) + the kept off-diagonal entries (CSR prp/pcol/pval, a few
+// per row at the thresholds it is meant for): one thread per row.  u = M r; partials
+// ||r||^2, r^T u and V-hat^T u in the layout of k_pcg_update1, so that k_pcg_fin1 forms
+// g = G^-1 V-hat^T u and rho = r^T u - delta t2^T g (eq. (3.5)) as for Jacobi.  The trimmed
+// row has a zero diagonal and no kept entries, so u is 0 there.
+template <typename T, int CM>
+__global__ __launch_bounds__(kBlock) void k_spai_sparse_step(
+    int n, const T* __restrict__ r, T* __restrict__ u, const int32_t* __restrict__ prp,
+    const int32_t* __restrict__ pcol, const float* __restrict__ pval,
+    const T* __restrict__ mdiag, const T* __restrict__ V, int64_t ldv, int c, DevState* st,
+    double* partials) {
+  if (st->done) return;
+  constexpr int NV = 2 + (CM > 0 ? CM : 0);
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    T vreg[CM > 0 ? CM : 1];
+#pragma unroll
+    for (int j = 0; j < CM; ++j) vreg[j] = V[l + (int64_t)j * ldv];
+    const T rl = r[l];
+    T ul = mdiag[l] * rl;
+    const int e1 = prp[l + 1];
+    for (int e = prp[l]; e < e1; ++e) ul += (T)pval[e] * r[pcol[e]];
+    u[l] = ul;
+    acc[0] += (double)rl * (double)rl;
+    acc[1] += (double)rl * (double)ul;
+#pragma unroll
+    for (int j = 0; j < CM; ++j) acc[2 + j] += (double)vreg[j] * (double)ul;
+  }
+  write_partials<NV>(acc, 2 + c, partials);
+}
+
+template <typename T>
+void launch_spai_sparse_step(int n, const T* r, T* u, const int32_t* prp, const int32_t* pcol,
+                             const float* pval, const T* mdiag, const T* V, int64_t ldv, int c,
+                             const double* Ginv, double delta, int init, DevState* st, RedBuf rb,
+                             hipStream_t s) {
+  const int grid = stream_grid(n);
+#define ISIRA_SPSTEP(CMV)                                                                    \
+  k_spai_sparse_step<T, CMV><<<grid, kBlock, 0, s>>>(n, r, u, prp, pcol, pval, mdiag, V, ldv, c, \
+                                                     st, rb.partials)
+  switch (pick_cm(c)) {
+    ISIRA_CM_CASES(ISIRA_SPSTEP)
+  }
+#undef ISIRA_SPSTEP
+  k_pcg_fin1<<<1, kFin, 0, s>>>(c, grid, rb.partials, Ginv, delta, init, st);
+  HIP_LAUNCH_CHECK();
+}
+template void launch_spai_sparse_step<double>(int, const double*, double*, const int32_t*,
+                                              const int32_t*, const float*, const double*,
+                                              const double*, int64_t, int, const double*, double,
+                                              int, DevState*, RedBuf, hipStream_t);
+template void launch_spai_sparse_step<float>(int, const float*, float*, const int32_t*,
+                                             const int32_t*, const float*, const float*,
+                                             const float*, int64_t, int, const double*, double,
+                                             int, DevState*, RedBuf, hipStream_t);
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spai_sparse_mv(int n, const T* __restrict__ x,
+                                                           T* __restrict__ y,
+                                                           const int32_t* __restrict__ prp,
+                                                           const int32_t* __restrict__ pcol,
+                                                           const float* __restrict__ pval,
+                                                           const T* __restrict__ mdiag,
+                                                           const DevState* skip) {
+  if (skip && skip->done) return;
+  for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    T yl = mdiag[l] * x[l];
+    const int e1 = prp[l + 1];
+    for (int e = prp[l]; e < e1; ++e) yl += (T)pval[e] * x[pcol[e]];
+    y[l] = yl;
+  }
+}
+
+template <typename T>
+void launch_spai_sparse_mv(int n, const T* x, T* y, const int32_t* prp, const int32_t* pcol,
+                           const float* pval, const T* mdiag, const DevState* skip_if_done,
+                           hipStream_t s) {
+  k_spai_sparse_mv<T><<<stream_grid(n), kBlock, 0, s>>>(n, x, y, prp, pcol, pval, mdiag,
+                                                        skip_if_done);
+  HIP_LAUNCH_CHECK();
+}
+template void launch_spai_sparse_mv<double>(int, const double*, double*, const int32_t*,
+                                            const int32_t*, const float*, const double*,
+                                            const DevState*, hipStream_t);
+template void launch_spai_sparse_mv<float>(int, const float*, float*, const int32_t*,
+                                           const int32_t*, const float*, const float*,
+                                           const DevState*, hipStream_t);
 // The partials (sum(p), V-hat^T p) are reduced by the next product's finishing dispatch.
 template <typename T>
 void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv, int c,
@@ -1205,10 +1295,10 @@ void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv
 template void launch_pcg_update1_plain<double>(int, double*, double*, const double*,
                                                const double*, const double*, int64_t, int,
                                                double, int, double, int, DevState*, RedBuf,
-                                               hipStream_t);
+                                               hipStream_t, bool);
 template void launch_pcg_update1_plain<float>(int, float*, float*, const float*, const float*,
                                               const float*, int64_t, int, double, int, double,
-                                              int, DevState*, RedBuf, hipStream_t);
+                                              int, DevState*, RedBuf, hipStream_t, bool);
 template void launch_pcg_update2_learned<double>(int, const double*, double*, const double*,
                                                  int64_t, int, const double*, double, int,
                                                  DevState*, RedBuf, hipStream_t);

@@ -22,9 +22,17 @@ struct SpaiWork {
   size_t scratch_elems = 0;
   double* gpart = nullptr;   // gradient partials
   size_t gpart_elems = 0;
+  // pruned form (isira_spai_prune): the kept off-diagonal entries of M as CSR in internal
+  // order; while set, every apply of M uses it (the dropped entries of offd are 0 as well)
+  bool pruned = false;
+  int64_t pnnz = 0;
+  int32_t* prp = nullptr;   // n + 1
+  int32_t* pcol = nullptr;  // pnnz
+  float* pval = nullptr;    // pnnz
 };
 
 void free_work(SpaiWork& w);
+void free_pruned(SpaiWork& w);
 
 // y = M x with the trimmed row zeroed (x carries 0 at `trim`), followed by the dots
 // st->t2[0..c) = V-hat^T y and st->t2[c] = x^T y used by eq. (3.5) in the PCG.
@@ -36,6 +44,12 @@ void apply(SpaiWork& w, const SpmvPlan& plan, const int32_t* rp, const int32_t* 
 template <typename T>
 void apply_plain(SpaiWork& w, const SpmvPlan& plan, const int32_t* rp, const int32_t* col,
                  const T* x, T* y, int n, int trim, hipStream_t s);
+// Pruned M only (w.pruned): u = M r with the partials of one PCG step, finished by the
+// Jacobi path's dispatch (see launch_spai_sparse_step).
+template <typename T>
+void sparse_step(const SpaiWork& w, int n, const T* r, T* u, const T* V, int64_t ldv, int c,
+                 const double* Ginv, double delta, int init, DevState* st, RedBuf rb,
+                 hipStream_t s);
 
 int32_t nparam();
 int ensure(SpaiWork& w, int64_t n, int64_t nnz);

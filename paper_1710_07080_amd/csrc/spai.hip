@@ -17,6 +17,18 @@ void free_work(SpaiWork& w) {
   w.rowidx = nullptr;
   w.gpart = nullptr;
   w.scratch_elems = w.gpart_elems = 0;
+  free_pruned(w);
+}
+
+void free_pruned(SpaiWork& w) {
+  if (w.prp) (void)hipFree(w.prp);
+  if (w.pcol) (void)hipFree(w.pcol);
+  if (w.pval) (void)hipFree(w.pval);
+  w.prp = nullptr;
+  w.pcol = nullptr;
+  w.pval = nullptr;
+  w.pruned = false;
+  w.pnnz = 0;
 }
 
 template <typename T>
@@ -39,13 +51,26 @@ static SpmvArgs<T> m_args(SpaiWork& w, const int32_t* rp, const int32_t* col, co
 }
 
 template <typename T>
+static const T* mdiag(const SpaiWork& w) {
+  if constexpr (sizeof(T) == 8) {
+    return w.diag64;
+  } else {
+    return w.diag32;
+  }
+}
+
+template <typename T>
 void apply(SpaiWork& w, const SpmvPlan& plan, const int32_t* rp, const int32_t* col,
            const T* x, T* y, int n, int trim, const T* V, int64_t ldv, int c, DevState* st,
            RedBuf rb, hipStream_t s) {
-  SpmvArgs<T> a = m_args<T>(w, rp, col, x, y, n, trim);
-  a.st = st;
-  a.check_done = 1;
-  launch_spmv<T>(plan, kF32Pos, a, rb, s);
+  if (w.pruned) {
+    launch_spai_sparse_mv<T>(n, x, y, w.prp, w.pcol, w.pval, mdiag<T>(w), st, s);
+  } else {
+    SpmvArgs<T> a = m_args<T>(w, rp, col, x, y, n, trim);
+    a.st = st;
+    a.check_done = 1;
+    launch_spmv<T>(plan, kF32Pos, a, rb, s);
+  }
   // [V-hat^T y, x^T y] -> st->t2[0..c]
   launch_multidot<T>(n, V, ldv, c, x, ldv, 1, y, nullptr, 0, 0, st->t2, rb, s, st);
 }
@@ -53,10 +78,28 @@ void apply(SpaiWork& w, const SpmvPlan& plan, const int32_t* rp, const int32_t* 
 template <typename T>
 void apply_plain(SpaiWork& w, const SpmvPlan& plan, const int32_t* rp, const int32_t* col,
                  const T* x, T* y, int n, int trim, hipStream_t s) {
+  if (w.pruned) {
+    launch_spai_sparse_mv<T>(n, x, y, w.prp, w.pcol, w.pval, mdiag<T>(w), nullptr, s);
+    return;
+  }
   SpmvArgs<T> a = m_args<T>(w, rp, col, x, y, n, trim);
   RedBuf none{nullptr, nullptr};
   launch_spmv<T>(plan, kF32Pos, a, none, s);
 }
+
+template <typename T>
+void sparse_step(const SpaiWork& w, int n, const T* r, T* u, const T* V, int64_t ldv, int c,
+                 const double* Ginv, double delta, int init, DevState* st, RedBuf rb,
+                 hipStream_t s) {
+  launch_spai_sparse_step<T>(n, r, u, w.prp, w.pcol, w.pval, mdiag<T>(w), V, ldv, c, Ginv, delta,
+                             init, st, rb, s);
+}
+template void sparse_step<double>(const SpaiWork&, int, const double*, double*, const double*,
+                                  int64_t, int, const double*, double, int, DevState*, RedBuf,
+                                  hipStream_t);
+template void sparse_step<float>(const SpaiWork&, int, const float*, float*, const float*,
+                                 int64_t, int, const double*, double, int, DevState*, RedBuf,
+                                 hipStream_t);
 
 template void apply<double>(SpaiWork&, const SpmvPlan&, const int32_t*, const int32_t*,
                             const double*, double*, int, int, const double*, int64_t, int,

@@ -111,7 +111,7 @@ EXPORTS = [
     "isira_default_options", "isira_create", "isira_destroy", "isira_get_info", "isira_solve",
     "isira_laplacian_apply", "isira_laplacian_apply_f32", "isira_time_spmv", "isira_inner_solve",
     "isira_orthonormalize", "isira_symeig", "isira_symeig_lowest", "isira_spai_nparam", "isira_spai_install",
-    "isira_spai_export", "isira_spai_loss_grad", "isira_adam_step", "isira_ml_default_options",
+    "isira_spai_prune", "isira_spai_export", "isira_spai_loss_grad", "isira_adam_step", "isira_ml_default_options",
     "isira_ml_setup", "isira_ml_get_info", "isira_ml_apply", "isira_ml_shape", "isira_strerror",
     "isira_last_error",
 ]
@@ -152,6 +152,7 @@ def load() -> ctypes.CDLL:
         "isira_symeig_lowest": (i32, [i32, vp, vp, vp]),
         "isira_spai_nparam": (i32, []),
         "isira_spai_install": (i32, [vp, vp, dbl, i64]),
+        "isira_spai_prune": (i32, [vp, dbl, ctypes.POINTER(i64)]),
         "isira_spai_export": (i32, [vp, vp, vp]),
         "isira_spai_loss_grad": (i32, [vp, vp, dbl, i64, vp, vp, i32, vp, _c_double_p]),
         "isira_adam_step": (i32, [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float,
@@ -428,6 +429,13 @@ class Context:
 
         _require_cuda(params, torch.float32, spai_nparam(), "params")
         _check(self._lib.isira_spai_install(self._h, _ptr(params), float(sigma), int(trim)))
+
+    def spai_prune(self, tau: float) -> int:
+        """Prune the installed learned M (isira_spai_prune); returns the kept off-diagonal
+        count."""
+        kept = ctypes.c_int64(0)
+        _check(self._lib.isira_spai_prune(self._h, float(tau), ctypes.byref(kept)))
+        return int(kept.value)
 
     def spai_export(self):
         import torch

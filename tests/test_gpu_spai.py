@@ -170,3 +170,114 @@ def test_trained_network_gain(P):
           f"time: Jacobi {sj['ms_total']:.1f} ms, learned {sl['ms_total']:.1f} ms")
     assert np.max(np.abs(el - ej) / ej) <= 1e-9
     assert sl["inner_total"] < 0.97 * sj["inner_total"]
+
+
+# ---- pruned learned M (isira_spai_prune) ----
+
+def _trained_or_jittered():
+    import os
+
+    from paper_1710_07080_amd import spai_train
+
+    if os.path.exists(spai_train.DEFAULT_WEIGHTS):
+        return np.load(spai_train.DEFAULT_WEIGHTS).astype(np.float32)
+    return _params(5, jitter=0.1)
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("tau", [0.0, 0.02, 0.1])
+def test_prune_decisions_match_oracle(P, name, tau):
+    """The kept set is an integer decision: both sides take it in FP64 from the same FP32
+    values (the GPU's own export before pruning), so it must agree exactly."""
+    g = GRAPHS[name]()
+    ctx = P.Context.from_graph(g)
+    p = _trained_or_jittered()
+    ctx.spai_install(torch.as_tensor(p, device="cuda"), sigma=0.0)
+    diag, offd = (t.cpu().numpy() for t in ctx.spai_export())
+    kept = ctx.spai_prune(tau)
+    diag2, offd2 = (t.cpu().numpy() for t in ctx.spai_export())
+    ref = SO.prune(g, diag.astype(np.float64), offd.astype(np.float64), tau)
+    assert np.array_equal(diag2, diag)
+    assert np.array_equal(offd2.astype(np.float64), ref)
+    assert kept == int(np.count_nonzero(ref))
+    if tau == 0.0:
+        assert kept == int(np.count_nonzero(offd))
+    print(f"{name} tau {tau}: kept {kept} of {g.nnz}")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("tau", [0.02, 0.3])
+def test_pruned_inner_solve(P, prec, tau):
+    g = GRAPHS["rmat12"]()
+    ctx = P.Context.from_graph(g)
+    L = O.laplacian(g)
+    d = O.degrees(g)
+    trim = O.trim_index(d)
+    delta = O.deflation_shift(d)
+    res = O.isira(g, 4, 0.0, 1e-9, gg.start_block(g.n, 4, 3), inner_rtol=1e-8)
+    V = res.evecs
+    ctx.spai_install(torch.as_tensor(_trained_or_jittered(), device="cuda"), sigma=0.0)
+    diag, offd = (t.cpu().numpy().astype(np.float64) for t in ctx.spai_export())
+    kept = ctx.spai_prune(tau)
+    off_p = SO.prune(g, diag, offd, tau)
+    assert kept == np.count_nonzero(off_p) > 0
+    r = np.random.default_rng(6).standard_normal(g.n)
+    r -= r.mean()
+    rtol = 1e-10 if prec == 0 else 1e-4
+    z, its, rel = ctx.inner_solve(torch.as_tensor(r, device="cuda"),
+                                  torch.as_tensor(np.ascontiguousarray(V.T), device="cuda"),
+                                  rtol=rtol, max_it=5000, prec=prec, precond=P.isira.PC_LEARNED)
+    z = z.cpu().numpy()
+    assert rel <= rtol
+    # reference: the oracle's inner solve with the same pruned M (the GPU's FP32 values)
+    keep = np.array([i for i in range(g.n) if i != trim])
+    Mh = SO.dense_M(g, diag, off_p)[np.ix_(keep, keep)]
+    z_ref, its_ref, _ = O.inner_solve(L, d, r, trim, 0.0, delta, V, 1e-12, 20000,
+                                      apply_minv_hat=lambda x: Mh @ x)
+    if prec == 0:
+        assert np.linalg.norm(z - z_ref) <= 1e-7 * np.linalg.norm(z_ref)
+        _, its_10, _ = O.inner_solve(L, d, r, trim, 0.0, delta, V, rtol, 20000,
+                                     apply_minv_hat=lambda x: Mh @ x)
+        assert abs(its - its_10) <= max(3, 0.1 * its_10), (its, its_10)
+    else:
+        Lt = L @ z + delta * V @ (V.T @ z)
+        assert np.linalg.norm(Lt - r) <= 5e-3 * np.linalg.norm(r)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pruned_solve_matches_dense(P, prec):
+    g = gg.rmat(11, 8, seed=31)
+    k = 12
+    lam = np.linalg.eigvalsh(O.laplacian(g).toarray())
+    ctx = P.Context.from_graph(g)
+    ctx.spai_install(torch.as_tensor(_trained_or_jittered(), device="cuda"), sigma=0.0)
+    assert ctx.spai_prune(0.02) > 0
+    tol = 1e-9
+    ev, X, resid, st = ctx.solve(k, 0.0, tol, u0=gg.start_block(g.n, 4, 5), inner_prec=prec,
+                                 precond=P.isira.PC_LEARNED, q=16, m=32)
+    X = X.cpu().numpy()
+    Ld = O.laplacian(g).toarray()
+    assert st["n_converged"] == k
+    assert np.allclose(np.sort(ev), lam[1:k + 1], rtol=1e-9, atol=0)
+    for j in range(k):
+        assert np.linalg.norm(Ld @ X[j] - ev[j] * X[j]) <= tol
+    assert np.abs(X @ X.T - np.eye(k)).max() <= 1e-10
+
+
+def test_prune_errors_and_reinstall(P):
+    g = GRAPHS["grid3d_w"]()
+    ctx = P.Context.from_graph(g)
+    with pytest.raises(P.IsiraError) as e:
+        ctx.spai_prune(0.1)  # nothing installed
+    assert e.value.code == P.isira.ISIRA_E_PRECOND
+    p = torch.as_tensor(_params(2), device="cuda")
+    ctx.spai_install(p, sigma=0.0)
+    full = ctx.spai_export()[1].cpu().numpy()
+    for bad in [-0.1, float("nan"), float("inf")]:
+        with pytest.raises(P.IsiraError) as e:
+            ctx.spai_prune(bad)
+        assert e.value.code == P.isira.ISIRA_E_ARG
+    assert ctx.spai_prune(10.0) == 0  # nothing kept: M is its diagonal
+    assert not ctx.spai_export()[1].cpu().numpy().any()
+    ctx.spai_install(p, sigma=0.0)  # installing again restores the full matrix
+    assert np.array_equal(ctx.spai_export()[1].cpu().numpy(), full)
