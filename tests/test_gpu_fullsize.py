@@ -6,7 +6,8 @@ eigenvalues within 1e-9 relative of the oracle's, true residuals ||Lx - lambda x
 by the oracle's own sparse Laplacian on the CPU (below tol, hence below 1e-8 ||L||_1),
 orthonormality, x orthogonal to 1, and the sign convention.  The eigenpairs do not depend
 on the inner preconditioner, so the multilevel solves are checked against the same
-references; the multilevel hierarchy and one cycle are also compared with the oracle's at
+references, and so are the solves with the trained learned preconditioner pruned as in the
+benchmark; the multilevel hierarchy and one cycle are also compared with the oracle's at
 full size (its set-up takes up to a minute on the host).
 """
 import json
@@ -58,12 +59,21 @@ def _setup(P, name):
 
 
 @pytest.mark.parametrize("name,prec,pc", [("rmat20", 0, 0), ("rmat20", 1, 0), ("rmat20", 0, 2),
-                                         ("grid128w", 1, 0), ("grid128w", 0, 0), ("grid128w", 1, 2)])
+                                         ("rmat20", 1, 1), ("grid128w", 1, 0), ("grid128w", 0, 0),
+                                         ("grid128w", 1, 2), ("grid128w", 1, 1)])
 def test_fullsize_matches_oracle(P, name, prec, pc):
     gold, g, ctx, L = _setup(P, name)
     k, tol = gold["k"], gold["tol"]
     if pc == P.isira.PC_MULTILEVEL:
         ctx.ml_setup()
+    if pc == P.isira.PC_LEARNED:
+        # the trained network, pruned as in the benchmark's learned + FP32 form
+        from paper_1710_07080_amd import spai_train
+
+        if not os.path.exists(spai_train.DEFAULT_WEIGHTS):
+            pytest.skip("no trained weights")
+        ctx.spai_install(spai_train.load(), sigma=gold["sigma"])
+        assert ctx.spai_prune(0.02) > 0
     ev, X, res, st = ctx.solve(k, gold["sigma"], tol, u0=gg.start_block(g.n, 4, 1), inner_prec=prec,
                                precond=pc)
     assert st["n_converged"] == k
