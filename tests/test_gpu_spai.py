@@ -211,7 +211,7 @@ def test_prune_decisions_match_oracle(P, name, tau):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("tau", [0.02, 0.3])
+@pytest.mark.parametrize("tau", [0.0, 0.02, 0.3])  # 0: every entry kept, hub rows of ~1000
 def test_pruned_inner_solve(P, prec, tau):
     g = GRAPHS["rmat12"]()
     ctx = P.Context.from_graph(g)
