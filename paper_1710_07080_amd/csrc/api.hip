@@ -807,7 +807,7 @@ void pcg_batch(isira_ctx* c, const InnerCfg& cfg, int nc, int iters, int init) {
                                   sig_over_n, first, c->st, c->rb, s);
       ml::apply<T>(c->ml, b.r, b.y, 1, c->st, c->rb, s, /*in_place=*/true);
       launch_multidot<T>(n, b.V, c->ld, nc, b.r, c->ld, 1, b.y, nullptr, 0, 0, c->st->t2, c->rb, s,
-                         c->st);
+                         &c->st->done);
       launch_spai_finish_rho(nc, c->Ginv, cfg.delta, first, c->st, s);
       launch_pcg_update2_learned<T>(n, b.y, b.p, b.Y, c->ld, nc, b.V, cfg.delta, first, c->st,
                                     c->rb, s);
@@ -866,19 +866,29 @@ int inner_pcg(isira_ctx* c, const InnerCfg& cfg, const double* r64, double mean,
 }
 
 // Classical Gram-Schmidt twice against [U(:,0:nu) Vout(:,0:nv) 1/sqrt(n)] in place on z.
-// cgs2_queue only queues the work: ||z||^2 before the second pass goes to
-// hbuf_host[kMaxCols + nc + 1] and after it to st->red[2], both valid after the next sync.
-int cgs2_queue(isira_ctx* c, const double* U, int nu, const double* V, int nv, double* z) {
+// With `selective`, the second pass runs only when the first one kept less than 1/sqrt(2)
+// of the norm (the test of Daniel, Gragg, Kaufman and Stewart, decided on the device, so
+// nothing waits for it): otherwise the first pass is already orthogonal to working
+// precision and the second pass's dispatches return at once.
+// cgs2_queue only queues the work: ||z||^2 before the first pass goes to
+// hbuf_host[kMaxCols + nc + 1] and at the end to st->red[2], both valid after the next sync.
+int cgs2_queue(isira_ctx* c, const double* U, int nu, const double* V, int nv, double* z,
+               bool selective = false) {
   const int n = (int)c->n;
   hipStream_t s = c->stream;
   const int nc = nu + nv;
   launch_multidot<double>(n, U, c->ld, nu, V, c->ld, nv, z, nullptr, 1, 1, c->hbuf, c->rb, s);
   int rc;
   if ((rc = read_h(c, nc + 2, kMaxCols))) return rc;
-  launch_gemv_sub(n, U, c->ld, nu, V, c->ld, nv, c->hbuf, 1, z, 0, c->st, c->rb, s);
-  // the second pass overwrites hbuf only after the copy above (stream order)
-  launch_multidot<double>(n, U, c->ld, nu, V, c->ld, nv, z, nullptr, 1, 0, c->hbuf, c->rb, s);
-  launch_gemv_sub(n, U, c->ld, nu, V, c->ld, nv, c->hbuf, 1, z, 1, c->st, c->rb, s);
+  launch_gemv_sub(n, U, c->ld, nu, V, c->ld, nv, c->hbuf, 1, z, selective ? 1 : 0, c->st, c->rb, s);
+  const int32_t* skip = nullptr;
+  if (selective) {
+    launch_dgks_decide(c->hbuf + nc + 1, c->st, s);
+    skip = &c->st->cgs_skip;
+  }
+  // the second pass overwrites hbuf only after the copy and the test above (stream order)
+  launch_multidot<double>(n, U, c->ld, nu, V, c->ld, nv, z, nullptr, 1, 0, c->hbuf, c->rb, s, skip);
+  launch_gemv_sub(n, U, c->ld, nu, V, c->ld, nv, c->hbuf, 1, z, 1, c->st, c->rb, s, skip);
   return ISIRA_OK;
 }
 
@@ -1068,7 +1078,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     double* u = c->U + (size_t)kk * ld;
     double* w = c->W + (size_t)kk * ld;
     for (;;) {
-      if ((r2 = cgs2_queue(c, c->U, kk, c->Vout, nconv, z))) return r2;
+      if ((r2 = cgs2_queue(c, c->U, kk, c->Vout, nconv, z, /*selective=*/true))) return r2;
       launch_scale_dev(n, z, c->st->red + 2, u, s);
       if (nconv > 0)
         launch_multidot<double>(n, c->Vout, ld, nconv, nullptr, ld, 0, u, nullptr, 0, 0, c->hbuf, c->rb, s);

@@ -88,6 +88,7 @@ struct DevState {
   // solution update still runs after the test has stopped the iteration
   double mr[10];
   int32_t last_it;
+  int32_t cgs_skip;  // 1: the second Gram-Schmidt pass is not needed (see launch_dgks_decide)
 };
 
 enum PcgStatus { kPcgOk = 0, kPcgCapped = 1, kPcgBreakdown = 2 };
@@ -220,16 +221,23 @@ template <typename T>
 void launch_enlarge(int n, const T* x, double* z, DevState* st, RedBuf rb, hipStream_t s);
 
 // Column dots h_j = sum_l A[l,j] * (w_l * z_l), j < na, then B, then (optional) sum z,
-// then (optional) z^T z.  Result into h (device).  skip_if_done: inside an inner solve,
-// both dispatches return at once once skip_if_done->done is set.
+// then (optional) z^T z.  Result into h (device).  skip: both dispatches return at once
+// when *skip is nonzero on the device (inside an inner solve: &st->done).
 template <typename T>
 void launch_multidot(int n, const T* A, int64_t lda, int na, const T* B, int64_t ldb, int nb,
                      const T* z, const T* wz, int with_sum, int with_self, double* h,
-                     RedBuf rb, hipStream_t s, const DevState* skip_if_done = nullptr);
-// z -= A hA + B hB + (with_sum ? h_sum/n : 0); optional ||z||^2 into st->red[2].
+                     RedBuf rb, hipStream_t s, const int32_t* skip = nullptr);
+// z -= A hA + B hB + (with_sum ? h_sum/n : 0); optional ||z||^2 into st->red[2].  skip as
+// for launch_multidot.
 void launch_gemv_sub(int n, const double* A, int64_t lda, int na, const double* B,
                      int64_t ldb, int nb, const double* h, int with_sum, double* z,
-                     int with_norm, DevState* st, RedBuf rb, hipStream_t s);
+                     int with_norm, DevState* st, RedBuf rb, hipStream_t s,
+                     const int32_t* skip = nullptr);
+// Second-pass test of Gram-Schmidt (Daniel, Gragg, Kaufman and Stewart, 1976): with
+// ||z||^2 before the first pass in h0sq (device) and after it in st->red[2], sets
+// st->cgs_skip = 1 when ||z_after|| >= ||z_before|| / sqrt(2), i.e. when the first pass
+// removed too little for cancellation to have spoiled orthogonality, else 0.
+void launch_dgks_decide(const double* h0sq, DevState* st, hipStream_t s);
 void launch_scale(int n, const double* z, double scale, double* u, hipStream_t s);
 void launch_scale_dev(int n, const double* z, const double* nrm2, double* u, hipStream_t s);
 void launch_pcg_reset(DevState* st, double rtol2, int maxit, hipStream_t s);

@@ -1403,8 +1403,8 @@ __global__ __launch_bounds__(kBlock) void k_multidot(int n, const T* __restrict_
                                                      int nb, const T* __restrict__ z,
                                                      const T* __restrict__ wz, int with_sum,
                                                      int with_self, double* h,
-                                                     double* partials, const DevState* skip) {
-  if (skip && skip->done) return;
+                                                     double* partials, const int32_t* skip) {
+  if (skip && *skip) return;
   __shared__ T zt[kTile];
   __shared__ double acc[kMaxCols];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1469,8 +1469,8 @@ __global__ __launch_bounds__(kBlock) void k_multidot(int n, const T* __restrict_
 
 // h[v] = sum over workgroups of partials[v * nblk + b]; one wave per value, fixed order.
 __global__ __launch_bounds__(64) void k_values_fin(int nv, int nblk, const double* partials,
-                                                   double* h, const DevState* skip = nullptr) {
-  if (skip && skip->done) return;
+                                                   double* h, const int32_t* skip = nullptr) {
+  if (skip && *skip) return;
   const int v = blockIdx.x;
   if (v >= nv) return;
   const double* pv = partials + (size_t)v * nblk;
@@ -1491,7 +1491,7 @@ __global__ __launch_bounds__(64) void k_values_fin(int nv, int nblk, const doubl
 template <typename T>
 void launch_multidot(int n, const T* A, int64_t lda, int na, const T* B, int64_t ldb, int nb,
                      const T* z, const T* wz, int with_sum, int with_self, double* h, RedBuf rb,
-                     hipStream_t s, const DevState* skip_if_done) {
+                     hipStream_t s, const int32_t* skip_if_done) {
   int grid = (n + kTile - 1) / kTile;
   if (grid > kStreamGrid) grid = kStreamGrid;
   k_multidot<T><<<grid, kBlock, 0, s>>>(n, A, lda, na, B, ldb, nb, z, wz, with_sum, with_self,
@@ -1502,10 +1502,10 @@ void launch_multidot(int n, const T* A, int64_t lda, int na, const T* B, int64_t
 }
 template void launch_multidot<double>(int, const double*, int64_t, int, const double*, int64_t,
                                       int, const double*, const double*, int, int, double*,
-                                      RedBuf, hipStream_t, const DevState*);
+                                      RedBuf, hipStream_t, const int32_t*);
 template void launch_multidot<float>(int, const float*, int64_t, int, const float*, int64_t, int,
                                      const float*, const float*, int, int, double*, RedBuf,
-                                     hipStream_t, const DevState*);
+                                     hipStream_t, const int32_t*);
 
 // z -= A hA + B hB (+ h_sum / n); optional ||z||^2 -> st->red[2].
 __global__ __launch_bounds__(kBlock) void k_gemv_sub(int n, const double* __restrict__ A,
@@ -1514,7 +1514,8 @@ __global__ __launch_bounds__(kBlock) void k_gemv_sub(int n, const double* __rest
                                                      int nb, const double* __restrict__ h,
                                                      int with_sum, double* __restrict__ z,
                                                      int with_norm, DevState* st,
-                                                     double* partials) {
+                                                     double* partials, const int32_t* skip) {
+  if (skip && *skip) return;
   __shared__ double sh[kMaxCols];
   const int ncol = na + nb;
   for (int v = threadIdx.x; v < ncol + with_sum; v += kBlock) sh[v] = h[v];
@@ -1535,10 +1536,19 @@ __global__ __launch_bounds__(kBlock) void k_gemv_sub(int n, const double* __rest
 
 void launch_gemv_sub(int n, const double* A, int64_t lda, int na, const double* B, int64_t ldb,
                      int nb, const double* h, int with_sum, double* z, int with_norm,
-                     DevState* st, RedBuf rb, hipStream_t s) {
+                     DevState* st, RedBuf rb, hipStream_t s, const int32_t* skip) {
   k_gemv_sub<<<stream_grid(n), kBlock, 0, s>>>(n, A, lda, na, B, ldb, nb, h, with_sum, z,
-                                               with_norm, st, rb.partials);
-  if (with_norm) k_values_fin<<<1, 64, 0, s>>>(1, stream_grid(n), rb.partials, st->red + 2);
+                                               with_norm, st, rb.partials, skip);
+  if (with_norm)
+    k_values_fin<<<1, 64, 0, s>>>(1, stream_grid(n), rb.partials, st->red + 2, skip);
+  HIP_LAUNCH_CHECK();
+}
+
+__global__ void k_dgks_decide(const double* h0sq, DevState* st) {
+  if (threadIdx.x == 0) st->cgs_skip = (st->red[2] >= 0.5 * h0sq[0]) ? 1 : 0;
+}
+void launch_dgks_decide(const double* h0sq, DevState* st, hipStream_t s) {
+  k_dgks_decide<<<1, 64, 0, s>>>(h0sq, st);
   HIP_LAUNCH_CHECK();
 }
 

@@ -72,7 +72,7 @@ void apply(SpaiWork& w, const SpmvPlan& plan, const int32_t* rp, const int32_t* 
     launch_spmv<T>(plan, kF32Pos, a, rb, s);
   }
   // [V-hat^T y, x^T y] -> st->t2[0..c]
-  launch_multidot<T>(n, V, ldv, c, x, ldv, 1, y, nullptr, 0, 0, st->t2, rb, s, st);
+  launch_multidot<T>(n, V, ldv, c, x, ldv, 1, y, nullptr, 0, 0, st->t2, rb, s, &st->done);
 }
 
 template <typename T>

@@ -272,6 +272,31 @@ def test_cgs2_orthogonality():
     assert before == pytest.approx(np.linalg.norm(z))
 
 
+def test_single_gram_schmidt_pass_when_little_is_removed():
+    """The second-pass test the solver applies (Daniel, Gragg, Kaufman, Stewart): when one
+    classical Gram-Schmidt pass keeps at least 1/sqrt(2) of the norm, its result is
+    orthogonal to working precision, and CGS2 changes it only at rounding level; with heavy
+    cancellation one pass is not enough.  Plain arithmetic on random data, no library
+    orthogonalization."""
+    rng = np.random.default_rng(8)
+    n, m = 5000, 60
+    Q = np.linalg.qr(rng.standard_normal((n, m)))[0]
+    worst = 0.0
+    for t in range(20):
+        z = rng.standard_normal(n) + Q @ rng.standard_normal(m) * rng.uniform(0.0, 0.8)
+        one = z - Q @ (Q.T @ z)
+        kept = np.linalg.norm(one) / np.linalg.norm(z)
+        assert kept >= 1 / np.sqrt(2)  # the case the test lets through
+        two, _, after = O.cgs2(Q, z)
+        worst = max(worst, np.abs(Q.T @ one).max() / np.linalg.norm(one))
+        assert np.linalg.norm(one - two) <= 1e-14 * after
+    assert worst <= 1e-14
+    z = rng.standard_normal(n) + Q @ rng.standard_normal(m) * 1e8  # heavy cancellation
+    one = z - Q @ (Q.T @ z)
+    assert np.linalg.norm(one) / np.linalg.norm(z) < 1 / np.sqrt(2)
+    assert np.abs(Q.T @ one).max() / np.linalg.norm(one) > 1e-12  # a second pass is needed
+
+
 def test_splitmix64_published_outputs():
     gold = json.load(open(os.path.join(GOLDEN, "splitmix64.json")))
     got = O.splitmix64(1234567, np.arange(3))
