@@ -223,10 +223,12 @@ int isira_spai_install(isira_ctx* ctx, const float* params, double sigma, int64_
  * of M (inner PCG, the Y = M V-hat columns of eq. (3.5), isira_spai_export) uses the pruned
  * matrix; the PCG step then applies it by one thread per row, fused with the dots of the
  * Jacobi form, which pays off when few entries per row are kept (tau around 0.01-0.1 for
- * the trained network).  Install again to undo.  *kept (host, may be NULL): the number of
- * stored off-diagonal entries kept.  While it runs it holds host copies of the pattern and
- * the values (about 9 bytes per stored entry, 8 more per kept one).  Errors: ISIRA_E_ARG (tau < 0 or not finite), ISIRA_E_PRECOND (no
- * learned M installed, or values found not symmetric), ISIRA_E_HIP. */
+ * the trained network).  Install again to undo (pruning a pruned M starts from the pruned
+ * values).  *kept (host, may be NULL): the number of stored off-diagonal entries kept.
+ * While it runs it holds host copies of the pattern and the values (about 9 bytes per
+ * stored entry, 8 more per kept one).  Errors: ISIRA_E_ARG (tau < 0 or not finite),
+ * ISIRA_E_PRECOND (no learned M installed, or values found not symmetric), ISIRA_E_HIP (a
+ * failed upload leaves no learned M installed). */
 int isira_spai_prune(isira_ctx* ctx, double tau, int64_t* kept);
 /* Export the installed M: diag (device n FP32, caller labels) and off-diagonal values
  * (device nnz FP32) in the caller's CSR order. */

@@ -1679,7 +1679,10 @@ extern "C" int isira_spai_prune(isira_ctx* c, double tau, int64_t* kept) {
   if (e == hipSuccess && pnnz > 0) e = hipMemcpy(c->spw.pval, pval.data(), pval.size() * 4, hipMemcpyHostToDevice);
   // the full-pattern values follow the pruning too (export, and any product on the pattern)
   if (e == hipSuccess) e = hipMemcpy(c->spw.offd, off.data(), off.size() * 4, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return undo(fail(ISIRA_E_HIP, std::string("isira_spai_prune upload: ") + hipGetErrorString(e)));
+  if (e != hipSuccess) {
+    c->has_learned = false;  // the device values may be half updated: install again
+    return undo(fail(ISIRA_E_HIP, std::string("isira_spai_prune upload: ") + hipGetErrorString(e)));
+  }
   c->spw.pruned = true;
   c->spw.pnnz = pnnz;
   if (kept) *kept = pnnz;
