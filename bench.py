@@ -439,6 +439,13 @@ def main():
                 row["max_rel_eval_diff_vs_plain"] = float(np.max(np.abs(a - b) / b))
             out[name] = row
             log(f"{name}: {row}")
+        if "fp32_learned_pruned" in out:
+            # the metric's comparison: learned preconditioner + FP32 inner solves against the
+            # plain FP64 method, same graph, start block and tolerances, same GPU
+            lp = out["fp32_learned_pruned"]
+            out["learned_fp32_vs_plain_fp64"] = {
+                "learned_fp32_s": lp["s"], "plain_fp64_s": st["ms_total"] / 1e3,
+                "speedup": lp["speedup_vs_plain_fp64"], "form": f"pruned learned M, tau {PRUNE_TAU}"}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(g, cfg, st, u0, args.inner_rtol, args.cpu_budget)
