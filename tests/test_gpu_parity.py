@@ -295,6 +295,30 @@ def test_solve_rmat14_vs_oracle(P):
     _compare(res_o, ev, X.cpu().numpy(), resid, g, 1e-9)
 
 
+@pytest.mark.parametrize("name,k", [("rmat12", 8), ("grid3d_w", 6)])
+def test_default_start_block_is_the_oracle_generator(P, name, k):
+    """Without a start block the library draws column j from the replacement generator of
+    the orthonormalization step: SplitMix64(seed) at counters j*n + (caller label), mapped
+    to [-1, 1).  The oracle's replacement_vector (pinned on the CPU to the published
+    SplitMix64 outputs) gives those columns, so a solve started from them as an explicit
+    block must be bit-identical to the solve without one, and both reach the oracle's
+    eigenvalues from that block."""
+    g = gg.rmat(12, 8, seed=3) if name == "rmat12" else GRAPHS[name]()
+    ctx = P.Context.from_graph(g)
+    seed, k0 = 987654321, 4
+    U0 = np.column_stack([O.replacement_vector(g.n, seed, j) for j in range(k0)])
+    print(f"default start block: {name} n={g.n} k={k} seed={seed}", flush=True)
+    ev_a, X_a, r_a, st_a = ctx.solve(k, 0.0, 1e-9, seed=seed, k0=k0)
+    ev_b, X_b, r_b, st_b = ctx.solve(k, 0.0, 1e-9, u0=U0, seed=seed)
+    assert st_a["n_converged"] == k and st_b["n_converged"] == k
+    assert st_a["outer_total"] == st_b["outer_total"]
+    assert st_a["inner_total"] == st_b["inner_total"]
+    assert np.array_equal(ev_a, ev_b) and np.array_equal(r_a, r_b)
+    assert torch.equal(X_a, X_b)
+    res_o = O.isira(g, k, 0.0, 1e-9, U0, inner_rtol=1e-6, seed=seed)
+    _compare(res_o, ev_a, X_a.cpu().numpy(), r_a, g, 1e-9)
+
+
 @pytest.mark.parametrize("which", ["max_degree", "min_degree", "label0"])
 def test_solve_trim_index_choices(P, which):
     """Thm 2.4: the enlarged inner solution does not depend on the trimmed vertex, so every

@@ -8,6 +8,7 @@ Laplacian built here by a loop over the edge list, and published generator outpu
 import json
 import math
 import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -302,8 +303,36 @@ def test_splitmix64_published_outputs():
     got = O.splitmix64(1234567, np.arange(3))
     assert [str(int(v)) for v in got] == gold["seed_1234567_first_three"]
     assert hex(int(O.splitmix64(0, [0])[0])) == gold["seed_0_first"]
+    seq0 = [int(h, 16) for h in gold["seed_0_first_four"]]
+    assert [int(v) for v in O.splitmix64(0, np.arange(4))] == seq0
     u = O.splitmix64_uniform(9, np.arange(100000))
     assert u.min() >= -1 and u.max() < 1 and abs(u.mean()) < 0.01
+
+
+def _uniform_from_published(z: int) -> Fraction:
+    # the replacement generator's reading: the top 53 bits of an output, as a fraction of
+    # 2^53, mapped affinely onto [-1, 1); exact rational arithmetic on the published integer
+    return Fraction(2 * (z >> 11), 1 << 53) - 1
+
+
+def test_replacement_vector_from_published_outputs():
+    """Entry l of replacement vector `draw` is output number draw*n + l of the sequence
+    started from the seed, mapped to [-1, 1): checked against the published SplitMix64
+    outputs (seed 0: four outputs; seed 1234567: three), exactly."""
+    gold = json.load(open(os.path.join(GOLDEN, "splitmix64.json")))
+    seq0 = [int(h, 16) for h in gold["seed_0_first_four"]]
+    seq1 = [int(v) for v in gold["seed_1234567_first_three"]]
+    # seed 0, n = 2: draw 0 holds outputs 0, 1 and draw 1 holds outputs 2, 3
+    for draw in (0, 1):
+        got = O.replacement_vector(2, 0, draw)
+        want = [_uniform_from_published(seq0[2 * draw + l]) for l in range(2)]
+        assert [Fraction(float(v)) for v in got] == want
+    # seed 1234567, n = 3, draw 0: outputs 0, 1, 2; n = 1: draw j is output j
+    got = O.replacement_vector(3, 1234567, 0)
+    assert [Fraction(float(v)) for v in got] == [_uniform_from_published(z) for z in seq1]
+    for draw in range(3):
+        v = O.replacement_vector(1, 1234567, draw)
+        assert Fraction(float(v[0])) == _uniform_from_published(seq1[draw])
 
 
 # ------------------------------------------------------------------------- Algorithm 3.2

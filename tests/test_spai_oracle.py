@@ -1,5 +1,6 @@
 """Pins of the SPAI network oracle: central finite differences of its hand-written
 backward pass, the SPD construction, BF16 rounding, and the Jacobi special case."""
+import math
 import pathlib
 
 import numpy as np
@@ -138,3 +139,71 @@ def test_isira_with_pruned_learned_matches_dense():
                   apply_minv_hat_factory=factory)
     ref, _ = O.smallest_positive_eigenpairs_dense(g, k)
     assert np.allclose(np.sort(res.evals), ref, rtol=1e-9, atol=0)
+
+
+def _weighted_graph(n, edges):
+    """CSRGraph from an explicit edge list (u, v, w), built by hand without the generators'
+    component and relabelling steps."""
+    rows = {i: [] for i in range(n)}
+    for u, v, w in edges:
+        rows[u].append((v, w))
+        rows[v].append((u, w))
+    rp, col, wt = [0], [], []
+    for i in range(n):
+        for v, w in sorted(rows[i]):
+            col.append(v)
+            wt.append(w)
+        rp.append(len(col))
+    return gg.CSRGraph(n, np.array(rp, np.int32), np.array(col, np.int32), np.array(wt, np.float64))
+
+
+def test_features_star_by_hand():
+    # Star, centre 0 joined to leaves 1..4 (unit weights), trimmed vertex 0, sigma = 0.5.
+    # Centre: d = n = 4, every neighbour has log d = 0, it is the trimmed vertex itself (no
+    # self loop, so not adjacent to it).  Leaf: d = n = 1, its one neighbour has log d = log 4,
+    # and it is adjacent to the trimmed vertex.
+    g = gg.star_graph(5)
+    f = SO.features(g, 0.5, 0)
+    l4 = math.log(4.0)
+    centre = [1.0, l4, l4, 0.0, 0.0, 0.125, 0.25, 0.0]
+    leaf = [1.0, 0.0, 0.0, l4, l4, 0.5, 1.0, 1.0]
+    assert f.shape == (5, SO.F)
+    assert np.allclose(f[0], centre, rtol=1e-15, atol=0)
+    for i in range(1, 5):
+        assert np.allclose(f[i], leaf, rtol=1e-15, atol=0)
+
+
+def test_features_weighted_path_by_hand():
+    # Path 0-1-2-3 with weights 2, 0.5, 3 and the trimmed vertex 1, sigma = 0.25.
+    # Weighted degrees d = (2, 2.5, 3.5, 3); neighbour counts (1, 2, 2, 1).  The columns are
+    # [1, log d_i, log n_i, mean_j log d_j, max_j log d_j, sigma/d_i, 1/n_i, adjacent to 1].
+    # Every pair of columns that a slip could confuse differs somewhere: log d vs log n
+    # (vertex 0: log 2 vs 0), mean vs max (vertex 1: (log 2 + log 3.5)/2 vs log 3.5),
+    # sigma/d vs 1/n, and the adjacency flag (vertices 0 and 2, not 1 itself or 3).
+    g = _weighted_graph(4, [(0, 1, 2.0), (1, 2, 0.5), (2, 3, 3.0)])
+    f = SO.features(g, 0.25, 1)
+    L = math.log
+    want = np.array([
+        [1.0, L(2.0), 0.0, L(2.5), L(2.5), 0.125, 1.0, 1.0],
+        [1.0, L(2.5), L(2.0), 0.5 * (L(2.0) + L(3.5)), L(3.5), 0.1, 0.5, 0.0],
+        [1.0, L(3.5), L(2.0), 0.5 * (L(2.5) + L(3.0)), L(3.0), 0.25 / 3.5, 0.5, 1.0],
+        [1.0, L(3.0), 0.0, L(3.5), L(3.5), 0.25 / 3.0, 1.0, 0.0],
+    ])
+    assert np.allclose(f, want, rtol=1e-15, atol=1e-300)
+
+
+def test_features_vertex_next_to_trimmed_hub():
+    # Two triangles sharing vertex 0 (the hub, degree 4) plus a pendant vertex 5 on vertex 3:
+    # the adjacency flag is 1 exactly for the neighbours of the trimmed vertex (1, 2, 3, 4)
+    # and the neighbour max picks the hub's log 4 for them while the mean does not.
+    g = _weighted_graph(6, [(0, 1, 1.0), (0, 2, 1.0), (1, 2, 1.0), (0, 3, 1.0), (0, 4, 1.0),
+                            (3, 4, 1.0), (3, 5, 1.0)])
+    f = SO.features(g, 0.0, 0)
+    L = math.log
+    assert f[:, 7].tolist() == [0.0, 1.0, 1.0, 1.0, 1.0, 0.0]
+    # vertex 1: neighbours 0 (d 4) and 2 (d 2)
+    assert np.allclose(f[1, 3:5], [0.5 * (L(4.0) + L(2.0)), L(4.0)], rtol=1e-15)
+    # vertex 3: neighbours 0 (d 4), 4 (d 2), 5 (d 1)
+    assert np.allclose(f[3, 1:5], [L(3.0), L(3.0), (L(4.0) + L(2.0) + 0.0) / 3.0, L(4.0)], rtol=1e-15)
+    # vertex 5: its one neighbour is 3 (d 3)
+    assert np.allclose(f[5], [1.0, 0.0, 0.0, L(3.0), L(3.0), 0.0, 1.0, 0.0], rtol=1e-15, atol=0)
