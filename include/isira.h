@@ -189,6 +189,19 @@ int isira_inner_solve(isira_ctx* ctx, const double* r, const double* V, int32_t 
 int isira_orthonormalize(isira_ctx* ctx, const double* Q, int32_t ncols, const double* z,
                          double* u, double* norms);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same orthonormalization as
+ * isira_orthonormalize -- classical Gram-Schmidt applied twice against the ncols columns of
+ * Q and 1/sqrt(n), then u = z_after / ||z_after|| (u = 0 when that norm is 0) -- that calls
+ * no hipMalloc, hipFree or allocating routine.  Q: device n-by-ncols (ld n), z: device n
+ * (read only), u: device n output (must not overlap z or Q), norms (host, 2): ||z|| before
+ * and after; all in the caller's labels.  Intermediates live in a fixed device array of the
+ * library (2 MiB, one per GPU, held until the process ends): ncols is limited to
+ * 0..ISIRA_MAX_BASIS (E_ARG beyond).  Calls that overlap on one GPU (other streams or
+ * threads) share that array and race; the call returns after its stream has finished. */
+int isira_orthonormalize_noalloc(isira_ctx* ctx, const double* Q, int32_t ncols,
+                                 const double* z, double* u, double* norms);
+
 /* Host-only: all eigenpairs of a symmetric k-by-k matrix H (column-major), eigenvalues
  * ascending in theta (k), unit eigenvectors in the columns of S (k-by-k column-major)
  * -- the Rayleigh-Ritz step of Algorithm 3.2.  Householder tridiagonalization followed

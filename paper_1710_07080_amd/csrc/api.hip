@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -81,6 +82,44 @@ void parallel_for(int64_t n, F f) {
 
 }  // namespace
 
+// ----------------------------------------------------- scratch of the allocation-free CGS2
+// Device memory of isira_orthonormalize_noalloc: the reduction partials of its column dots,
+// the column values, a saved norm and the small state.  One copy per GPU, held until the
+// process ends; every call on a GPU uses the same copy.
+constexpr int kNoAllocMaxCols = ISIRA_MAX_BASIS;
+constexpr size_t kNoAllocPartials = (size_t)(kNoAllocMaxCols + 2) * kStreamGrid;  // doubles
+constexpr size_t kNoAllocH = kNoAllocPartials;             // kMaxCols column values
+constexpr size_t kNoAllocNorm0 = kNoAllocH + kMaxCols;      // ||z||^2 before the first pass
+constexpr size_t kNoAllocState = (kNoAllocNorm0 + 1 + 31) / 32 * 32;  // DevState, 256-B aligned
+constexpr size_t kNoAllocBytes =
+    (kNoAllocState * sizeof(double) + sizeof(DevState) + 255) / 256 * 256;
+static_assert(kNoAllocBytes <= ((size_t)2 << 20), "scratch of the allocation-free CGS2 exceeds 2 MiB");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;  // per device: device address of `scratch`
+
+// Address of this GPU's copy of `scratch` (the device current on entry), looked up once per
+// device.  Host code uses only this address, never the array's name.
+int scratch_address(void** out) {
+  *out = nullptr;
+  int dev = 0;
+  CKH(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize(dev + 1, nullptr);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ISIRA_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return ISIRA_OK;
+}
+}  // namespace
+
 // ------------------------------------------------------------------------------ context
 
 struct isira_ctx {
@@ -137,6 +176,8 @@ struct isira_ctx {
   // multilevel preconditioner (hierarchy of L-hat for the trim index ml.trim)
   ml::Hierarchy ml;
   spai::SpaiWork spw;
+  // this GPU's copy of the allocation-free CGS2 scratch (looked up at creation)
+  unsigned char* scratch_dev = nullptr;
 };
 
 // Power-law test on the degree-sorted labels: at least a quarter of the gathers hit the
@@ -399,7 +440,10 @@ extern "C" int isira_create(isira_ctx** out, int64_t n, int64_t nnz, const int32
   if (rc) return rc;
   if (!connected(n, row_ptr, col)) return fail(ISIRA_E_DISCONNECTED, "graph is not connected");
 
+  void* scratch_dev = nullptr;
+  if ((rc = scratch_address(&scratch_dev))) return rc;
   isira_ctx* ctx = new isira_ctx();
+  ctx->scratch_dev = (unsigned char*)scratch_dev;
   ctx->n = n;
   ctx->nnz = nnz;
   ctx->ld = (int)((n + 63) / 64 * 64);
@@ -1493,6 +1537,44 @@ extern "C" int isira_orthonormalize(isira_ctx* c, const double* Q, int32_t ncols
   launch_scale(n, c->z64, norms[1] > 0 ? 1.0 / norms[1] : 0.0, c->tmp64, s);
   launch_gather<double, double>(n, c->tmp64, c->d_iperm, u, s);
   SYNC_OR_RETURN(c);
+  return ISIRA_OK;
+}
+
+// Allocation-free variant of isira_orthonormalize for callers that cannot allocate: the
+// vectors stay in the caller's labels (Gram-Schmidt does not depend on the order of the
+// rows), z is copied into u and orthogonalized there, and every intermediate lives in this
+// GPU's `scratch`.  Each value in scratch is written before it is read, so nothing is
+// cleared; calls that overlap on one GPU share scratch and race.
+extern "C" int isira_orthonormalize_noalloc(isira_ctx* c, const double* Q, int32_t ncols,
+                                            const double* z, double* u, double* norms) {
+  if (!c || !z || !u || !norms || (ncols > 0 && !Q)) return fail(ISIRA_E_ARG, "NULL argument");
+  if (ncols < 0 || ncols > kNoAllocMaxCols)
+    return fail(ISIRA_E_ARG, "ncols must be 0.." + std::to_string(kNoAllocMaxCols) +
+                                 " (the allocation-free scratch holds the partials of at most " +
+                                 std::to_string(kNoAllocMaxCols) + " columns)");
+  if (!c->scratch_dev) return fail(ISIRA_E_STATE, "no scratch address for this context");
+  const int n = (int)c->n;
+  hipStream_t s = c->stream;
+  double* base = (double*)c->scratch_dev;
+  RedBuf rb{base, nullptr};
+  double* h = base + kNoAllocH;
+  double* norm0 = base + kNoAllocNorm0;
+  DevState* st = (DevState*)(base + kNoAllocState);
+  CKH(hipMemcpyAsync(u, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // first pass: h = [Q 1]^T u and u^T u, then u -= Q h_Q + 1 (1^T u) / n
+  launch_multidot<double>(n, Q, n, ncols, nullptr, n, 0, u, nullptr, 1, 1, h, rb, s);
+  CKH(hipMemcpyAsync(norm0, h + ncols + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_gemv_sub(n, Q, n, ncols, nullptr, n, 0, h, 1, u, 0, st, rb, s);
+  // second pass, with ||u||^2 into st->red[2]
+  launch_multidot<double>(n, Q, n, ncols, nullptr, n, 0, u, nullptr, 1, 0, h, rb, s);
+  launch_gemv_sub(n, Q, n, ncols, nullptr, n, 0, h, 1, u, 1, st, rb, s);
+  launch_scale_dev(n, u, st->red + 2, u, s);
+  double sq[2];
+  CKH(hipMemcpyAsync(&sq[0], norm0, sizeof(double), hipMemcpyDeviceToHost, s));
+  CKH(hipMemcpyAsync(&sq[1], st->red + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  CKH(hipStreamSynchronize(s));
+  norms[0] = std::sqrt(std::max(0.0, sq[0]));
+  norms[1] = std::sqrt(std::max(0.0, sq[1]));
   return ISIRA_OK;
 }
 

@@ -1563,9 +1563,9 @@ void launch_scale(int n, const double* z, double scale, double* u, hipStream_t s
 }
 
 // u = z / sqrt(*nrm2) with the squared norm left on the device (u = 0 when it is not > 0).
-__global__ __launch_bounds__(kBlock) void k_scale_dev(int n, const double* __restrict__ z,
-                                                      const double* nrm2,
-                                                      double* __restrict__ u) {
+// (z and u may be the same vector: each entry is read before it is written, by one thread)
+__global__ __launch_bounds__(kBlock) void k_scale_dev(int n, const double* z, const double* nrm2,
+                                                      double* u) {
   const double v = *nrm2;
   const double sc = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)

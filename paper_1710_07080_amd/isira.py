@@ -110,7 +110,7 @@ class MlInfo(ctypes.Structure):
 EXPORTS = [
     "isira_default_options", "isira_create", "isira_destroy", "isira_get_info", "isira_solve",
     "isira_laplacian_apply", "isira_laplacian_apply_f32", "isira_time_spmv", "isira_inner_solve",
-    "isira_orthonormalize", "isira_symeig", "isira_symeig_lowest", "isira_spai_nparam", "isira_spai_install",
+    "isira_orthonormalize", "isira_orthonormalize_noalloc", "isira_symeig", "isira_symeig_lowest", "isira_spai_nparam", "isira_spai_install",
     "isira_spai_prune", "isira_spai_export", "isira_spai_loss_grad", "isira_adam_step", "isira_ml_default_options",
     "isira_ml_setup", "isira_ml_get_info", "isira_ml_apply", "isira_ml_shape", "isira_strerror",
     "isira_last_error",
@@ -148,6 +148,7 @@ def load() -> ctypes.CDLL:
         "isira_inner_solve": (i32, [vp, vp, vp, i32, dbl, dbl, i64, dbl, i32, i32, i32, i32, vp,
                                     _c_int32_p, _c_double_p]),
         "isira_orthonormalize": (i32, [vp, vp, i32, vp, vp, _c_double_p]),
+        "isira_orthonormalize_noalloc": (i32, [vp, vp, i32, vp, vp, _c_double_p]),
         "isira_symeig": (i32, [i32, vp, vp, vp]),
         "isira_symeig_lowest": (i32, [i32, vp, vp, vp]),
         "isira_spai_nparam": (i32, []),
@@ -391,6 +392,20 @@ class Context:
         _check(self._lib.isira_orthonormalize(self._h, _ptr(Q) if nc else None, nc, _ptr(z), _ptr(u),
                                               norms.ctypes.data_as(_c_double_p)))
         return u, norms
+
+    def orthonormalize_noalloc(self, Q, z, u):
+        """The same CGS2 through the allocation-free entry point, into the caller's u."""
+        import torch
+
+        _require_cuda(z, torch.float64, self.n, "z")
+        _require_cuda(u, torch.float64, self.n, "u")
+        nc = 0 if Q is None else Q.shape[0]
+        if nc:
+            _require_cuda(Q, torch.float64, nc * self.n, "Q")
+        norms = np.zeros(2)
+        _check(self._lib.isira_orthonormalize_noalloc(self._h, _ptr(Q) if nc else None, nc, _ptr(z),
+                                                      _ptr(u), norms.ctypes.data_as(_c_double_p)))
+        return norms
 
     # ---- multilevel preconditioner ----
     def ml_setup(self, omega: Optional[float] = None, coarse_max: Optional[int] = None,
