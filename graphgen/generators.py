@@ -34,9 +34,15 @@ class CSRGraph:
         return np.diff(self.row_ptr.astype(np.int64))
 
 
-def _csr_from_undirected(n, u, v, w=None, *, lcc=True, relabel_seed=None, name="", meta=None):
+def _csr_from_undirected(n, u, v, w=None, *, lcc=True, relabel_seed=None, name="", meta=None,
+                         device=None):
     """Symmetrize, drop self loops and duplicates, keep the largest component,
-    optionally apply a seeded random relabelling, and return sorted CSR."""
+    optionally apply a seeded random relabelling, and return sorted CSR.
+    ``device`` (a torch device name) runs the same steps with torch sorts on that device
+    (large graphs); the CSR it returns is identical."""
+    if device is not None:
+        return _csr_from_undirected_torch(n, u, v, w, lcc=lcc, relabel_seed=relabel_seed, name=name,
+                                          meta=meta, device=device)
     u = np.asarray(u, dtype=np.int64)
     v = np.asarray(v, dtype=np.int64)
     keep = u != v
@@ -76,6 +82,74 @@ def _csr_from_undirected(n, u, v, w=None, *, lcc=True, relabel_seed=None, name="
     col = mat.indices.astype(np.int32)
     wout = None if w is None else mat.data.astype(np.float64)
     g = CSRGraph(int(n), row_ptr, col, wout, name=name, meta=dict(meta or {}))
+    g.meta.update(n=int(n), nnz=g.nnz)
+    return g
+
+
+def _csr_from_undirected_torch(n, u, v, w, *, lcc, relabel_seed, name, meta, device):
+    """The steps of _csr_from_undirected with torch on ``device``: the same edge set (the
+    first occurrence of each undirected edge keeps its weight), the largest component by
+    minimum-label propagation (ties: the component with the smallest vertex, as the scipy
+    labelling gives), the same seeded permutation, and rows and columns sorted."""
+    import torch
+
+    dev = torch.device(device)
+    u = torch.as_tensor(np.asarray(u, dtype=np.int64), device=dev)
+    v = torch.as_tensor(np.asarray(v, dtype=np.int64), device=dev)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    wt = None
+    if w is not None:
+        wt = torch.as_tensor(np.asarray(w, dtype=np.float64), device=dev)[keep]
+    del keep
+    a = torch.minimum(u, v)
+    b = torch.maximum(u, v)
+    del u, v
+    key, order = torch.sort(a * n + b, stable=True)
+    first = torch.ones_like(key, dtype=torch.bool)
+    first[1:] = key[1:] != key[:-1]
+    del key
+    pick = order[first]  # first occurrence of each edge, in increasing key order
+    del order, first
+    a, b = a[pick], b[pick]
+    if wt is not None:
+        wt = wt[pick]
+    del pick
+    if lcc:
+        rows = torch.cat([a, b])
+        cols = torch.cat([b, a])
+        lab = torch.arange(n, device=dev, dtype=torch.int64)
+        while True:
+            nl = lab.clone()
+            nl.scatter_reduce_(0, rows, lab[cols], reduce="amin", include_self=True)
+            nl = nl[nl]
+            if torch.equal(nl, lab):
+                break
+            lab = nl
+        del rows, cols
+        big = int(torch.argmax(torch.bincount(lab, minlength=n)))
+        inlcc = lab == big
+        if not bool(inlcc.all()):
+            rank = torch.cumsum(inlcc.to(torch.int64), 0) - 1
+            sel = inlcc[a]
+            a, b = rank[a[sel]], rank[b[sel]]
+            if wt is not None:
+                wt = wt[sel]
+            n = int(inlcc.sum())
+    if relabel_seed is not None:
+        perm = torch.as_tensor(np.random.default_rng(relabel_seed).permutation(n), device=dev)
+        a, b = perm[a], perm[b]
+    rows = torch.cat([a, b])
+    cols = torch.cat([b, a])
+    del a, b
+    _, order = torch.sort(rows * n + cols)
+    col = cols[order].to(torch.int32).cpu().numpy()
+    counts = torch.bincount(rows, minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    row_ptr[1:] = torch.cumsum(counts, 0).cpu().numpy()
+    wout = None if wt is None else torch.cat([wt, wt])[order].cpu().numpy()
+    del rows, cols, order
+    g = CSRGraph(int(n), row_ptr.astype(np.int32), col, wout, name=name, meta=dict(meta or {}))
     g.meta.update(n=int(n), nnz=g.nnz)
     return g
 
@@ -182,10 +256,10 @@ def random_connected(n: int, extra: int, seed: int, weights: Optional[tuple] = N
 
 
 def rmat(scale: int, edge_factor: int, seed: int, probs=(0.57, 0.19, 0.19, 0.05),
-         relabel: bool = True) -> CSRGraph:
+         relabel: bool = True, device=None) -> CSRGraph:
     """R-MAT graph: edge_factor * 2**scale edge samples, no per-level noise, then
     symmetrized, deduplicated, self loops removed, largest connected component,
-    and a seeded random relabelling."""
+    and a seeded random relabelling.  ``device``: see _csr_from_undirected."""
     a, b, c, _ = probs
     rng = np.random.default_rng(seed)
     n = 1 << scale
@@ -193,29 +267,40 @@ def rmat(scale: int, edge_factor: int, seed: int, probs=(0.57, 0.19, 0.19, 0.05)
     u = np.zeros(m, dtype=np.int64)
     v = np.zeros(m, dtype=np.int64)
     chunk = 1 << 22
+    xp = np
+    if device is not None:  # the same draws, with the bit arithmetic on the device
+        import torch as xp
     for lo in range(0, m, chunk):
         hi = min(m, lo + chunk)
-        uu = np.zeros(hi - lo, dtype=np.int64)
-        vv = np.zeros(hi - lo, dtype=np.int64)
+        uu = xp.zeros(hi - lo, dtype=xp.int64)
+        vv = xp.zeros(hi - lo, dtype=xp.int64)
+        if device is not None:
+            uu, vv = uu.to(device), vv.to(device)
         for _ in range(scale):
             r = rng.random(hi - lo)
+            if device is not None:
+                r = xp.as_tensor(r, device=device)
             ubit = r >= a + b
             vbit = ((r >= a) & (r < a + b)) | (r >= a + b + c)
             uu = (uu << 1) | ubit
             vv = (vv << 1) | vbit
+        if device is not None:
+            uu, vv = uu.cpu().numpy(), vv.cpu().numpy()
         u[lo:hi] = uu
         v[lo:hi] = vv
     return _csr_from_undirected(
         n, u, v, lcc=True, relabel_seed=seed + 7919 if relabel else None,
         name=f"rmat{scale}_ef{edge_factor}_s{seed}",
-        meta=dict(scale=scale, edge_factor=edge_factor, seed=seed, probs=list(probs)),
+        meta=dict(scale=scale, edge_factor=edge_factor, seed=seed, probs=list(probs)), device=device,
     )
 
 
-def chung_lu(n: int, beta: float, avg_deg: float, seed: int, pairs_per_vertex: int = 12) -> CSRGraph:
+def chung_lu(n: int, beta: float, avg_deg: float, seed: int, pairs_per_vertex: int = 12,
+             device=None) -> CSRGraph:
     """Chung-Lu graph: expected-degree weights w_i ~ (i+1)^(-1/(beta-1)) scaled to mean
     avg_deg and capped at sqrt(sum w); pairs_per_vertex*n endpoint pairs drawn
-    proportionally to w; then the largest component and a seeded relabelling."""
+    proportionally to w; then the largest component and a seeded relabelling.
+    ``device``: see _csr_from_undirected (the endpoint search runs there too)."""
     rng = np.random.default_rng(seed)
     i = np.arange(n, dtype=np.float64)
     wt = (i + 1.0) ** (-1.0 / (beta - 1.0))
@@ -224,12 +309,19 @@ def chung_lu(n: int, beta: float, avg_deg: float, seed: int, pairs_per_vertex: i
     cdf = np.cumsum(wt)
     cdf /= cdf[-1]
     m = pairs_per_vertex * n
-    u = np.searchsorted(cdf, rng.random(m), side="right")
-    v = np.searchsorted(cdf, rng.random(m), side="right")
+    if device is None:
+        u = np.searchsorted(cdf, rng.random(m), side="right")
+        v = np.searchsorted(cdf, rng.random(m), side="right")
+    else:
+        import torch
+
+        cdf_t = torch.as_tensor(cdf, device=device)
+        u = torch.searchsorted(cdf_t, torch.as_tensor(rng.random(m), device=device), right=True).cpu().numpy()
+        v = torch.searchsorted(cdf_t, torch.as_tensor(rng.random(m), device=device), right=True).cpu().numpy()
     return _csr_from_undirected(
         n, np.minimum(u, n - 1), np.minimum(v, n - 1), lcc=True, relabel_seed=seed + 7919,
         name=f"chunglu{n}_b{beta}_d{avg_deg}_s{seed}",
-        meta=dict(beta=beta, avg_deg=avg_deg, seed=seed),
+        meta=dict(beta=beta, avg_deg=avg_deg, seed=seed), device=device,
     )
 
 

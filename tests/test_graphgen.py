@@ -43,3 +43,32 @@ def test_seeded_and_deterministic():
     assert g.col[0] == 1 and g.w[0] == first
     U = gg.start_block(50, 3, 1)
     assert U.shape == (50, 3) and U.flags.f_contiguous
+
+
+def _dup_weighted(device=None):
+    # repeated undirected edges with different weights (the first occurrence keeps its
+    # weight), self loops, and three components: the largest is not the one of vertex 0
+    rng = np.random.default_rng(21)
+    u = np.concatenate([[0, 1, 0], 3 + rng.integers(0, 200, 900), 250 + rng.integers(0, 40, 60)])
+    v = np.concatenate([[1, 0, 0], 3 + rng.integers(0, 200, 900), 250 + rng.integers(0, 40, 60)])
+    w = rng.uniform(0.5, 1.5, u.size)
+    return gg.generators._csr_from_undirected(300, u, v, w, lcc=True, relabel_seed=5, device=device)
+
+
+@pytest.mark.parametrize("make", [
+    lambda d: gg.rmat(12, 8, seed=5, device=d), lambda d: gg.rmat(11, 16, seed=4000, device=d),
+    lambda d: gg.chung_lu(20000, 2.1, 24.0, seed=6, device=d), _dup_weighted,
+    lambda d: gg.generators._csr_from_undirected(50, np.arange(49), np.arange(1, 50), lcc=False,
+                                                 device=d),
+])
+def test_torch_path_gives_the_same_csr(make):
+    """The torch-sorted path (used on the GPU for the large workloads) returns exactly the
+    CSR of the numpy/scipy path: same vertex count, pattern, order and weights."""
+    a = make(None)
+    b = make("cpu")
+    assert a.n == b.n and a.nnz == b.nnz
+    assert np.array_equal(a.row_ptr, b.row_ptr) and b.row_ptr.dtype == np.int32
+    assert np.array_equal(a.col, b.col) and b.col.dtype == np.int32
+    assert (a.w is None) == (b.w is None)
+    if a.w is not None:
+        assert np.array_equal(a.w, b.w)
