@@ -41,10 +41,10 @@ def workload(name):
         return gg.grid2d(64, 64), dict(k=10, sigma=0.0, tol=1e-10)
     if name == "grid128w":
         return gg.grid3d(128, 128, 128, weights=(0.5, 1.5), seed=3), dict(k=20, sigma=0.0, tol=1e-8)
-    if name == "chunglu24":  # n = 2^24, beta 2.1, mean degree 24 (generation takes minutes)
-        return gg.chung_lu(1 << 24, 2.1, 24.0, seed=5), dict(k=50, sigma=0.0, tol=1e-8)
+    if name == "chunglu24":  # n = 2^24, beta 2.1, mean degree 24 (sorted on the GPU)
+        return gg.chung_lu(1 << 24, 2.1, 24.0, seed=5, device="cuda"), dict(k=50, sigma=0.0, tol=1e-8)
     if name == "rmat22e16":  # held-out graph of the learned preconditioner: scale 22, mean degree 32
-        return gg.rmat(22, 16, seed=4000), dict(k=20, sigma=0.0, tol=1e-8)
+        return gg.rmat(22, 16, seed=4000, device="cuda"), dict(k=20, sigma=0.0, tol=1e-8)
     if name.startswith("rmat"):
         s = int(name[4:])
         return gg.rmat(s, 8, seed=2), dict(k=20, sigma=0.0, tol=1e-8)

@@ -41,6 +41,7 @@ extern "C" {
 #define ISIRA_E_HIP (-4)        /* a HIP runtime call failed (allocation, launch, copy) */
 #define ISIRA_E_PRECOND (-5)    /* the learned preconditioner is missing or not usable */
 #define ISIRA_E_STATE (-6)      /* entry point called in the wrong state */
+#define ISIRA_E_WORKSPACE (-7)  /* the caller's workspace is too small for this call */
 
 /* ---- weight dtypes ---- */
 #define ISIRA_W_NONE 0 /* unit weights (plain adjacency A) */
@@ -113,6 +114,9 @@ typedef struct {
   int32_t restarts, breakdowns, refreshes, inner_fallbacks, inner_capped;
   int32_t outer_per_pair[ISIRA_STATS_MAX];
   int32_t inner_per_pair[ISIRA_STATS_MAX];
+  /* wall time (ms) of the whole solve and of its phases: inner solves (with the first batch
+     of each, queued behind the Ritz residual), orthonormalization and expansion, host
+     Rayleigh-Ritz, the Ritz residual kernels (HIP events), restarts and purges */
   double ms_total, ms_inner, ms_ortho, ms_rr_host, ms_residual, ms_restart;
   int64_t trim_index;                  /* caller label of the trimmed vertex */
   double delta;
@@ -142,6 +146,36 @@ int isira_create(isira_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
                  const int32_t* col, const void* w, int32_t w_dtype, void* stream,
                  int32_t validate);
 
+/* ---- caller-owned device memory (the boundary's workspace form) ----
+ * isira_workspace_bytes: an upper bound of the device bytes one context needs for a graph of
+ * n vertices and nnz stored off-diagonal entries (weights of dtype w_dtype) to run
+ * isira_create_ws and then isira_solve for up to k pairs with the options opt (NULL: the
+ * defaults; m and k size the basis U, W of Algorithm 3.2 and the deflation blocks).  flags:
+ * ISIRA_WS_LEARNED adds the learned preconditioner's buffers (isira_spai_install and
+ * isira_spai_prune).  The multilevel hierarchy (isira_ml_setup) and the training entry points
+ * need more, which their sizes decide; on a workspace context they take it from the
+ * workspace and fail with ISIRA_E_WORKSPACE when it is short.  Returns 0 for invalid sizes. */
+#define ISIRA_WS_LEARNED 1
+size_t isira_workspace_bytes(int64_t n, int64_t nnz, int32_t w_dtype, int32_t k,
+                             const isira_options* opt, int32_t flags);
+/* isira_create with caller-owned device memory: every device buffer of the context (the
+ * relabelled CSR, degrees, the SpMV plan, reduction buffers, and the solve workspace for k
+ * pairs with options opt, sized here at creation) is carved from `workspace` (device,
+ * ws_bytes bytes, owned by the caller and kept alive until isira_destroy); the library makes
+ * no device allocation.  csr_on_device: 0 = row_ptr/col/w are host arrays as for
+ * isira_create, 1 = they are device arrays (read once into a host copy for validation and
+ * relabelling).  Pinned host buffers (a few KB plus a 1 MiB upload ring) are still the
+ * library's.  Errors as isira_create, plus ISIRA_E_WORKSPACE when ws_bytes is short (take
+ * isira_workspace_bytes).  A later solve with a larger k or m than sized here, or any call
+ * that needs more device memory, fails with ISIRA_E_WORKSPACE instead of allocating. */
+int isira_create_ws(isira_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                    const int32_t* col, const void* w, int32_t w_dtype, int32_t csr_on_device,
+                    void* workspace, size_t ws_bytes, int32_t k, const isira_options* opt,
+                    void* stream, int32_t validate);
+/* Device bytes of the context now in use and at most (both contexts), and the workspace's
+ * usable size (0 for a context that allocates its own memory); any pointer may be NULL. */
+int isira_memory_info(const isira_ctx* ctx, size_t* in_use, size_t* peak, size_t* capacity);
+
 void isira_destroy(isira_ctx* ctx);
 int isira_get_info(const isira_ctx* ctx, isira_info* info);
 
@@ -163,12 +197,15 @@ int isira_solve(isira_ctx* ctx, int32_t k, double sigma, double tol, const isira
 int isira_laplacian_apply(isira_ctx* ctx, const double* x, double* y);
 /* y = L x with FP32 vectors and FP32 weights (the inner-solve operator precision). */
 int isira_laplacian_apply_f32(isira_ctx* ctx, const float* x, float* y);
-/* Time `reps` back-to-back launches of the main dispatch of the FP64 (prec 0) or FP32
- * (prec 1) Laplacian product (kernel symbol k_spmv<..., TAG = 1, ...>) on internal vectors,
- * with HIP events on the context stream; *ms_per = average ms per launch.  The finishing
- * dispatch of rows split into chunks (a few of the longest rows) is left out, so the
- * probe's output is not a complete product and is not used. */
-int isira_time_spmv(isira_ctx* ctx, int32_t prec, int32_t reps, double* ms_per);
+/* Time `reps` launches of the main dispatch of the FP64 (prec 0) or FP32 (prec 1) Laplacian
+ * product (kernel symbol k_spmv<..., TAG = 1, ...>) on internal vectors, with HIP events on
+ * the context stream; *ms_per = average ms per launch.  cold = 0: back-to-back launches
+ * (the graph may stay in the 256 MB memory-side cache between them); cold = 1: before each
+ * launch a 512 MiB device buffer (taken from the context's memory and released afterwards)
+ * is read and written, and each launch is timed on its own, so every launch starts from
+ * HBM.  The finishing dispatch of rows split into chunks (a few of the longest rows) is left
+ * out, so the probe's output is not a complete product and is not used. */
+int isira_time_spmv(isira_ctx* ctx, int32_t prec, int32_t reps, int32_t cold, double* ms_per);
 
 /* One inner solve of Algorithm 3.2's expansion step: solve the trimmed, shifted,
  * deflated system (2.15) for r_hat = r with entry `trim` deleted, by PCG with the

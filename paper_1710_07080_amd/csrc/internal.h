@@ -3,12 +3,55 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "isira.h"
 
 namespace isira {
+
+// Device memory of one context.  By default each block is its own hipMalloc; once a
+// caller's workspace is attached (isira_create_ws) every block is carved from that one range
+// instead (first fit, 256-byte aligned, freed blocks merged with their neighbours), and the
+// library makes no device allocation of its own.
+class DevMem {
+ public:
+  static constexpr size_t kAlign = 256;
+  void attach(void* base, size_t bytes);
+  bool external() const { return base_ != nullptr; }
+  // ISIRA_OK; ISIRA_E_WORKSPACE when the attached workspace has no free range that large;
+  // ISIRA_E_HIP when hipMalloc fails.  *p is nullptr on failure.
+  int alloc(void** p, size_t bytes);
+  void release(void* p);
+  size_t in_use() const { return in_use_; }
+  size_t peak() const { return peak_; }
+  size_t capacity() const { return cap_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t cap_ = 0;
+  std::map<size_t, size_t> free_;           // offset -> bytes of the free ranges
+  std::unordered_map<void*, size_t> live_;  // block -> bytes
+  size_t in_use_ = 0, peak_ = 0;
+};
+
+// Typed helpers: count elements of T (at least one); the error text goes to the thread's
+// last-error message.
+int dev_alloc_bytes(DevMem& m, void** p, size_t bytes);
+template <typename T>
+int dalloc(DevMem& m, T** p, size_t count) {
+  return dev_alloc_bytes(m, (void**)p, (count == 0 ? 1 : count) * sizeof(T));
+}
+template <typename T>
+void dfree(DevMem& m, T*& p) {
+  if (p) m.release((void*)p);
+  p = nullptr;
+}
+inline size_t dev_round(size_t bytes) {
+  return ((bytes == 0 ? 1 : bytes) + DevMem::kAlign - 1) / DevMem::kAlign * DevMem::kAlign;
+}
 
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 #ifndef ISIRA_STREAM_GRID
@@ -116,9 +159,11 @@ struct SpmvPlan {
 };
 
 // Work units of the sparse product for a CSR matrix of n rows (host arrays); the plan's
-// device arrays are allocated here and released by free_spmv_plan.
-int build_spmv_plan(int n, const int32_t* rp, const int32_t* col, SpmvPlan& P);
-void free_spmv_plan(SpmvPlan& P);
+// device arrays are allocated from mem here and released by free_spmv_plan.
+int build_spmv_plan(DevMem& mem, int n, const int32_t* rp, const int32_t* col, SpmvPlan& P);
+void free_spmv_plan(DevMem& mem, SpmvPlan& P);
+// Upper bound of the bytes build_spmv_plan allocates for a matrix of n rows and nnz entries.
+size_t spmv_plan_bytes_bound(int64_t n, int64_t nnz);
 
 // Value mode of the sparse product y = diag .* x + sgn * sum_j v_ij x_j.
 enum ValMode { kUnitNeg = 0, kF32Neg = 1, kF64Neg = 2, kF32Pos = 3, kF64Pos = 4 };

@@ -1552,8 +1552,8 @@ void launch_dgks_decide(const double* h0sq, DevState* st, hipStream_t s) {
   HIP_LAUNCH_CHECK();
 }
 
-__global__ __launch_bounds__(kBlock) void k_scale(int n, const double* __restrict__ z,
-                                                  double scale, double* __restrict__ u) {
+// (z and u may be the same vector)
+__global__ __launch_bounds__(kBlock) void k_scale(int n, const double* z, double scale, double* u) {
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock)
     u[l] = z[l] * scale;
 }
@@ -1637,6 +1637,7 @@ void launch_ritz_vector(int n, const double* U, int64_t ld, int k, const double*
 // LDS read feeds eight FMAs.  All reads of a tile precede its writes, so the update is in place.
 constexpr int kTsRows = 64;
 constexpr int kTsCw = 8;
+constexpr size_t kTsMfmaLds = 128 * 1024;  // LDS bytes of the matrix-core form's copy of S
 __global__ __launch_bounds__(kBlock) void k_tsgemm_inplace(int n, double* __restrict__ U,
                                                            int64_t ld, int k,
                                                            const double* __restrict__ St,
@@ -1693,8 +1694,115 @@ __global__ __launch_bounds__(kBlock) void k_tsgemm_inplace(int n, double* __rest
     }
   }
 }
+// The same product on the FP64 matrix cores.  S, zero-padded to kp = k rounded up to 4 rows
+// and QP = NT * 16 columns, is staged once per workgroup in LDS.  A wave owns 16 rows of U
+// and every output column: with the transposed product (U S)^T = S^T U^T, one
+// v_mfma_f64_16x16x4 takes A = a 16 x 4 block of S^T from LDS (lane l: S(i0 + l/16,
+// 16u + l%16)) and B = a 4 x 16 block of U^T (lane l: U(16t + l%16, i0 + l/16): four 128-byte
+// row segments), and adds into the 16 x 16 block u of (U S)^T, whose lane l holds entries
+// (16u + 4j + l/16, 16t + l%16), j = 0..3 -- so every store writes whole 128-byte segments.
+// The B blocks of the next four k-steps are loaded while the current four are multiplied.
+// A wave reads its 16 rows
+// of all k columns before it writes any of them and no other wave touches those rows, so
+// the update is in place.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+template <int NT, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_tsgemm_mfma(int n, double* U, int64_t ld, int k,
+                                                         const double* __restrict__ St, int q) {
+  extern __shared__ double sS[];
+  constexpr int QP = NT * 16;
+  const int kp = (k + 3) & ~3;
+  for (int e = threadIdx.x; e < kp * QP; e += THREADS) {
+    const int i = e / QP, j = e - i * QP;
+    sS[e] = (i < k && j < q) ? St[(int64_t)i * q + j] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, c = lane & 15;
+  constexpr int WPB = THREADS / 64;
+  const int ntiles = (n + 15) >> 4;
+  for (int t = blockIdx.x * WPB + (threadIdx.x >> 6); t < ntiles; t += gridDim.x * WPB) {
+    const int row = t * 16 + c;
+    const bool rok = row < n;
+    const double* ur = U + row;
+    dbl4 acc[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // B blocks of four k-steps (16 columns of U) are loaded together, one group ahead
+    double bc[4], bn[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int i = 4 * st + g;
+      bc[st] = (rok && i < k) ? ur[(int64_t)i * ld] : 0.0;
+    }
+    for (int i0 = 0; i0 < kp; i0 += 16) {
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int i = i0 + 16 + 4 * st + g;
+        bn[st] = (rok && i < k) ? ur[(int64_t)i * ld] : 0.0;
+      }
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        if (i0 + 4 * st < kp) {
+          const double* srow = sS + (i0 + 4 * st + g) * QP + c;
+#pragma unroll
+          for (int u = 0; u < NT; ++u)
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(srow[u * 16], bc[st], acc[u], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int st = 0; st < 4; ++st) bc[st] = bn[st];
+    }
+    if (rok) {
+#pragma unroll
+      for (int u = 0; u < NT; ++u)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = u * 16 + 4 * j + g;
+          if (col < q) U[row + (int64_t)col * ld] = acc[u][j];
+        }
+    }
+  }
+}
+
+template <int NT>
+static void launch_tsgemm_mfma_nt(int n, double* U, int64_t ld, int k, const double* St, int q,
+                                  size_t lds, hipStream_t s) {
+  constexpr int TH = NT <= 4 ? 1024 : 512;  // 16 NT registers per lane: accumulators and S
+  static bool lds_raised = false;
+  if (!lds_raised) {
+    (void)hipFuncSetAttribute((const void*)k_tsgemm_mfma<NT, TH>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTsMfmaLds);
+    lds_raised = true;
+  }
+  int grid = (((n + 15) >> 4) + (TH / 64) - 1) / (TH / 64);
+  if (grid > 1024) grid = 1024;
+  k_tsgemm_mfma<NT, TH><<<grid, TH, lds, s>>>(n, U, ld, k, St, q);
+}
+
 void launch_tsgemm_inplace(int n, double* U, int64_t ld, int k, const double* St, int q,
                            hipStream_t s) {
+  const int nt = (q + 15) / 16;
+  const size_t lds = (size_t)((k + 3) & ~3) * nt * 16 * sizeof(double);
+  if (lds <= kTsMfmaLds) {
+    switch (nt) {
+      case 1: launch_tsgemm_mfma_nt<1>(n, U, ld, k, St, q, lds, s); break;
+      case 2: launch_tsgemm_mfma_nt<2>(n, U, ld, k, St, q, lds, s); break;
+      case 3: launch_tsgemm_mfma_nt<3>(n, U, ld, k, St, q, lds, s); break;
+      case 4: launch_tsgemm_mfma_nt<4>(n, U, ld, k, St, q, lds, s); break;
+      case 5: launch_tsgemm_mfma_nt<5>(n, U, ld, k, St, q, lds, s); break;
+      case 6: launch_tsgemm_mfma_nt<6>(n, U, ld, k, St, q, lds, s); break;
+      case 7: launch_tsgemm_mfma_nt<7>(n, U, ld, k, St, q, lds, s); break;
+      case 8: launch_tsgemm_mfma_nt<8>(n, U, ld, k, St, q, lds, s); break;
+      case 9: launch_tsgemm_mfma_nt<9>(n, U, ld, k, St, q, lds, s); break;
+      case 10: launch_tsgemm_mfma_nt<10>(n, U, ld, k, St, q, lds, s); break;
+      case 11: launch_tsgemm_mfma_nt<11>(n, U, ld, k, St, q, lds, s); break;
+      default: launch_tsgemm_mfma_nt<12>(n, U, ld, k, St, q, lds, s); break;
+    }
+    HIP_LAUNCH_CHECK();
+    return;
+  }
+  // S too large for the LDS of one workgroup (k and q both near ISIRA_MAX_BASIS)
   int grid = (n + kTsRows - 1) / kTsRows;
   if (grid > 2048) grid = 2048;
   static bool lds_raised = false;  // k <= 192 needs up to 96 KB of dynamic LDS

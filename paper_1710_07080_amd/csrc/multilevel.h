@@ -27,6 +27,7 @@ struct Level {
 };
 
 struct Hierarchy {
+  DevMem* mem = nullptr;  // the context's device memory (set at context creation)
   bool ready = false;
   int trim = -1;  // internal index of the trimmed vertex
   double omega = 0.0;

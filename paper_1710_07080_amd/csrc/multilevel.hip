@@ -39,15 +39,10 @@ int err(int code, const std::string& m) { return set_error(code, m.c_str()); }
   } while (0)
 
 template <typename T>
-int dal(T** p, size_t count, int64_t& bytes) {
-  *p = nullptr;
-  if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-  if (e != hipSuccess)
-    return err(ISIRA_E_HIP, std::string("hipMalloc(") + std::to_string(count * sizeof(T)) +
-                                " bytes): " + hipGetErrorString(e));
-  bytes += (int64_t)(count * sizeof(T));
-  return ISIRA_OK;
+int dal(DevMem& m, T** p, size_t count, int64_t& bytes) {
+  const int rc = dalloc(m, p, count);
+  if (rc == ISIRA_OK) bytes += (int64_t)dev_round((count == 0 ? 1 : count) * sizeof(T));
+  return rc;
 }
 
 template <typename T>
@@ -57,9 +52,8 @@ int put(T* d, const std::vector<T>& h) {
 }
 
 template <typename T>
-void dfr(T*& p) {
-  if (p) (void)hipFree((void*)p);
-  p = nullptr;
+void dfr(DevMem& m, T*& p) {
+  dfree(m, p);
 }
 
 // One level on the host: A_ij = -w for the stored off-diagonal entries, A_ii = diag.
@@ -422,12 +416,12 @@ int upload_level(Level& L, int n, int nc, const HostMats& M, Hierarchy& H) {
   L.ld = M.ld;
   int64_t& by = H.device_bytes;
   int rc;
-  if ((rc = dal(&L.down_rp, M.drp.size(), by)) || (rc = dal(&L.down_col, M.dcol.size(), by)) ||
-      (rc = dal(&L.down_v64, M.dval.size(), by)) || (rc = dal(&L.down_v32, M.dval.size(), by)) ||
-      (rc = dal(&L.up_rp, M.urp.size(), by)) || (rc = dal(&L.up_col, M.ucol.size(), by)) ||
-      (rc = dal(&L.up_v64, M.uval.size(), by)) || (rc = dal(&L.up_v32, M.uval.size(), by)) ||
-      (rc = dal(&L.up_diag64, M.udiag.size(), by)) || (rc = dal(&L.up_diag32, M.udiag.size(), by)) ||
-      (rc = dal(&L.buf64, (size_t)L.ld + nc, by)) || (rc = dal(&L.buf32, (size_t)L.ld + nc, by)))
+  if ((rc = dal(*H.mem, &L.down_rp, M.drp.size(), by)) || (rc = dal(*H.mem, &L.down_col, M.dcol.size(), by)) ||
+      (rc = dal(*H.mem, &L.down_v64, M.dval.size(), by)) || (rc = dal(*H.mem, &L.down_v32, M.dval.size(), by)) ||
+      (rc = dal(*H.mem, &L.up_rp, M.urp.size(), by)) || (rc = dal(*H.mem, &L.up_col, M.ucol.size(), by)) ||
+      (rc = dal(*H.mem, &L.up_v64, M.uval.size(), by)) || (rc = dal(*H.mem, &L.up_v32, M.uval.size(), by)) ||
+      (rc = dal(*H.mem, &L.up_diag64, M.udiag.size(), by)) || (rc = dal(*H.mem, &L.up_diag32, M.udiag.size(), by)) ||
+      (rc = dal(*H.mem, &L.buf64, (size_t)L.ld + nc, by)) || (rc = dal(*H.mem, &L.buf32, (size_t)L.ld + nc, by)))
     return rc;
   if ((rc = put(L.down_rp, M.drp)) || (rc = put(L.down_col, M.dcol)) || (rc = put(L.down_v64, M.dval)) ||
       (rc = put(L.down_v32, to32(M.dval))) || (rc = put(L.up_rp, M.urp)) || (rc = put(L.up_col, M.ucol)) ||
@@ -437,8 +431,8 @@ int upload_level(Level& L, int n, int nc, const HostMats& M, Hierarchy& H) {
   // the level buffers are read in full by the products' own-row loads: keep them finite
   MLCK(hipMemset(L.buf64, 0, ((size_t)L.ld + nc) * sizeof(double)));
   MLCK(hipMemset(L.buf32, 0, ((size_t)L.ld + nc) * sizeof(float)));
-  if ((rc = build_spmv_plan(nc, M.drp.data(), M.dcol.data(), L.down))) return rc;
-  if ((rc = build_spmv_plan(n, M.urp.data(), M.ucol.data(), L.up))) return rc;
+  if ((rc = build_spmv_plan(*H.mem, nc, M.drp.data(), M.dcol.data(), L.down))) return rc;
+  if ((rc = build_spmv_plan(*H.mem, n, M.urp.data(), M.ucol.data(), L.up))) return rc;
   H.stored_nnz += (int64_t)M.dcol.size() + (int64_t)M.ucol.size();
   return ISIRA_OK;
 }
@@ -448,9 +442,9 @@ int upload_coarsest(const HostCoarsest& C, Hierarchy& H) {
   H.mL = C.m;
   int64_t& by = H.device_bytes;
   int rc;
-  if ((rc = dal(&H.cidx, C.cidx.size(), by)) || (rc = dal(&H.cpos, C.cpos.size(), by)) ||
-      (rc = dal(&H.Ainv, C.Ainv.size(), by)) || (rc = dal(&H.cdinv, C.cdinv.size(), by)) ||
-      (rc = dal(&H.bufL64, (size_t)C.n, by)) || (rc = dal(&H.bufL32, (size_t)C.n, by)))
+  if ((rc = dal(*H.mem, &H.cidx, C.cidx.size(), by)) || (rc = dal(*H.mem, &H.cpos, C.cpos.size(), by)) ||
+      (rc = dal(*H.mem, &H.Ainv, C.Ainv.size(), by)) || (rc = dal(*H.mem, &H.cdinv, C.cdinv.size(), by)) ||
+      (rc = dal(*H.mem, &H.bufL64, (size_t)C.n, by)) || (rc = dal(*H.mem, &H.bufL32, (size_t)C.n, by)))
     return rc;
   if ((rc = put(H.cidx, C.cidx)) || (rc = put(H.cpos, C.cpos)) || (rc = put(H.Ainv, C.Ainv)) ||
       (rc = put(H.cdinv, C.cdinv)))
@@ -463,16 +457,19 @@ int upload_coarsest(const HostCoarsest& C, Hierarchy& H) {
 }  // namespace
 
 void release(Hierarchy& H) {
+  if (!H.mem) return;  // nothing was ever allocated
   for (Level& L : H.lv) {
-    free_spmv_plan(L.down);
-    free_spmv_plan(L.up);
-    dfr(L.down_rp); dfr(L.down_col); dfr(L.down_v64); dfr(L.down_v32);
-    dfr(L.up_rp); dfr(L.up_col); dfr(L.up_v64); dfr(L.up_v32); dfr(L.up_diag64);
-    dfr(L.up_diag32); dfr(L.buf64); dfr(L.buf32);
+    free_spmv_plan(*H.mem, L.down);
+    free_spmv_plan(*H.mem, L.up);
+    dfr(*H.mem, L.down_rp); dfr(*H.mem, L.down_col); dfr(*H.mem, L.down_v64); dfr(*H.mem, L.down_v32);
+    dfr(*H.mem, L.up_rp); dfr(*H.mem, L.up_col); dfr(*H.mem, L.up_v64); dfr(*H.mem, L.up_v32); dfr(*H.mem, L.up_diag64);
+    dfr(*H.mem, L.up_diag32); dfr(*H.mem, L.buf64); dfr(*H.mem, L.buf32);
   }
-  dfr(H.cidx); dfr(H.cpos); dfr(H.Ainv); dfr(H.cdinv); dfr(H.bufL64); dfr(H.bufL32);
-  dfr(H.zero64); dfr(H.zero32);
+  dfr(*H.mem, H.cidx); dfr(*H.mem, H.cpos); dfr(*H.mem, H.Ainv); dfr(*H.mem, H.cdinv); dfr(*H.mem, H.bufL64); dfr(*H.mem, H.bufL32);
+  dfr(*H.mem, H.zero64); dfr(*H.mem, H.zero32);
+  DevMem* mem = H.mem;
   H = Hierarchy{};
+  H.mem = mem;
 }
 
 int setup(Hierarchy& H, int n, const int32_t* rp, const int32_t* col, const double* w,
@@ -501,8 +498,8 @@ int setup(Hierarchy& H, int n, const int32_t* rp, const int32_t* col, const doub
   }
   int maxc = 1;
   for (int l = 0; l < L; ++l) maxc = std::max(maxc, H.lv[l].nc);
-  if ((rc = dal(&H.zero64, (size_t)maxc, H.device_bytes)) ||
-      (rc = dal(&H.zero32, (size_t)maxc, H.device_bytes))) {
+  if ((rc = dal(*H.mem, &H.zero64, (size_t)maxc, H.device_bytes)) ||
+      (rc = dal(*H.mem, &H.zero32, (size_t)maxc, H.device_bytes))) {
     release(H);
     return rc;
   }

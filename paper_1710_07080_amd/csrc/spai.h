@@ -7,6 +7,7 @@ namespace isira {
 namespace spai {
 
 struct SpaiWork {
+  DevMem* mem = nullptr;     // the context's device memory (set at context creation)
   int64_t n = 0, nnz = 0;
   float* diag32 = nullptr;   // M_ii (internal order)
   double* diag64 = nullptr;  // M_ii in FP64 for the FP64 inner solve
@@ -53,6 +54,7 @@ void sparse_step(const SpaiWork& w, int n, const T* r, T* u, const T* V, int64_t
 
 int32_t nparam();
 int ensure(SpaiWork& w, int64_t n, int64_t nnz);
+size_t work_bytes(int64_t n, int64_t nnz);  // device bytes ensure() allocates
 // Network forward: fills diag32 / diag64 / offd (internal order) for (sigma, trim).
 int forward(SpaiWork& w, const int32_t* rp, const int32_t* col, const void* wts, int wdt,
             const double* deg, int n, int64_t nnz, double sigma, int trim, const float* params,

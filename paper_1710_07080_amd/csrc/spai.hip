@@ -6,27 +6,22 @@ namespace isira {
 namespace spai {
 
 void free_work(SpaiWork& w) {
-  for (float** p : {&w.diag32, &w.offd, &w.feat, &w.t1, &w.h, &w.agg, &w.sdiag, &w.scratch}) {
-    if (*p) (void)hipFree(*p);
-    *p = nullptr;
-  }
-  if (w.diag64) (void)hipFree(w.diag64);
-  if (w.rowidx) (void)hipFree(w.rowidx);
-  if (w.gpart) (void)hipFree(w.gpart);
-  w.diag64 = nullptr;
-  w.rowidx = nullptr;
-  w.gpart = nullptr;
+  if (!w.mem) return;  // nothing was ever allocated
+  for (float** p : {&w.diag32, &w.offd, &w.feat, &w.t1, &w.h, &w.agg, &w.sdiag, &w.scratch})
+    dfree(*w.mem, *p);
+  dfree(*w.mem, w.diag64);
+  dfree(*w.mem, w.rowidx);
+  dfree(*w.mem, w.gpart);
   w.scratch_elems = w.gpart_elems = 0;
   free_pruned(w);
 }
 
 void free_pruned(SpaiWork& w) {
-  if (w.prp) (void)hipFree(w.prp);
-  if (w.pcol) (void)hipFree(w.pcol);
-  if (w.pval) (void)hipFree(w.pval);
-  w.prp = nullptr;
-  w.pcol = nullptr;
-  w.pval = nullptr;
+  if (w.mem) {
+    dfree(*w.mem, w.prp);
+    dfree(*w.mem, w.pcol);
+    dfree(*w.mem, w.pval);
+  }
   w.pruned = false;
   w.pnnz = 0;
 }

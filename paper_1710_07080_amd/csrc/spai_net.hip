@@ -683,38 +683,46 @@ namespace spai {
 
 int32_t nparam() { return NP; }
 
-static int alloc_f(float** p, size_t count) {
-  return hipMalloc((void**)p, (count ? count : 1) * sizeof(float)) == hipSuccess ? 0 : -1;
-}
-
 int ensure(SpaiWork& w, int64_t n, int64_t nnz) {
   if (w.n == n && w.nnz == nnz && w.diag32) return 0;
   free_work(w);
   w.n = n;
   w.nnz = nnz;
-  if (alloc_f(&w.diag32, n) || hipMalloc((void**)&w.diag64, n * sizeof(double)) != hipSuccess ||
-      alloc_f(&w.offd, nnz) || alloc_f(&w.feat, n * F) || alloc_f(&w.t1, n * H) ||
-      alloc_f(&w.h, n * H) || alloc_f(&w.agg, n * H) || alloc_f(&w.sdiag, n) ||
-      hipMalloc((void**)&w.rowidx, nnz * sizeof(int32_t)) != hipSuccess)
-    return -1;
+  DevMem& m = *w.mem;
+  int rc;
+  if ((rc = dalloc(m, &w.diag32, n)) || (rc = dalloc(m, &w.diag64, n)) || (rc = dalloc(m, &w.offd, nnz)) ||
+      (rc = dalloc(m, &w.feat, n * F)) || (rc = dalloc(m, &w.t1, n * H)) || (rc = dalloc(m, &w.h, n * H)) ||
+      (rc = dalloc(m, &w.agg, n * H)) || (rc = dalloc(m, &w.sdiag, n)) || (rc = dalloc(m, &w.rowidx, nnz))) {
+    free_work(w);
+    return rc;
+  }
   return 0;
 }
 
-static float* scratch(SpaiWork& w, size_t elems) {
+// bytes of the buffers ensure() allocates
+size_t work_bytes(int64_t n, int64_t nnz) {
+  return dev_round(n * 4) + dev_round(n * 8) + dev_round(nnz * 4) + dev_round(n * F * 4) +
+         3 * dev_round(n * H * 4) + dev_round(n * 4) + dev_round(nnz * 4);
+}
+
+static int scratch(SpaiWork& w, size_t elems, float** out) {
+  *out = nullptr;
   if (w.scratch_elems < elems) {
-    if (w.scratch) (void)hipFree(w.scratch);
-    w.scratch = nullptr;
+    dfree(*w.mem, w.scratch);
     w.scratch_elems = 0;
-    if (hipMalloc((void**)&w.scratch, elems * sizeof(float)) != hipSuccess) return nullptr;
+    const int rc = dalloc(*w.mem, &w.scratch, elems);
+    if (rc) return rc;
     w.scratch_elems = elems;
   }
-  return w.scratch;
+  *out = w.scratch;
+  return 0;
 }
 
 int forward(SpaiWork& w, const int32_t* rp, const int32_t* col, const void* wts, int wdt,
             const double* deg, int n, int64_t nnz, double sigma, int trim, const float* params,
             hipStream_t s) {
-  if (ensure(w, n, nnz)) return -1;
+  int rc = ensure(w, n, nnz);
+  if (rc) return rc;
   const int gw = grid_for(n, kBlock / 64, 8192);
   k_rowidx<<<gw, kBlock, 0, s>>>(n, rp, w.rowidx);
   k_features<<<gw, kBlock, 0, s>>>(n, rp, col, deg, trim, sigma, w.feat);
@@ -733,13 +741,15 @@ int loss_grad(SpaiWork& w, const int32_t* rp, const int32_t* col, const void* wt
               const int32_t* perm, const float* r, const float* z, int S, float* grad,
               double* loss_host, RedBuf rb, hipStream_t s) {
   if (S < 1 || S > 64) return -2;
-  if (forward(w, rp, col, wts, wdt, deg, n, nnz, sigma, trim, params, s)) return -1;
+  int frc = forward(w, rp, col, wts, wdt, deg, n, nnz, sigma, trim, params, s);
+  if (frc) return frc;
   const size_t nS = (size_t)n * S;
   // 4 sample blocks, 6 per-vertex H-vectors + 2 scalars, per-entry dpre/u/dg, then 16-byte
   // aligned doubles zz[64] and the loss (65 doubles = 130 floats) with generous slack
   const size_t need = 4 * nS + (size_t)n * (6 * H + 2) + (size_t)nnz * (2 * H + 1) + 512;
-  float* base = scratch(w, need);
-  if (!base) return -1;
+  float* base = nullptr;
+  const int src = scratch(w, need, &base);
+  if (src) return src;
   float* Rt = base;
   float* Zt = Rt + nS;
   float* Yt = Zt + nS;

@@ -23,6 +23,8 @@ ISIRA_E_DISCONNECTED = -3
 ISIRA_E_HIP = -4
 ISIRA_E_PRECOND = -5
 ISIRA_E_STATE = -6
+ISIRA_E_WORKSPACE = -7
+WS_LEARNED = 1
 W_NONE, W_F32, W_F64 = 0, 1, 2
 FP64, FP32 = 0, 1
 PC_JACOBI, PC_LEARNED, PC_MULTILEVEL = 0, 1, 2
@@ -108,7 +110,8 @@ class MlInfo(ctypes.Structure):
 
 
 EXPORTS = [
-    "isira_default_options", "isira_create", "isira_destroy", "isira_get_info", "isira_solve",
+    "isira_default_options", "isira_create", "isira_create_ws", "isira_workspace_bytes",
+    "isira_memory_info", "isira_destroy", "isira_get_info", "isira_solve",
     "isira_laplacian_apply", "isira_laplacian_apply_f32", "isira_time_spmv", "isira_inner_solve",
     "isira_orthonormalize", "isira_orthonormalize_noalloc", "isira_symeig", "isira_symeig_lowest", "isira_spai_nparam", "isira_spai_install",
     "isira_spai_prune", "isira_spai_export", "isira_spai_loss_grad", "isira_adam_step", "isira_ml_default_options",
@@ -139,12 +142,17 @@ def load() -> ctypes.CDLL:
         "isira_default_options": (i32, [ctypes.POINTER(Options)]),
         "isira_create": (i32, [ctypes.POINTER(vp), i64, i64, vp, vp, vp, i32, vp, i32]),
         "isira_destroy": (None, [vp]),
+        "isira_create_ws": (i32, [ctypes.POINTER(vp), i64, i64, vp, vp, vp, i32, i32, vp, ctypes.c_size_t,
+                                  i32, ctypes.POINTER(Options), vp, i32]),
+        "isira_workspace_bytes": (ctypes.c_size_t, [i64, i64, i32, i32, ctypes.POINTER(Options), i32]),
+        "isira_memory_info": (i32, [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                    ctypes.POINTER(ctypes.c_size_t)]),
         "isira_get_info": (i32, [vp, ctypes.POINTER(Info)]),
         "isira_solve": (i32, [vp, i32, dbl, dbl, ctypes.POINTER(Options), vp, vp, vp,
                               ctypes.POINTER(Stats)]),
         "isira_laplacian_apply": (i32, [vp, vp, vp]),
         "isira_laplacian_apply_f32": (i32, [vp, vp, vp]),
-        "isira_time_spmv": (i32, [vp, i32, i32, _c_double_p]),
+        "isira_time_spmv": (i32, [vp, i32, i32, i32, _c_double_p]),
         "isira_inner_solve": (i32, [vp, vp, vp, i32, dbl, dbl, i64, dbl, i32, i32, i32, i32, vp,
                                     _c_int32_p, _c_double_p]),
         "isira_orthonormalize": (i32, [vp, vp, i32, vp, vp, _c_double_p]),
@@ -197,6 +205,14 @@ def _require_cuda(t, dtype, numel, name):
         raise TypeError(f"{name} must be a contiguous CUDA tensor of dtype {dtype}")
     if t.numel() < numel:
         raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
+
+
+def workspace_bytes(n: int, nnz: int, k: int, w_dtype: int = W_NONE, flags: int = 0, **opts) -> int:
+    """isira_workspace_bytes: device bytes of a context made by Context.with_workspace."""
+    o = default_options()
+    for key, val in opts.items():
+        setattr(o, key, val)
+    return int(load().isira_workspace_bytes(int(n), int(nnz), int(w_dtype), int(k), ctypes.byref(o), int(flags)))
 
 
 def default_options() -> Options:
@@ -272,6 +288,56 @@ class Context:
         _check(lib.isira_create(ctypes.byref(handle), self.n, self.nnz, _ptr(row_ptr), _ptr(col), wp,
                                 wdt, s, 1 if validate else 0))
         self._h = handle
+
+    @classmethod
+    def with_workspace(cls, n: int, row_ptr, col, w=None, *, workspace, k: int, stream: Optional[int] = None,
+                       validate: bool = True, **opts) -> "Context":
+        """isira_create_ws: every device buffer of the context is carved from `workspace` (a
+        CUDA uint8 tensor the caller keeps alive); row_ptr/col/w may be numpy arrays (host) or
+        CUDA tensors (device).  opts size the solve workspace (m, q) as for solve()."""
+        import torch
+
+        lib = load()
+        self = cls.__new__(cls)
+        self._lib = lib
+        self.n = int(n)
+        on_dev = isinstance(row_ptr, torch.Tensor)
+        if on_dev:
+            for t, dt in ((row_ptr, torch.int32), (col, torch.int32)):
+                _require_cuda(t, dt, 1, "CSR array")
+            self.nnz = int(col.numel())
+        else:
+            row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            self.nnz = int(row_ptr[-1])
+        wdt = W_NONE
+        if w is not None:
+            if on_dev:
+                wdt = W_F32 if w.dtype == torch.float32 else W_F64
+            else:
+                w = np.ascontiguousarray(w)
+                if w.dtype != np.float32:
+                    w = w.astype(np.float64, copy=False)
+                wdt = W_F32 if w.dtype == np.float32 else W_F64
+        if not (isinstance(workspace, torch.Tensor) and workspace.is_cuda):
+            raise TypeError("workspace must be a CUDA tensor")
+        o = default_options()
+        for key, val in opts.items():
+            setattr(o, key, val)
+        self._workspace = workspace  # the context's memory lives there
+        handle = ctypes.c_void_p()
+        s = current_stream() if stream is None else stream
+        _check(lib.isira_create_ws(ctypes.byref(handle), self.n, self.nnz, _ptr(row_ptr), _ptr(col), _ptr(w), wdt,
+                                   1 if on_dev else 0, workspace.data_ptr(),
+                                   workspace.numel() * workspace.element_size(), int(k), ctypes.byref(o), s,
+                                   1 if validate else 0))
+        self._h = handle
+        return self
+
+    def memory_info(self) -> dict:
+        a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(self._lib.isira_memory_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"in_use": a.value, "peak": b.value, "capacity": c.value}
 
     @classmethod
     def from_graph(cls, g, weights_dtype=None, **kw) -> "Context":
@@ -351,9 +417,10 @@ class Context:
         _check(self._lib.isira_laplacian_apply_f32(self._h, _ptr(x), _ptr(y)))
         return y
 
-    def time_spmv(self, prec: int = FP64, reps: int = 50) -> float:
+    def time_spmv(self, prec: int = FP64, reps: int = 50, cold: bool = False) -> float:
+        """Average ms per launch of the product's main dispatch (cold: each launch from HBM)."""
         ms = ctypes.c_double(0)
-        _check(self._lib.isira_time_spmv(self._h, int(prec), int(reps), ctypes.byref(ms)))
+        _check(self._lib.isira_time_spmv(self._h, int(prec), int(reps), 1 if cold else 0, ctypes.byref(ms)))
         return ms.value
 
     def inner_solve(self, r, V=None, sigma: float = 0.0, delta: float = 0.0, trim: int = -1,

@@ -144,3 +144,17 @@ def test_host_symeig_lowest(P, case):
         v0 = V[:, 0]
         sin = np.linalg.norm(s1 - (s1 @ v0) * v0)  # the part of s1 orthogonal to v0
         assert sin <= 64 * 2.0 ** -53 * scale / gap + 1e-14
+
+
+def test_workspace_bytes_bound(P):
+    wb = P.isira.workspace_bytes
+    n, nnz = 100000, 1600000
+    assert wb(2, 10, 4) == 0 and wb(n, nnz, 0) == 0 and wb(n, nnz, 65) == 0
+    assert wb(n, nnz, 4, m=193) == 0  # m beyond ISIRA_MAX_BASIS
+    a = wb(n, nnz, 10)
+    # at least the basis U, W (n x m FP64, m = 2 (k + 10)) and the CSR column indices
+    assert a >= 2 * n * 40 * 8 + nnz * 4
+    assert wb(n, nnz, 20) > a  # more pairs: a larger basis and more deflation columns
+    assert wb(n, nnz, 10, w_dtype=P.isira.W_F64) >= a + nnz * 12  # FP64 and FP32 weights
+    assert wb(n, nnz, 10, flags=P.isira.WS_LEARNED) >= a + nnz * 12  # M's values and pruned copy
+    assert wb(n, nnz, 10, q=30, m=60) > a
