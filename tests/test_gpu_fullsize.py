@@ -29,6 +29,9 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 WORKLOADS = {
     "rmat20": lambda: gg.rmat(20, 8, seed=2),
     "grid128w": lambda: gg.grid3d(128, 128, 128, weights=(0.5, 1.5), seed=3),
+    # the learned preconditioner's held-out graph: R-MAT scale 22, edge factor 16 (mean degree
+    # 32 before deduplication), built with the GPU sorts (same CSR as the numpy path)
+    "rmat22e16": lambda: gg.rmat(22, 16, seed=4000, device="cuda"),
 }
 
 
@@ -60,7 +63,8 @@ def _setup(P, name):
 
 @pytest.mark.parametrize("name,prec,pc", [("rmat20", 0, 0), ("rmat20", 1, 0), ("rmat20", 0, 2),
                                          ("rmat20", 1, 1), ("grid128w", 1, 0), ("grid128w", 0, 0),
-                                         ("grid128w", 1, 2), ("grid128w", 1, 1)])
+                                         ("grid128w", 1, 2), ("grid128w", 1, 1),
+                                         ("rmat22e16", 0, 0), ("rmat22e16", 1, 1)])
 def test_fullsize_matches_oracle(P, name, prec, pc):
     gold, g, ctx, L = _setup(P, name)
     k, tol = gold["k"], gold["tol"]
