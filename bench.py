@@ -4,13 +4,17 @@ One step = one full isira_solve (Algorithm 3.2: Rayleigh-Ritz, residual, trimmed
 PCG inner solve, enlargement, CGS2, expansion, restart/purge/lock) for the k smallest
 positive eigenpairs of a seeded synthetic graph that is already resident in HBM.
 
-Default workload: R-MAT scale 20 (8 * 2^20 edge samples, (0.57, 0.19, 0.19, 0.05)),
-symmetrized, deduplicated, self loops removed, largest connected component, unit
-weights; FP64 plain method (Jacobi), k = 20, sigma = 0, tol = 1e-8.
+Default workload: the learned preconditioner's held-out graph, R-MAT scale 22 with 16 * 2^22
+edge samples ((0.57, 0.19, 0.19, 0.05), symmetrized, deduplicated, self loops removed,
+largest connected component, unit weights; n = 2,394,541, 128 M stored entries), k = 20,
+sigma = 0, tol = 1e-8.  The timed form is the metric's "learned + FP32": the trained network's
+approximate inverse (pruned) as the inner preconditioner and FP32 inner solves, with FP64
+outer steps.  The plain FP64 method (Jacobi) and FP32 Jacobi (the learned part's own gain)
+are timed beside it the same way (median of the same number of solves).
 
 Prints one JSON line: time to k eigenpairs (seconds, lower is better), the SpMV roofline
-of the dominant kernel (measured live with HIP events on the library's stream), and the
-FP64 CPU oracle timed on a bounded sample on this host.
+of the dominant kernel (measured live with HIP events on the library's stream, each launch
+from HBM), and the FP64 CPU oracle timed on a bounded sample on this host.
 """
 from __future__ import annotations
 
@@ -26,6 +30,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+DEFAULT_WORKLOAD = "rmat22e16"
+WORKLOAD_TEXT = {
+    "rmat22e16": "rmat22e16: held-out R-MAT scale 22, 16 * 2^22 edge samples, LCC, unit weights",
+    "rmat20": "rmat20: R-MAT scale 20, edge factor 8, LCC, unit weights",
+    "chunglu24": "chunglu24: Chung-Lu n = 2^24, exponent 2.1, mean degree 24, LCC, unit weights",
+    "grid128w": "grid128w: 3-D 7-point grid 128^3, weights U[0.5, 1.5]",
+    "grid64": "grid64: 2-D 5-point grid 64 x 64, unit weights",
+}
 
 
 def log(msg):
@@ -58,7 +70,7 @@ CAL_BYTES = 256 << 20  # size of the calibration copy in --probe runs
 PRUNE_TAU = 0.02
 # HBM traffic of the dominant kernel from rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE),
 # with the sources it was measured on; it is reported only while those sources are unchanged.
-TRAFFIC_SUMMARY = os.path.join(HERE, "profiles", "k_spmv_fp64_rmat20_traffic.md")
+PROFILES = os.path.join(HERE, "profiles")
 KERNEL_SOURCES = [os.path.join(HERE, "paper_1710_07080_amd", "csrc", f)
                   for f in ("kernels.hip", "internal.h", "api.hip")]
 
@@ -73,13 +85,15 @@ def sources_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
-    """Bytes per launch of the FP64 product from the committed counter summary, or None when
-    there is none for this workload or the kernel sources changed since it was taken."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def measured_traffic(workload, prec):
+    """Bytes per launch of the product (prec "fp64" / "fp32") from the committed counter
+    summary, or None when there is none for this workload or the kernel sources changed
+    since it was taken."""
+    path = os.path.join(PROFILES, f"k_spmv_{prec}_{workload}_traffic.md")
+    if not os.path.exists(path):
         return None
     rec = None
-    with open(TRAFFIC_SUMMARY) as f:
+    with open(path) as f:
         for line in f:
             if line.startswith("traffic_json: "):
                 rec = json.loads(line[len("traffic_json: "):])
@@ -122,10 +136,25 @@ def spmv_bytes(g, s):
     return 4 * (g.n + 1) + g.nnz * (4 + sw) + 3 * g.n * s
 
 
-def cpu_baseline(g, cfg, gpu_stats, u0, inner_rtol, budget):
-    """The FP64 oracle on the same graph, start block and parameters, stopped after
-    `budget` seconds; its time per outer iteration is scaled by the GPU run's outer
-    iteration count to the time for all k pairs."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, cfg, ref_stats, u0, inner_rtol, budget):
+    """The FP64 oracle (plain method, same graph, start block and tolerances) on one host
+    core for a bounded sample: its set-up, then outer iterations until `budget` seconds.  Each
+    sampled outer iteration's time is fitted (non-negative least squares) as a * (inner
+    iterations) + b * (columns of U and V) + c, and the fit is applied to the counts of the
+    GPU's plain FP64 solve of the same workload (inner iterations, summed basis columns,
+    outer iterations) to estimate the oracle's time to k pairs."""
+    from scipy.optimize import nnls
     from threadpoolctl import threadpool_limits
 
     from oracle import isira_oracle as O
@@ -135,17 +164,25 @@ def cpu_baseline(g, cfg, gpu_stats, u0, inner_rtol, budget):
         res = O.isira(g, cfg["k"], cfg["sigma"], cfg["tol"], u0, inner_rtol=inner_rtol,
                       time_budget=budget)
         el = time.perf_counter() - t0
-    outer_done = len(res.history)
-    per_outer = el / max(1, outer_done)
-    est = per_outer * gpu_stats["outer_total"]
+    rows = np.array(res.outer_log, dtype=np.float64).reshape(-1, 3)
+    if len(rows) < 3:
+        return {"value": None, "unit": "s", "cores": 1, "kind": "oracle", "cpu": cpu_model(),
+                "sample": f"too few outer iterations in {el:.1f} s"}
+    A = np.column_stack([rows[:, 1], rows[:, 2], np.ones(len(rows))])
+    coef, _ = nnls(A, rows[:, 0])
+    counts = np.array([ref_stats["inner_total"], ref_stats["basis_cols_total"], ref_stats["outer_total"]],
+                      dtype=np.float64)
+    est = res.setup_seconds + float(coef @ counts)
     return {
-        "value": est, "unit": "s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle iSIRA on the same graph/start block/tolerances, stopped after "
-                   f"{el:.1f} s with {outer_done} outer iterations and {res.converged} pairs "
-                   f"locked; time per outer iteration x {gpu_stats['outer_total']} outer "
-                   f"iterations of the GPU solve"),
-        "outer_iterations_sampled": outer_done,
-        "pairs_locked_in_sample": res.converged,
+        "value": est, "unit": "s", "cores": 1, "kind": "oracle", "cpu": cpu_model(),
+        "sample": (f"oracle iSIRA (plain FP64, numpy/scipy on 1 thread) on the same graph, start block and "
+                   f"tolerances: set-up {res.setup_seconds:.1f} s, then {len(rows)} outer iterations in "
+                   f"{el - res.setup_seconds:.1f} s ({int(rows[:, 1].sum())} inner iterations, "
+                   f"{res.converged} pairs locked); per outer iteration {coef[0]:.3g} s per inner "
+                   f"iteration + {coef[1]:.3g} s per basis column + {coef[2]:.3g} s, applied to the GPU "
+                   f"plain FP64 solve's {ref_stats['inner_total']} inner iterations, "
+                   f"{ref_stats['basis_cols_total']} basis columns and {ref_stats['outer_total']} outer "
+                   f"iterations"),
     }
 
 
@@ -166,7 +203,7 @@ def trim_study(ctx, g, cfg, opts, args):
             ts.append(st["ms_total"] / 1e3)
         ev = np.sort(ev)
         ref = ev if ref is None else ref
-        row = {"trim": name, "vertex": trim, "degree": float(d[trim]), "s": min(ts),
+        row = {"trim": name, "vertex": trim, "degree": float(d[trim]), "median_s": float(np.median(ts)),
                "outer_total": st["outer_total"], "inner_total": st["inner_total"],
                "converged": st["n_converged"], "max_resid": float(np.max(res)),
                "max_rel_eval_diff_vs_max_degree": float(np.max(np.abs(ev - ref) / ref))
@@ -190,7 +227,7 @@ def rank_one_study(ctx, g, cfg, opts, args):
             ts.append(st["ms_total"] / 1e3)
         ev = np.sort(ev)
         ref = ev if ref is None else ref
-        rows.append({"rank_one_term": name, "s": min(ts), "outer_total": st["outer_total"],
+        rows.append({"rank_one_term": name, "median_s": float(np.median(ts)), "outer_total": st["outer_total"],
                      "inner_total": st["inner_total"], "inner_fallbacks": st["inner_fallbacks"],
                      "converged": st["n_converged"], "max_resid": float(np.max(res)),
                      "max_rel_eval_diff_vs_kept": float(np.max(np.abs(ev - ref) / ref))
@@ -216,7 +253,7 @@ def shift_study(ctx, g, cfg, opts, args, P):
             ts.append(st["ms_total"] / 1e3)
         ev = np.sort(ev)
         ref = ev if ref is None else ref
-        row = {"variant": name, "s": min(ts), "outer_total": st["outer_total"],
+        row = {"variant": name, "median_s": float(np.median(ts)), "outer_total": st["outer_total"],
                "inner_total": st["inner_total"], "inner_fallbacks": st["inner_fallbacks"],
                "sigma_last": st["sigma_last"], "converged": st["n_converged"],
                "max_resid": float(np.max(res)) if len(res) else None,
@@ -239,23 +276,57 @@ def prune_setup(ctx) -> dict:
             "prune_setup_s": time.perf_counter() - t}
 
 
+def timed_solves(ctx, cfg, steps, **opts):
+    """`steps` solves of one form; returns (per-solve seconds from HIP events on the
+    context's stream, the last solve's outputs)."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    times, last = [], None
+    for _ in range(steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        last = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], **opts)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    return times, last
+
+
+def form_row(times, out, gold, ref_ev=None):
+    ev, X, res, st = out
+    row = {"median_s": float(np.median(times)), "min_s": float(np.min(times)), "solves": len(times),
+           "converged": st["n_converged"], "outer_total": st["outer_total"], "inner_total": st["inner_total"],
+           "max_resid": float(np.max(res)) if len(res) else None}
+    if gold is not None:
+        row["rel_eval_err_vs_oracle"] = rel_err(ev, gold)
+    if ref_ev is not None and len(ev) == len(ref_ev):
+        a, b = np.sort(ev), np.sort(ref_ev)
+        row["max_rel_eval_diff_vs_plain_fp64"] = float(np.max(np.abs(a - b) / b))
+    return row
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--inner-rtol", type=float, default=1e-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=40.0)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="time only the metric's two forms (learned + FP32 and plain FP64) and FP32 Jacobi")
+    ap.add_argument("--variant-steps", type=int, default=3,
+                    help="solves of each further variant (moving shift, multilevel, full learned M)")
     ap.add_argument("--precond", choices=["jacobi", "learned", "learned_pruned", "multilevel"],
-                    default="jacobi",
-                    help="preconditioner of the timed solve (default: the plain method's Jacobi)")
-    ap.add_argument("--inner-prec", choices=["fp64", "fp32"], default="fp64",
-                    help="precision of the timed solve's inner solves (default: the plain FP64 method)")
+                    default="learned_pruned",
+                    help="preconditioner of the timed form (default: the pruned learned M)")
+    ap.add_argument("--inner-prec", choices=["fp64", "fp32"], default="fp32",
+                    help="precision of the timed form's inner solves (default FP32)")
     ap.add_argument("--probe", action="store_true",
-                    help="only a 256 MiB device copy (counter calibration) and launches of the "
+                    help="only a 256 MiB device copy (counter calibration) and cold launches of the "
                          "FP64 and FP32 products, for rocprofv3 counter runs")
     ap.add_argument("--probe-reps", type=int, default=20)
     ap.add_argument("--study", choices=["trim", "rank1", "shift"], default=None,
@@ -292,32 +363,15 @@ def main():
         b.copy_(a)  # the calibration copy: CAL_BYTES read, CAL_BYTES written
         torch.cuda.synchronize()
         del a, b
-        ms64 = ctx.time_spmv(P.isira.FP64, reps=args.probe_reps)
-        ms32 = ctx.time_spmv(P.isira.FP32, reps=args.probe_reps)
+        ms64 = ctx.time_spmv(P.isira.FP64, reps=args.probe_reps, cold=True)
+        ms32 = ctx.time_spmv(P.isira.FP32, reps=args.probe_reps, cold=True)
         print(json.dumps({"probe": args.workload, "calibration_copy_bytes": CAL_BYTES,
                           "spmv64_ms": ms64, "spmv64_bytes": spmv_bytes(g, 8),
                           "spmv32_ms": ms32, "spmv32_bytes": spmv_bytes(g, 4),
-                          "reps": args.probe_reps}), flush=True)
+                          "reps": args.probe_reps, "cold": True}), flush=True)
         return
     u0 = gg.start_block(g.n, 4, 1)
     opts = dict(u0=u0, inner_rtol=args.inner_rtol)
-    # the timed solve: the plain FP64 method unless another form is asked for
-    main_pc = {"jacobi": P.isira.PC_JACOBI, "learned": P.isira.PC_LEARNED,
-               "learned_pruned": P.isira.PC_LEARNED,
-               "multilevel": P.isira.PC_MULTILEVEL}[args.precond]
-    main_prec = P.isira.FP32 if args.inner_prec == "fp32" else P.isira.FP64
-    main_setup = {}
-    if main_pc == P.isira.PC_MULTILEVEL:
-        main_setup = ctx.ml_setup()
-        log(f"multilevel set-up: {main_setup}")
-    elif main_pc == P.isira.PC_LEARNED:
-        from paper_1710_07080_amd import spai_train
-
-        ctx.spai_install(spai_train.load(SPAI_WEIGHTS), sigma=cfg["sigma"])
-        if args.precond == "learned_pruned":
-            main_setup = prune_setup(ctx)
-            log(f"pruned learned M: {main_setup}")
-    main_opts = dict(opts, inner_prec=main_prec, precond=main_pc)
     if args.study == "trim":
         trim_study(ctx, g, cfg, opts, args)
         return
@@ -327,36 +381,70 @@ def main():
     if args.study == "shift":
         shift_study(ctx, g, cfg, opts, args, P)
         return
-    stream = torch.cuda.current_stream()
+    gold = golden(args.workload)
+    # ---- the timed form (default: the metric's learned + FP32)
+    main_pc = {"jacobi": P.isira.PC_JACOBI, "learned": P.isira.PC_LEARNED,
+               "learned_pruned": P.isira.PC_LEARNED, "multilevel": P.isira.PC_MULTILEVEL}[args.precond]
+    main_prec = P.isira.FP32 if args.inner_prec == "fp32" else P.isira.FP64
+    setup = {}
+    if main_pc == P.isira.PC_MULTILEVEL:
+        setup = ctx.ml_setup()
+    elif main_pc == P.isira.PC_LEARNED:
+        from paper_1710_07080_amd import spai_train
+
+        t = time.perf_counter()
+        ctx.spai_install(spai_train.load(SPAI_WEIGHTS), sigma=cfg["sigma"])
+        torch.cuda.synchronize()
+        setup = {"network_forward_s": time.perf_counter() - t}
+        if args.precond == "learned_pruned":
+            setup.update(prune_setup(ctx))
+    log(f"set-up of the timed form: {setup}")
+    main_opts = dict(opts, inner_prec=main_prec, precond=main_pc)
     for w in range(args.warmup):
         ev, X, res, st = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], **main_opts)
         log(f"warmup {w}: {st['ms_total'] / 1e3:.3f} s, converged {st['n_converged']}")
+    stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     wall0 = time.perf_counter()
-    stats = []
-    for s in range(args.steps):
+    step_s, stats = [], []
+    for s_ in range(args.steps):
+        t = time.perf_counter()
         ev, X, res, st = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], **main_opts)
+        step_s.append(time.perf_counter() - t)
         stats.append(st)
-        log(f"step {s}: {st['ms_total'] / 1e3:.3f} s, outer {st['outer_total']}, "
+        log(f"step {s_}: {st['ms_total'] / 1e3:.3f} s, outer {st['outer_total']}, "
             f"inner {st['inner_total']}, converged {st['n_converged']}")
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    ms_total = e0.elapsed_time(e1)
-    sec_per_step = ms_total / 1e3 / args.steps
+    sec_per_step = e0.elapsed_time(e1) / 1e3 / args.steps
     st = stats[-1]
     ok = st["n_converged"] == cfg["k"] and float(np.max(res)) < cfg["tol"]
-    # dominant kernel: the FP64 Laplacian SpMV, timed by HIP events on the context stream
-    ms_spmv = ctx.time_spmv(P.isira.FP64, reps=200)
-    b64 = spmv_bytes(g, 8)
-    achieved = b64 / (ms_spmv * 1e-3) / 1e9
-    ms_spmv32 = ctx.time_spmv(P.isira.FP32, reps=200)
-    b32 = spmv_bytes(g, 4)
-    trec = measured_traffic(args.workload)
-    traffic = trec["bytes_per_launch"] if trec else None
+    main_out = (ev, X, res, st)
+    # ---- the plain FP64 method and FP32 Jacobi, the same number of solves, median
+    ref_steps = max(1, args.steps)
+    t64, out64 = timed_solves(ctx, cfg, ref_steps, inner_prec=P.isira.FP64, precond=P.isira.PC_JACOBI, **opts)
+    plain = form_row(t64, out64, gold)
+    log(f"plain_fp64: {plain}")
+    t32, out32 = timed_solves(ctx, cfg, ref_steps, inner_prec=P.isira.FP32, precond=P.isira.PC_JACOBI, **opts)
+    j32 = form_row(t32, out32, gold, out64[0])
+    log(f"fp32_jacobi: {j32}")
+    main_row = form_row(step_s, main_out, gold, out64[0])
+    # ---- dominant kernel of the timed form: its Laplacian product (FP32 inner solves ->
+    # the FP32 product), every launch timed from HBM (cold), and back to back (warm)
+    kprec = "fp32" if main_prec == P.isira.FP32 else "fp64"
+    kp = P.isira.FP32 if main_prec == P.isira.FP32 else P.isira.FP64
+    ms_cold = ctx.time_spmv(kp, reps=100, cold=True)
+    ms_warm = ctx.time_spmv(kp, reps=100, cold=False)
+    kb = spmv_bytes(g, 4 if kprec == "fp32" else 8)
+    achieved = kb / (ms_cold * 1e-3) / 1e9
+    ms64_cold = ctx.time_spmv(P.isira.FP64, reps=100, cold=True)
+    trec = measured_traffic(args.workload, kprec)
+    form = (f"{args.precond} M + SMW, {args.inner_prec.upper()} inner PCG, FP64 outer"
+            if main_pc == P.isira.PC_LEARNED else f"{args.precond} + SMW, {args.inner_prec.upper()} inner PCG")
     out = {
         "metric": "time to k eigpairs @ resid 1e-8 (learned+FP32 vs plain FP64); SpMV HBM GB/s",
         "value": sec_per_step,
@@ -368,87 +456,69 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64" if main_prec == P.isira.FP64 else "f32 inner, f64 outer",
+        "dtype": "f32 inner, f64 outer" if main_prec == P.isira.FP32 else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: R-MAT scale 20, edge factor 8, LCC, unit weights"
-            if args.workload == "rmat20" else args.workload,
+            "workload": WORKLOAD_TEXT.get(args.workload, args.workload),
             "n": g.n, "nnz": g.nnz, "k": cfg["k"], "sigma": cfg["sigma"], "tol": cfg["tol"],
-            "inner": f"{args.inner_prec.upper()} PCG, {args.precond} + SMW", "inner_rtol": args.inner_rtol,
+            "form": form, "inner_rtol": args.inner_rtol,
         },
         "converged": bool(ok),
         "max_resid": float(np.max(res)),
         "outer_total": st["outer_total"],
         "inner_total": st["inner_total"],
+        "median_s": main_row["median_s"],
         "phases_ms": {k: round(st[k], 2) for k in ("ms_total", "ms_inner", "ms_ortho", "ms_rr_host",
                                                   "ms_residual", "ms_restart")},
         "wall_s_per_step": wall / args.steps,
+        "setup": setup,
+        "plain_fp64": plain,
+        "fp32_jacobi": j32,
+        "learned_fp32_vs_plain_fp64": {
+            "speedup_median": plain["median_s"] / main_row["median_s"],
+            "learned_fp32_median_s": main_row["median_s"], "plain_fp64_median_s": plain["median_s"]},
+        "learned_vs_fp32_jacobi": {"speedup_median": j32["median_s"] / main_row["median_s"]},
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_spmv<double, ..., TAG=1, ...> main dispatch of the FP64 Laplacian product (isira_time_spmv)",
-            "bytes_per_launch": b64, "ms_per_launch": ms_spmv,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": trec["bytes_per_launch"] if trec else None,
+            "kernel": f"k_spmv<{'float' if kprec == 'fp32' else 'double'}, ..., TAG=1, ...> main dispatch of the "
+                      f"{kprec.upper()} Laplacian product (isira_time_spmv, each launch after a 512 MiB flush)",
+            "bytes_per_launch": kb, "ms_per_launch": ms_cold, "ms_per_launch_warm": ms_warm,
         },
-        "spmv_fp32": {"ms_per_launch": ms_spmv32, "bytes_per_launch": b32,
-                      "achieved_GBs": b32 / (ms_spmv32 * 1e-3) / 1e9},
+        "spmv_fp64_cold": {"ms_per_launch": ms64_cold, "bytes_per_launch": spmv_bytes(g, 8),
+                           "achieved_GBs": spmv_bytes(g, 8) / (ms64_cold * 1e-3) / 1e9},
     }
-    gold = golden(args.workload)
     if gold is not None:
-        out[ref_key(args.workload)] = rel_err(ev, gold)
+        out[ref_key(args.workload)] = main_row.get("rel_eval_err_vs_oracle") or rel_err(ev, gold)
+    out["max_rel_eval_diff_vs_plain_fp64"] = main_row.get("max_rel_eval_diff_vs_plain_fp64")
     if not args.no_variants:
-        # the same solve with FP32 inner solves, Jacobi and learned preconditioner
-        # and the purge step's moving shift (sigma <- theta_2, MINRES inner solves)
         fixed, moving = P.isira.SHIFT_FIXED, P.isira.SHIFT_MOVING
-        # (name, inner precision, preconditioner, shift mode, set-up run before its solves)
-        variants = [("fp32_jacobi", P.isira.FP32, P.isira.PC_JACOBI, fixed, None)]
+        variants = [("moving_shift_fp64", P.isira.FP64, P.isira.PC_JACOBI, moving, None),
+                    ("moving_shift_fp32", P.isira.FP32, P.isira.PC_JACOBI, moving, None)]
         if os.path.exists(SPAI_WEIGHTS):
             from paper_1710_07080_amd import spai_train
 
-            ctx.spai_install(spai_train.load(SPAI_WEIGHTS), sigma=cfg["sigma"])
-            variants.append(("fp32_learned", P.isira.FP32, P.isira.PC_LEARNED, fixed, None))
-            # the same M pruned to its largest off-diagonal entries (set-up timed on its own)
-            variants.append(("fp32_learned_pruned", P.isira.FP32, P.isira.PC_LEARNED, fixed,
-                             lambda: prune_setup(ctx)))
-        variants += [("moving_shift_fp64", P.isira.FP64, P.isira.PC_JACOBI, moving, None),
-                     ("moving_shift_fp32", P.isira.FP32, P.isira.PC_JACOBI, moving, None)]
-        # multilevel preconditioner (aggregation multigrid for L-hat): set-up once per
-        # graph and trim index, outside the timed solves, reported on its own
+            def full_m():
+                ctx.spai_install(spai_train.load(SPAI_WEIGHTS), sigma=cfg["sigma"])
+                return {}
+
+            variants.append(("fp32_learned_full_M", P.isira.FP32, P.isira.PC_LEARNED, fixed, full_m))
         mlinfo = ctx.ml_setup()
         out["multilevel_setup"] = {k: mlinfo[k] for k in ("levels", "rows", "connected", "coarsest_dense",
                                                           "stored_nnz", "device_bytes", "setup_ms")}
-        log(f"multilevel set-up: {out['multilevel_setup']}")
         variants += [("multilevel_fp64", P.isira.FP64, P.isira.PC_MULTILEVEL, fixed, None),
                      ("multilevel_fp32", P.isira.FP32, P.isira.PC_MULTILEVEL, fixed, None)]
         for name, prec, pc, mode, prep in variants:
             extra = prep() if prep is not None else {}
-            best = None
-            for _ in range(max(1, args.steps)):
-                evv, Xv, resv, stv = ctx.solve(cfg["k"], cfg["sigma"], cfg["tol"], inner_prec=prec,
-                                               precond=pc, shift_mode=mode, **opts)
-                if best is None or stv["ms_total"] < best[3]["ms_total"]:
-                    best = (evv, Xv, resv, stv)
-            evv, Xv, resv, stv = best
-            row = {"s": stv["ms_total"] / 1e3, "converged": stv["n_converged"],
-                   "outer_total": stv["outer_total"], "inner_total": stv["inner_total"],
-                   "max_resid": float(np.max(resv)) if len(resv) else None,
-                   "speedup_vs_plain_fp64": (st["ms_total"] / stv["ms_total"]), **extra}
-            if gold is not None:
-                row[ref_key(args.workload)] = rel_err(evv, gold)
-            a, b = np.sort(evv), np.sort(ev)
-            if len(a) == len(b):
-                row["max_rel_eval_diff_vs_plain"] = float(np.max(np.abs(a - b) / b))
+            tv, outv = timed_solves(ctx, cfg, max(1, args.variant_steps), inner_prec=prec, precond=pc,
+                                    shift_mode=mode, **opts)
+            row = dict(form_row(tv, outv, gold, out64[0]), **extra)
+            row["speedup_vs_plain_fp64"] = plain["median_s"] / row["median_s"]
             out[name] = row
             log(f"{name}: {row}")
-        if "fp32_learned_pruned" in out:
-            # the metric's comparison: learned preconditioner + FP32 inner solves against the
-            # plain FP64 method, same graph, start block and tolerances, same GPU
-            lp = out["fp32_learned_pruned"]
-            out["learned_fp32_vs_plain_fp64"] = {
-                "learned_fp32_s": lp["s"], "plain_fp64_s": st["ms_total"] / 1e3,
-                "speedup": lp["speedup_vs_plain_fp64"], "form": f"pruned learned M, tau {PRUNE_TAU}"}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(g, cfg, st, u0, args.inner_rtol, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(g, cfg, out64[3], u0, args.inner_rtol, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

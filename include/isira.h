@@ -121,6 +121,8 @@ typedef struct {
   int64_t trim_index;                  /* caller label of the trimmed vertex */
   double delta;
   double sigma_last;                   /* the shift of the last inner solve */
+  int64_t basis_cols_total;            /* sum over outer iterations of the basis width plus
+                                          the locked pairs (the columns its dense steps read) */
 } isira_stats;
 
 typedef struct {

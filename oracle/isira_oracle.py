@@ -306,6 +306,10 @@ class IsiraResult:
     breakdowns: int = 0
     refreshes: int = 0
     history: list = dataclasses.field(default_factory=list)  # ||r|| per outer iteration
+    # per outer iteration: (seconds, inner iterations, basis width + locked pairs); set-up
+    # seconds before the first one (timing records for cost models, no arithmetic)
+    outer_log: list = dataclasses.field(default_factory=list)
+    setup_seconds: float = 0.0
 
 
 def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[int] = None,
@@ -367,14 +371,31 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
     evals, evecs, outer_its, inner_its, history = [], [], [], [], []
     restarts = refreshes = 0
     outer = 0
+    # timing records (no arithmetic): per outer iteration its seconds, inner iterations and
+    # the columns of U and V it worked with
+    setup_s = _time.perf_counter() - t_start
+    log, mark = [], None
+
+    def tick(inner_so_far, cols):
+        nonlocal mark
+        now = _time.perf_counter()
+        if mark is not None:
+            log.append((now - mark[0], inner_so_far - mark[1], mark[2]))
+        mark = (now, inner_so_far, cols)
+
+    def done(res):
+        res.outer_log, res.setup_seconds = log, setup_s
+        return res
+
     for _j in range(k):
         its_here = 0
         inner_here = 0
         locked = False
         while not locked:
+            tick(sum(inner_its) + inner_here, U.shape[1] + V.shape[1])
             if outer >= max_outer or (time_budget is not None and _time.perf_counter() - t_start > time_budget):
-                return _finish(L, evals, evecs, outer_its + [its_here], inner_its + [inner_here], i, dl,
-                               restarts, breakdowns, refreshes, history, partial=True)
+                return done(_finish(L, evals, evecs, outer_its + [its_here], inner_its + [inner_here], i, dl,
+                                    restarts, breakdowns, refreshes, history, partial=True))
             outer += 1
             its_here += 1
             # subspace extraction: all eigenpairs of H, ascending, unit eigenvectors
@@ -441,7 +462,8 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
             W = np.column_stack([W, w])
         outer_its.append(its_here)
         inner_its.append(inner_here)
-    return _finish(L, evals, evecs, outer_its, inner_its, i, dl, restarts, breakdowns, refreshes, history)
+    tick(sum(inner_its), U.shape[1] + V.shape[1])
+    return done(_finish(L, evals, evecs, outer_its, inner_its, i, dl, restarts, breakdowns, refreshes, history))
 
 
 def _reseed(L, V, dl, ones, n, seed, draws, breakdowns):

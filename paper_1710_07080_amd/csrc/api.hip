@@ -1349,6 +1349,7 @@ extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
     }
     outer++;
     its_pair++;
+    S.basis_cols_total += kk + nconv;
     // ---- Rayleigh-Ritz: the eigenvalues of H (ascending) and the eigenvector of the
     // smallest; all eigenvectors only when a pair is locked or the basis restarts
     double t0 = now_ms();

@@ -68,7 +68,7 @@ class Stats(ctypes.Structure):
         ("ms_total", ctypes.c_double), ("ms_inner", ctypes.c_double), ("ms_ortho", ctypes.c_double),
         ("ms_rr_host", ctypes.c_double), ("ms_residual", ctypes.c_double),
         ("ms_restart", ctypes.c_double), ("trim_index", ctypes.c_int64), ("delta", ctypes.c_double),
-        ("sigma_last", ctypes.c_double),
+        ("sigma_last", ctypes.c_double), ("basis_cols_total", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
