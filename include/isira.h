@@ -345,6 +345,19 @@ int isira_ml_get_info(const isira_ctx* ctx, isira_ml_info* info);
  * stay 0. */
 int isira_ml_shape(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* w,
                    int64_t trim, const isira_ml_options* opt, isira_ml_info* info);
+/* Host-only: level `level` (0 = L-hat) of the hierarchy isira_ml_shape describes, for the
+ * parity of its Galerkin products A_{l+1} = P_l^T A_l P_l: rows (*rows) and stored
+ * off-diagonal entries (*nnz) of A_l; when rp_out is not NULL also its CSR (rp_out rows+1,
+ * col_out / w_out nnz, where w_out holds the positive weights w_ij and the matrix entry is
+ * -w_ij), its diagonal (diag_out, rows) and the aggregate of each vertex on the next level
+ * (agg_out, rows; -1 for a vertex in no aggregate and on the coarsest level).  Level 0 is in
+ * the caller's labels with the trimmed vertex's row empty and its diagonal 0; a coarse level
+ * numbers its vertices in the order of their aggregates' first members on the finer level.
+ * All outputs are host arrays; no GPU is touched. */
+int isira_ml_level_matrix(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* w,
+                          int64_t trim, const isira_ml_options* opt, int32_t level, int64_t* rows,
+                          int64_t* nnz, int32_t* rp_out, int32_t* col_out, double* w_out,
+                          double* diag_out, int32_t* agg_out);
 /* y = cycle(x-hat) enlarged by a zero at the trimmed vertex; x, y device n FP64, caller
  * labels (x's trimmed entry is ignored).  prec: ISIRA_FP64, or ISIRA_FP32 (the cycle in
  * FP32 vectors and matrix values, as inside FP32 inner solves).  E_STATE before set-up. */

@@ -683,7 +683,7 @@ extern "C" size_t isira_workspace_bytes(int64_t n, int64_t nnz, int32_t w_dtype,
   const size_t ld = (size_t)((n + 63) / 64 * 64);
   size_t b = create_bytes(n, nnz, w_dtype) + solve_ws_bytes(ld, m, k, 0);
   if (flags & ISIRA_WS_LEARNED)  // the network's buffers and a pruned copy of every entry
-    b += spai::work_bytes(n, nnz) + dev_round((n + 1) * 4) + 2 * dev_round(nnz * 4);
+    b += spai::work_bytes(n, nnz) + dev_round((n + 1) * 4) + 2 * dev_round(nnz * 4) + dev_round(n * 4);
   return b + ((size_t)1 << 20);  // slack for alignment of the caller's pointer
 }
 
@@ -1973,7 +1973,13 @@ extern "C" int isira_spai_prune(isira_ctx* c, double tau, int64_t* kept) {
   if ((rc = dalloc(c->mem, &c->spw.prp, (size_t)n + 1))) return undo(rc);
   if ((rc = dalloc(c->mem, &c->spw.pcol, (size_t)pnnz))) return undo(rc);
   if ((rc = dalloc(c->mem, &c->spw.pval, (size_t)pnnz))) return undo(rc);
+  std::vector<int32_t> plong;
+  for (int64_t i = 0; i < n; ++i)
+    if (cnt[i] > kSpLongRow) plong.push_back((int32_t)i);
+  if ((rc = dalloc(c->mem, &c->spw.plong, plong.size()))) return undo(rc);
   hipError_t e = hipMemcpy(c->spw.prp, prp.data(), prp.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !plong.empty())
+    e = hipMemcpy(c->spw.plong, plong.data(), plong.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && pnnz > 0) e = hipMemcpy(c->spw.pcol, pcol.data(), pcol.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && pnnz > 0) e = hipMemcpy(c->spw.pval, pval.data(), pval.size() * 4, hipMemcpyHostToDevice);
   // the full-pattern values follow the pruning too (export, and any product on the pattern)
@@ -1984,6 +1990,7 @@ extern "C" int isira_spai_prune(isira_ctx* c, double tau, int64_t* kept) {
   }
   c->spw.pruned = true;
   c->spw.pnnz = pnnz;
+  c->spw.n_long = (int64_t)plong.size();
   if (kept) *kept = pnnz;
   return ISIRA_OK;
 }

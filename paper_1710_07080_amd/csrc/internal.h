@@ -241,17 +241,20 @@ void launch_pcg_update1_plain(int n, T* x, T* r, const T* p, const T* q, const T
                               int init, DevState* st, RedBuf rb, hipStream_t s,
                               bool with_fin = true);
 // Pruned learned M (diagonal mdiag plus the kept off-diagonal CSR prp/pcol/pval):
-// u = M r with the partials ||r||^2, r^T u, V-hat^T u, then k_pcg_fin1 (eq. (3.5)).
+// u = M r with the partials ||r||^2, r^T u, V-hat^T u, then k_pcg_fin1 (eq. (3.5)).  Rows
+// with more than kSpLongRow kept entries (listed in plong, n_long of them) are summed first,
+// one wave per row; the thread-per-row pass reads their u.
+constexpr int kSpLongRow = 32;
 template <typename T>
 void launch_spai_sparse_step(int n, const T* r, T* u, const int32_t* prp, const int32_t* pcol,
-                             const float* pval, const T* mdiag, const T* V, int64_t ldv, int c,
-                             const double* Ginv, double delta, int init, DevState* st, RedBuf rb,
-                             hipStream_t s);
+                             const float* pval, const T* mdiag, const int32_t* plong, int n_long,
+                             const T* V, int64_t ldv, int c, const double* Ginv, double delta,
+                             int init, DevState* st, RedBuf rb, hipStream_t s);
 // y = M x for the pruned M; returns at once when skip_if_done is set and done.
 template <typename T>
 void launch_spai_sparse_mv(int n, const T* x, T* y, const int32_t* prp, const int32_t* pcol,
-                           const float* pval, const T* mdiag, const DevState* skip_if_done,
-                           hipStream_t s);
+                           const float* pval, const T* mdiag, const int32_t* plong, int n_long,
+                           const DevState* skip_if_done, hipStream_t s);
 template <typename T>
 void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv, int c,
                                 const T* V, double delta, int init, DevState* st, RedBuf rb,

@@ -1209,10 +1209,15 @@ __global__ __launch_bounds__(kBlock) void k_spai_sparse_step(
 #pragma unroll
     for (int j = 0; j < CM; ++j) vreg[j] = V[l + (int64_t)j * ldv];
     const T rl = r[l];
-    T ul = mdiag[l] * rl;
-    const int e1 = prp[l + 1];
-    for (int e = prp[l]; e < e1; ++e) ul += (T)pval[e] * r[pcol[e]];
-    u[l] = ul;
+    const int e0 = prp[l], e1 = prp[l + 1];
+    T ul;
+    if (e1 - e0 > kSpLongRow) {
+      ul = u[l];  // summed by k_spai_long_rows
+    } else {
+      ul = mdiag[l] * rl;
+      for (int e = e0; e < e1; ++e) ul += (T)pval[e] * r[pcol[e]];
+      u[l] = ul;
+    }
     acc[0] += (double)rl * (double)rl;
     acc[1] += (double)rl * (double)ul;
 #pragma unroll
@@ -1221,12 +1226,46 @@ __global__ __launch_bounds__(kBlock) void k_spai_sparse_step(
   write_partials<NV>(acc, 2 + c, partials);
 }
 
+// u[l] = M_ll x[l] + sum of the kept m_lj x[j] for the listed long rows, one wave per row
+// (lanes stride over the row, then a wave sum).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spai_long_rows(int n_long, const int32_t* __restrict__ rows,
+                                                           const T* __restrict__ x, T* __restrict__ u,
+                                                           const int32_t* __restrict__ prp,
+                                                           const int32_t* __restrict__ pcol,
+                                                           const float* __restrict__ pval,
+                                                           const T* __restrict__ mdiag,
+                                                           const DevState* skip) {
+  if (skip && skip->done) return;
+  const int lane = threadIdx.x & 63;
+  const int nw = (gridDim.x * kBlock) >> 6;
+  for (int w = (blockIdx.x * kBlock + threadIdx.x) >> 6; w < n_long; w += nw) {
+    const int l = rows[w];
+    T acc = T(0);
+    const int e1 = prp[l + 1];
+    for (int e = prp[l] + lane; e < e1; e += 64) acc += (T)pval[e] * x[pcol[e]];
+    acc = wave_sum(acc);
+    if (lane == 0) u[l] = mdiag[l] * x[l] + acc;
+  }
+}
+
+template <typename T>
+static void launch_long_rows(int n_long, const int32_t* rows, const T* x, T* u, const int32_t* prp,
+                             const int32_t* pcol, const float* pval, const T* mdiag,
+                             const DevState* skip, hipStream_t s) {
+  if (n_long <= 0) return;
+  int grid = (n_long + kBlock / 64 - 1) / (kBlock / 64);
+  if (grid > kStreamGrid) grid = kStreamGrid;
+  k_spai_long_rows<T><<<grid, kBlock, 0, s>>>(n_long, rows, x, u, prp, pcol, pval, mdiag, skip);
+}
+
 template <typename T>
 void launch_spai_sparse_step(int n, const T* r, T* u, const int32_t* prp, const int32_t* pcol,
-                             const float* pval, const T* mdiag, const T* V, int64_t ldv, int c,
-                             const double* Ginv, double delta, int init, DevState* st, RedBuf rb,
-                             hipStream_t s) {
+                             const float* pval, const T* mdiag, const int32_t* plong, int n_long,
+                             const T* V, int64_t ldv, int c, const double* Ginv, double delta,
+                             int init, DevState* st, RedBuf rb, hipStream_t s) {
   const int grid = stream_grid(n);
+  launch_long_rows<T>(n_long, plong, r, u, prp, pcol, pval, mdiag, st, s);
 #define ISIRA_SPSTEP(CMV)                                                                    \
   k_spai_sparse_step<T, CMV><<<grid, kBlock, 0, s>>>(n, r, u, prp, pcol, pval, mdiag, V, ldv, c, \
                                                      st, rb.partials)
@@ -1239,12 +1278,14 @@ void launch_spai_sparse_step(int n, const T* r, T* u, const int32_t* prp, const 
 }
 template void launch_spai_sparse_step<double>(int, const double*, double*, const int32_t*,
                                               const int32_t*, const float*, const double*,
-                                              const double*, int64_t, int, const double*, double,
-                                              int, DevState*, RedBuf, hipStream_t);
+                                              const int32_t*, int, const double*, int64_t, int,
+                                              const double*, double, int, DevState*, RedBuf,
+                                              hipStream_t);
 template void launch_spai_sparse_step<float>(int, const float*, float*, const int32_t*,
                                              const int32_t*, const float*, const float*,
-                                             const float*, int64_t, int, const double*, double,
-                                             int, DevState*, RedBuf, hipStream_t);
+                                             const int32_t*, int, const float*, int64_t, int,
+                                             const double*, double, int, DevState*, RedBuf,
+                                             hipStream_t);
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_spai_sparse_mv(int n, const T* __restrict__ x,
@@ -1256,27 +1297,29 @@ __global__ __launch_bounds__(kBlock) void k_spai_sparse_mv(int n, const T* __res
                                                            const DevState* skip) {
   if (skip && skip->done) return;
   for (int l = blockIdx.x * kBlock + threadIdx.x; l < n; l += gridDim.x * kBlock) {
+    const int e0 = prp[l], e1 = prp[l + 1];
+    if (e1 - e0 > kSpLongRow) continue;  // summed by k_spai_long_rows
     T yl = mdiag[l] * x[l];
-    const int e1 = prp[l + 1];
-    for (int e = prp[l]; e < e1; ++e) yl += (T)pval[e] * x[pcol[e]];
+    for (int e = e0; e < e1; ++e) yl += (T)pval[e] * x[pcol[e]];
     y[l] = yl;
   }
 }
 
 template <typename T>
 void launch_spai_sparse_mv(int n, const T* x, T* y, const int32_t* prp, const int32_t* pcol,
-                           const float* pval, const T* mdiag, const DevState* skip_if_done,
-                           hipStream_t s) {
+                           const float* pval, const T* mdiag, const int32_t* plong, int n_long,
+                           const DevState* skip_if_done, hipStream_t s) {
+  launch_long_rows<T>(n_long, plong, x, y, prp, pcol, pval, mdiag, skip_if_done, s);
   k_spai_sparse_mv<T><<<stream_grid(n), kBlock, 0, s>>>(n, x, y, prp, pcol, pval, mdiag,
                                                         skip_if_done);
   HIP_LAUNCH_CHECK();
 }
 template void launch_spai_sparse_mv<double>(int, const double*, double*, const int32_t*,
                                             const int32_t*, const float*, const double*,
-                                            const DevState*, hipStream_t);
+                                            const int32_t*, int, const DevState*, hipStream_t);
 template void launch_spai_sparse_mv<float>(int, const float*, float*, const int32_t*,
                                            const int32_t*, const float*, const float*,
-                                           const DevState*, hipStream_t);
+                                           const int32_t*, int, const DevState*, hipStream_t);
 // The partials (sum(p), V-hat^T p) are reduced by the next product's finishing dispatch.
 template <typename T>
 void launch_pcg_update2_learned(int n, const T* y, T* p, const T* Y, int64_t ldv, int c,

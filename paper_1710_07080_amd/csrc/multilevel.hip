@@ -627,6 +627,48 @@ extern "C" int isira_ml_shape(int64_t n, const int32_t* row_ptr, const int32_t* 
   return ISIRA_OK;
 }
 
+// Host-only: level `level` of the same hierarchy as CSR of its off-diagonal weights (the
+// matrix entries are their negatives), its diagonal and its aggregation map into the next
+// level (all -1 on the coarsest).  Level 0 is in the caller's labels with the trimmed
+// vertex's row empty; a coarse level numbers its vertices in the order of their aggregates'
+// first members on the finer level.  With rp_out NULL only *rows and *nnz are set.
+extern "C" int isira_ml_level_matrix(int64_t n, const int32_t* row_ptr, const int32_t* col,
+                                     const double* w, int64_t trim, const isira_ml_options* opt,
+                                     int32_t level, int64_t* rows, int64_t* nnz, int32_t* rp_out,
+                                     int32_t* col_out, double* w_out, double* diag_out,
+                                     int32_t* agg_out) {
+  using namespace isira::ml;
+  if (n < 3 || !row_ptr || !col || !opt || !rows || !nnz) return isira::set_error(ISIRA_E_ARG, "bad argument");
+  if (trim < 0 || trim >= n) return isira::set_error(ISIRA_E_ARG, "trim out of range");
+  if (!(opt->omega > 0.0 && opt->omega < 1.0) || opt->coarse_max < 0 || opt->coarse_max > 2048 ||
+      opt->max_levels < 1 || opt->max_levels > ISIRA_ML_MAX_LEVELS)
+    return isira::set_error(ISIRA_E_ARG, "options out of range");
+  std::vector<int32_t> perm((size_t)n);
+  for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+  std::vector<HostLevel> lev;
+  std::vector<std::vector<int32_t>> aggs;
+  std::vector<HostMats> mats;
+  HostCoarsest co;
+  Params prm{opt->omega, opt->coarse_max, opt->max_levels};
+  const int rc = build_host((int)n, row_ptr, col, w, perm.data(), (int)trim, prm, lev, aggs, mats, co);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)lev.size()) return isira::set_error(ISIRA_E_ARG, "level out of range");
+  const HostLevel& A = lev[level];
+  *rows = A.n;
+  *nnz = (int64_t)A.col.size();
+  if (!rp_out) return ISIRA_OK;
+  if (!col_out || !w_out || !diag_out || !agg_out) return isira::set_error(ISIRA_E_ARG, "NULL output");
+  std::copy(A.rp.begin(), A.rp.end(), rp_out);
+  std::copy(A.col.begin(), A.col.end(), col_out);
+  std::copy(A.w.begin(), A.w.end(), w_out);
+  std::copy(A.diag.begin(), A.diag.end(), diag_out);
+  if (level < (int)aggs.size())
+    std::copy(aggs[level].begin(), aggs[level].end(), agg_out);
+  else
+    std::fill(agg_out, agg_out + A.n, -1);
+  return ISIRA_OK;
+}
+
 namespace isira {
 namespace ml {
 

@@ -30,6 +30,8 @@ struct SpaiWork {
   int32_t* prp = nullptr;   // n + 1
   int32_t* pcol = nullptr;  // pnnz
   float* pval = nullptr;    // pnnz
+  int32_t* plong = nullptr; // rows with more than kSpLongRow kept entries (one wave each)
+  int64_t n_long = 0;
 };
 
 void free_work(SpaiWork& w);

@@ -21,7 +21,9 @@ void free_pruned(SpaiWork& w) {
     dfree(*w.mem, w.prp);
     dfree(*w.mem, w.pcol);
     dfree(*w.mem, w.pval);
+    dfree(*w.mem, w.plong);
   }
+  w.n_long = 0;
   w.pruned = false;
   w.pnnz = 0;
 }
@@ -59,7 +61,7 @@ void apply(SpaiWork& w, const SpmvPlan& plan, const int32_t* rp, const int32_t* 
            const T* x, T* y, int n, int trim, const T* V, int64_t ldv, int c, DevState* st,
            RedBuf rb, hipStream_t s) {
   if (w.pruned) {
-    launch_spai_sparse_mv<T>(n, x, y, w.prp, w.pcol, w.pval, mdiag<T>(w), st, s);
+    launch_spai_sparse_mv<T>(n, x, y, w.prp, w.pcol, w.pval, mdiag<T>(w), w.plong, (int)w.n_long, st, s);
   } else {
     SpmvArgs<T> a = m_args<T>(w, rp, col, x, y, n, trim);
     a.st = st;
@@ -74,7 +76,7 @@ template <typename T>
 void apply_plain(SpaiWork& w, const SpmvPlan& plan, const int32_t* rp, const int32_t* col,
                  const T* x, T* y, int n, int trim, hipStream_t s) {
   if (w.pruned) {
-    launch_spai_sparse_mv<T>(n, x, y, w.prp, w.pcol, w.pval, mdiag<T>(w), nullptr, s);
+    launch_spai_sparse_mv<T>(n, x, y, w.prp, w.pcol, w.pval, mdiag<T>(w), w.plong, (int)w.n_long, nullptr, s);
     return;
   }
   SpmvArgs<T> a = m_args<T>(w, rp, col, x, y, n, trim);
@@ -86,8 +88,8 @@ template <typename T>
 void sparse_step(const SpaiWork& w, int n, const T* r, T* u, const T* V, int64_t ldv, int c,
                  const double* Ginv, double delta, int init, DevState* st, RedBuf rb,
                  hipStream_t s) {
-  launch_spai_sparse_step<T>(n, r, u, w.prp, w.pcol, w.pval, mdiag<T>(w), V, ldv, c, Ginv, delta,
-                             init, st, rb, s);
+  launch_spai_sparse_step<T>(n, r, u, w.prp, w.pcol, w.pval, mdiag<T>(w), w.plong, (int)w.n_long, V,
+                             ldv, c, Ginv, delta, init, st, rb, s);
 }
 template void sparse_step<double>(const SpaiWork&, int, const double*, double*, const double*,
                                   int64_t, int, const double*, double, int, DevState*, RedBuf,

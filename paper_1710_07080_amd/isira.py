@@ -115,7 +115,7 @@ EXPORTS = [
     "isira_laplacian_apply", "isira_laplacian_apply_f32", "isira_time_spmv", "isira_inner_solve",
     "isira_orthonormalize", "isira_orthonormalize_noalloc", "isira_symeig", "isira_symeig_lowest", "isira_spai_nparam", "isira_spai_install",
     "isira_spai_prune", "isira_spai_export", "isira_spai_loss_grad", "isira_adam_step", "isira_ml_default_options",
-    "isira_ml_setup", "isira_ml_get_info", "isira_ml_apply", "isira_ml_shape", "isira_strerror",
+    "isira_ml_setup", "isira_ml_get_info", "isira_ml_apply", "isira_ml_shape", "isira_ml_level_matrix", "isira_strerror",
     "isira_last_error",
 ]
 
@@ -171,6 +171,8 @@ def load() -> ctypes.CDLL:
         "isira_ml_get_info": (i32, [vp, ctypes.POINTER(MlInfo)]),
         "isira_ml_apply": (i32, [vp, i32, vp, vp]),
         "isira_ml_shape": (i32, [i64, vp, vp, vp, i64, ctypes.POINTER(MlOptions), ctypes.POINTER(MlInfo)]),
+        "isira_ml_level_matrix": (i32, [i64, vp, vp, vp, i64, ctypes.POINTER(MlOptions), i32,
+                                        ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp, vp, vp]),
         "isira_strerror": (ctypes.c_char_p, [i32]),
         "isira_last_error": (ctypes.c_char_p, []),
     }
@@ -243,6 +245,34 @@ def ml_shape(g, trim: int, omega: float = 0.9, coarse_max: int = 512, max_levels
                                  None if w is None else w.ctypes.data, int(trim), ctypes.byref(o),
                                  ctypes.byref(inf)))
     return inf.as_dict()
+
+
+def ml_level_matrix(g, trim: int, level: int, omega: float = 0.9, coarse_max: int = 512,
+                    max_levels: int = 24):
+    """Host-only level `level` of the multilevel hierarchy for graph g (caller labels):
+    (scipy CSR of the off-diagonal weights, diagonal, aggregation map into the next level)."""
+    import scipy.sparse as sp
+
+    o = MlOptions()
+    o.omega, o.coarse_max, o.max_levels, o.trim_index = float(omega), int(coarse_max), int(max_levels), int(trim)
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(g.col, dtype=np.int32)
+    w = None if g.w is None else np.ascontiguousarray(g.w, dtype=np.float64)
+    lib = load()
+    rows, nnz = ctypes.c_int64(), ctypes.c_int64()
+    args = (int(g.n), rp.ctypes.data, col.ctypes.data, None if w is None else w.ctypes.data, int(trim),
+            ctypes.byref(o), int(level), ctypes.byref(rows), ctypes.byref(nnz))
+    _check(lib.isira_ml_level_matrix(*args, None, None, None, None, None))
+    m, e = rows.value, nnz.value
+    orp = np.zeros(m + 1, dtype=np.int32)
+    ocol = np.zeros(max(e, 1), dtype=np.int32)
+    ow = np.zeros(max(e, 1))
+    od = np.zeros(m)
+    oagg = np.zeros(m, dtype=np.int32)
+    _check(lib.isira_ml_level_matrix(*args, orp.ctypes.data, ocol.ctypes.data, ow.ctypes.data, od.ctypes.data,
+                                     oagg.ctypes.data))
+    W = sp.csr_matrix((ow[:e], ocol[:e], orp), shape=(m, m))
+    return W, od, oagg
 
 
 def symeig_lowest(H: np.ndarray):

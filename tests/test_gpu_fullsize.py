@@ -19,6 +19,7 @@ import pytest
 import graphgen as gg
 from oracle import isira_oracle as O
 from oracle import multilevel_oracle as ML
+from ml_levels import hierarchy_with_library_matrices
 
 pytestmark = pytest.mark.gpu
 
@@ -119,14 +120,22 @@ def test_fullsize_multilevel_cycle(P, name):
     assert info["connected"] == [ML.connected_count(A) for A in h.A]
     x = np.random.default_rng(6).standard_normal(g.n)
     ref = np.insert(ML.vcycle(h, O.trim(x, i)), i, 0.0)
-    # The coarse matrices are Galerkin sums of many fine weights, added in another order on
-    # each side, so their entries differ in the last few bits; the exact coarsest solve
-    # turns a relative perturbation u of its matrix into up to kappa(A_L) u in the cycle.
+    # The coarsest level is solved exactly: the library applies an explicit inverse formed by
+    # Cholesky, the oracle a sparse direct solve, and either carries an error of about
+    # kappa(A_L) u (4 u kappa allowed).  Against the oracle's cycle over the library's own
+    # level matrices that is the only term besides the cycle's rounding; against the
+    # oracle's own matrices their rounding differences (a few u each, pinned entry by entry on
+    # the CPU) add about as much again through the same solve.
+    hl = hierarchy_with_library_matrices(P, g, i, h, 512)
+    ref_l = np.insert(ML.vcycle(hl, O.trim(x, i)), i, 0.0)
     ev = np.linalg.eigvalsh(h.A[-1].toarray()) if h.A[-1].shape[0] > 1 else np.ones(1)
     kappa = ev[-1] / ev[0]
-    for prec, bound in [(0, 1e-12 + 64 * 2.0 ** -53 * kappa), (1, 3e-5)]:
+    u = 2.0 ** -53
+    for prec, bound, bound_l in [(0, 1e-12 + 8 * u * kappa, 1e-12 + 4 * u * kappa), (1, 3e-5, 3e-5)]:
         y = ctx.ml_apply(torch.as_tensor(x, device="cuda"), prec=prec).cpu().numpy()
         err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
-        print(f"{name} cycle prec={prec}: relative error {err:.2e} (bound {bound:.1e}, coarsest "
-              f"condition {kappa:.2e}), levels {info['rows']}")
-        assert err <= bound
+        err_l = np.linalg.norm(y - ref_l) / np.linalg.norm(ref_l)
+        print(f"{name} cycle prec={prec}: relative error {err:.2e} against the oracle (bound "
+              f"{bound:.1e}, coarsest condition {kappa:.2e}), {err_l:.2e} against the oracle's cycle "
+              f"over the library's matrices (bound {bound_l:.1e}), levels {info['rows']}")
+        assert err <= bound and err_l <= bound_l

@@ -79,6 +79,44 @@ def test_laplacian_apply_fp64(P, name):
     assert inf["delta_default"] == pytest.approx(O.deflation_shift(O.degrees(g)), rel=4e-16 * g.counts().max())
 
 
+def _big_power_law(weighted):
+    # more than 2^20 vertices in degree order (the hub-cached shape) with rows split into
+    # many chunks; weights, when asked for, are a symmetric hash of the edge's end points
+    # mapped to [0.5, 1.5)
+    g = gg.rmat(21, 16, seed=77, device="cpu")
+    if weighted:
+        rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+        a = np.minimum(rows, g.col.astype(np.int64))
+        b = np.maximum(rows, g.col.astype(np.int64))
+        h = (a * 2654435761 + b * 40503) % 1000003
+        g = gg.CSRGraph(g.n, g.row_ptr, g.col, 0.5 + h / 1000003.0, name=g.name + "_w")
+    return g
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_laplacian_apply_large_power_law(P, weighted):
+    """The product on an R-MAT scale-21 graph (1.2 M vertices, hub rows of 100 K entries) in
+    FP64 and FP32 against the oracle's Laplacian, within the dot-product error bounds."""
+    g = _big_power_law(weighted)
+    assert g.n > (1 << 20) and g.counts().max() > 8 * 8192
+    print(f"large power-law product: n={g.n} nnz={g.nnz} weighted={weighted}", flush=True)
+    ctx = P.Context.from_graph(g)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(g.n)
+    ref = O.laplacian_apply(g, x)
+    absL = O.laplacian(g)
+    absL.data = np.abs(absL.data)
+    mag = absL @ np.abs(x)
+    y = ctx.laplacian_apply(_dev(x)).cpu().numpy()
+    bound = (g.counts().max() + 2) * 2.0 ** -53 * 1.01 * mag
+    assert np.all(np.abs(y - ref) <= bound + 1e-300)
+    x32 = x.astype(np.float32)
+    y32 = ctx.laplacian_apply_f32(_dev(x32, torch.float32)).cpu().numpy().astype(np.float64)
+    ref32 = O.laplacian_apply(g, x32.astype(np.float64))
+    bound32 = (g.counts().max() + 4) * 2.0 ** -24 * 1.01 * (absL @ np.abs(x32.astype(np.float64)))
+    assert np.all(np.abs(y32 - ref32) <= bound32)
+
+
 @pytest.mark.parametrize("name", ["grid3d_w", "rmat14", "hubs", "rmat17", "chunglu"])
 def test_laplacian_apply_fp32(P, name):
     g = GRAPHS[name]()

@@ -68,3 +68,60 @@ def test_shape_errors(P):
     with pytest.raises(P.IsiraError) as e:
         P.isira.ml_shape(g, 0, coarse_max=0, max_levels=2)
     assert e.value.code == P.isira.ISIRA_E_PRECOND
+
+
+GALERKIN = [c for c in CASES if c[0] in ("grid3d_w", "rmat14", "rand_w", "star_paths", "chunglu", "rmat12_trim_min")]
+
+
+@pytest.mark.parametrize("name,make,cm,trim", GALERKIN, ids=[c[0] for c in GALERKIN])
+def test_galerkin_levels_match_oracle_entrywise(P, name, make, cm, trim):
+    """Every level's matrix A_{l+1} = P_l^T A_l P_l of the library's set-up against the
+    oracle's, entry by entry: both sum the same fine entries in other orders, so each entry
+    differs by at most 2 (K - 1) u times the sum of the absolute values of its K fine terms
+    (u = 2^-53).  The coarse vertices are matched through the aggregates (same rule, other
+    numbering)."""
+    import scipy.sparse as sp
+
+    g = make()
+    d = O.degrees(g)
+    i = O.trim_index(d) if trim is None else int(np.argmin(d))
+    h = ML.setup(g, i, coarse_max=cm)
+    keep = np.delete(np.arange(g.n), i)
+    pi = keep.copy()  # oracle vertex index -> library vertex index on the current level
+    Aabs = abs(h.A[0]).tocsr()
+    # number of terms summed into each entry: one weight off the diagonal, the row's weights
+    # (all of them, the trimmed vertex's too) on the diagonal
+    K = Aabs.copy()
+    K.data[:] = 1.0
+    K = (K - sp.diags(K.diagonal()) + sp.diags(g.counts()[keep].astype(np.float64))).tocsr()
+    u = 2.0 ** -53
+    worst = 0.0
+    for lvl, A in enumerate(h.A):
+        W, dg, agg = P.isira.ml_level_matrix(g, i, lvl, coarse_max=cm)
+        Alib = (sp.diags(dg) - W).tocsr()[pi][:, pi]
+        diff = abs(Alib - A).tocsr()
+        bound = (2.0 * u * K.multiply(Aabs)).tocsr()
+        # entries outside the oracle's pattern must be exactly zero
+        outside = diff - diff.multiply(bound > 0)
+        assert outside.count_nonzero() == 0 or abs(outside).max() == 0.0, (name, lvl)
+        ratio = diff.multiply(bound > 0)
+        if ratio.nnz:
+            b = bound[ratio.nonzero()]
+            r = np.asarray(ratio[ratio.nonzero()]).ravel() / np.asarray(b).ravel()
+            worst = max(worst, float(r.max()))
+            assert r.max() <= 1.0, (name, lvl, float(r.max()))
+        if lvl + 1 < len(h.A):
+            agg_o = h.agg[lvl]
+            nxt = -np.ones(h.A[lvl + 1].shape[0], dtype=np.int64)
+            mem = np.flatnonzero(agg_o >= 0)
+            lib_ids = agg[pi[mem]]
+            assert np.all(lib_ids >= 0)
+            nxt[agg_o[mem]] = lib_ids
+            # one library aggregate per oracle aggregate, and the same members
+            assert np.all(nxt >= 0) and np.unique(nxt).size == nxt.size
+            assert np.array_equal(nxt[agg_o[mem]], agg[pi[mem]])
+            Pm = h.P[lvl]
+            Aabs = (Pm.T @ Aabs @ Pm).tocsr()
+            K = (Pm.T @ K @ Pm).tocsr()
+            pi = nxt
+    print(f"{name}: {len(h.A)} levels, largest entry difference / its rounding bound {worst:.3f}")
