@@ -71,17 +71,25 @@ PRUNE_TAU = 0.02
 # HBM traffic of the dominant kernel from rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE),
 # with the sources it was measured on; it is reported only while those sources are unchanged.
 PROFILES = os.path.join(HERE, "profiles")
-KERNEL_SOURCES = [os.path.join(HERE, "paper_1710_07080_amd", "csrc", f)
-                  for f in ("kernels.hip", "internal.h", "api.hip")]
+CSRC = os.path.join(HERE, "paper_1710_07080_amd", "csrc")
+# The product's sources: kernels.hip up to the PCG updates (the product and the reduction
+# helpers it uses), internal.h, and the relabelling and work-unit plan of api.hip.
+PRODUCT_SOURCES = [("kernels.hip", None, "// ------------------------------------------------------------------ PCG updates"),
+                   ("internal.h", None, None),
+                   ("api.hip", "// Power-law test on the degree-sorted labels", "void isira::free_spmv_plan")]
 
 
 def sources_digest():
+    """sha256 prefix of the product's sources (a traffic record is valid while they match)."""
     import hashlib
 
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
-        with open(path, "rb") as f:
-            h.update(f.read())
+    for name, begin, end in PRODUCT_SOURCES:
+        with open(os.path.join(CSRC, name)) as f:
+            text = f.read()
+        a = text.index(begin) if begin else 0
+        b = text.index(end) if end else len(text)
+        h.update(text[a:b].encode())
     return h.hexdigest()[:16]
 
 

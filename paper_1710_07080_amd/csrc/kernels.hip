@@ -1808,10 +1808,93 @@ __global__ __launch_bounds__(THREADS) void k_tsgemm_mfma(int n, double* U, int64
   }
 }
 
+// More than four 16-column tiles: the tiles are shared out among G waves per 16-row tile
+// (NTW tiles each, so that accumulators and S fragments stay within the registers of a
+// 1024-thread workgroup); the G waves of a row tile sit in one workgroup, and a barrier
+// between the multiplications and the stores keeps every read of U before any write.
+template <int NTW, int G>
+__global__ __launch_bounds__(1024) void k_tsgemm_mfma_g(int n, double* U, int64_t ld, int k,
+                                                        const double* __restrict__ St, int q) {
+  extern __shared__ double sS[];
+  constexpr int QP = NTW * G * 16;
+  constexpr int RT = 16 / G;  // row tiles per workgroup and round (16 waves, RT * G used)
+  const int kp = (k + 3) & ~3;
+  for (int e = threadIdx.x; e < kp * QP; e += 1024) {
+    const int i = e / QP, j = e - i * QP;
+    sS[e] = (i < k && j < q) ? St[(int64_t)i * q + j] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int rt = wave / G, cg = wave - rt * G;
+  const bool active = rt < RT;
+  const int ntiles = (n + 15) >> 4;
+  for (int base = blockIdx.x * RT; base < ntiles; base += gridDim.x * RT) {
+    const int t = base + rt;
+    const int row = t * 16 + c;
+    const bool rok = active && t < ntiles && row < n;
+    const double* ur = U + row;
+    dbl4 acc[NTW];
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+    if (active && t < ntiles) {
+      double bc[4], bn[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int i = 4 * st + g;
+        bc[st] = (rok && i < k) ? ur[(int64_t)i * ld] : 0.0;
+      }
+      for (int i0 = 0; i0 < kp; i0 += 16) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int i = i0 + 16 + 4 * st + g;
+          bn[st] = (rok && i < k) ? ur[(int64_t)i * ld] : 0.0;
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          if (i0 + 4 * st < kp) {
+            const double* srow = sS + (i0 + 4 * st + g) * QP + cg * NTW * 16 + c;
+#pragma unroll
+            for (int u = 0; u < NTW; ++u)
+              acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(srow[u * 16], bc[st], acc[u], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) bc[st] = bn[st];
+      }
+    }
+    __syncthreads();  // every wave of these row tiles has read its rows of U
+    if (rok) {
+#pragma unroll
+      for (int u = 0; u < NTW; ++u)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = (cg * NTW + u) * 16 + 4 * j + g;
+          if (col < q) U[row + (int64_t)col * ld] = acc[u][j];
+        }
+    }
+  }
+}
+
+template <int NTW, int G>
+static void launch_tsgemm_mfma_g(int n, double* U, int64_t ld, int k, const double* St, int q,
+                                 size_t lds, hipStream_t s) {
+  static bool lds_raised = false;
+  if (!lds_raised) {
+    (void)hipFuncSetAttribute((const void*)k_tsgemm_mfma_g<NTW, G>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTsMfmaLds);
+    lds_raised = true;
+  }
+  constexpr int RT = 16 / G;
+  int grid = (((n + 15) >> 4) + RT - 1) / RT;
+  if (grid > 1024) grid = 1024;
+  k_tsgemm_mfma_g<NTW, G><<<grid, 1024, lds, s>>>(n, U, ld, k, St, q);
+}
+
 template <int NT>
 static void launch_tsgemm_mfma_nt(int n, double* U, int64_t ld, int k, const double* St, int q,
                                   size_t lds, hipStream_t s) {
-  constexpr int TH = NT <= 4 ? 1024 : 512;  // 16 NT registers per lane: accumulators and S
+  constexpr int TH = 1024;  // up to four tiles: accumulators and S fragments fit
   static bool lds_raised = false;
   if (!lds_raised) {
     (void)hipFuncSetAttribute((const void*)k_tsgemm_mfma<NT, TH>,
@@ -1826,21 +1909,22 @@ static void launch_tsgemm_mfma_nt(int n, double* U, int64_t ld, int k, const dou
 void launch_tsgemm_inplace(int n, double* U, int64_t ld, int k, const double* St, int q,
                            hipStream_t s) {
   const int nt = (q + 15) / 16;
-  const size_t lds = (size_t)((k + 3) & ~3) * nt * 16 * sizeof(double);
+  // tiles covered: nt itself up to 4; else NTW tiles for each of G waves per row tile
+  const int ntw = nt <= 4 ? nt : ((nt == 5 || nt == 6 || nt == 9) ? 3 : 4);
+  const int grp = nt <= 4 ? 1 : (nt <= 8 ? 2 : 3);
+  const size_t lds = (size_t)((k + 3) & ~3) * ntw * grp * 16 * sizeof(double);
   if (lds <= kTsMfmaLds) {
     switch (nt) {
       case 1: launch_tsgemm_mfma_nt<1>(n, U, ld, k, St, q, lds, s); break;
       case 2: launch_tsgemm_mfma_nt<2>(n, U, ld, k, St, q, lds, s); break;
       case 3: launch_tsgemm_mfma_nt<3>(n, U, ld, k, St, q, lds, s); break;
       case 4: launch_tsgemm_mfma_nt<4>(n, U, ld, k, St, q, lds, s); break;
-      case 5: launch_tsgemm_mfma_nt<5>(n, U, ld, k, St, q, lds, s); break;
-      case 6: launch_tsgemm_mfma_nt<6>(n, U, ld, k, St, q, lds, s); break;
-      case 7: launch_tsgemm_mfma_nt<7>(n, U, ld, k, St, q, lds, s); break;
-      case 8: launch_tsgemm_mfma_nt<8>(n, U, ld, k, St, q, lds, s); break;
-      case 9: launch_tsgemm_mfma_nt<9>(n, U, ld, k, St, q, lds, s); break;
-      case 10: launch_tsgemm_mfma_nt<10>(n, U, ld, k, St, q, lds, s); break;
-      case 11: launch_tsgemm_mfma_nt<11>(n, U, ld, k, St, q, lds, s); break;
-      default: launch_tsgemm_mfma_nt<12>(n, U, ld, k, St, q, lds, s); break;
+      case 5:
+      case 6: launch_tsgemm_mfma_g<3, 2>(n, U, ld, k, St, q, lds, s); break;
+      case 7:
+      case 8: launch_tsgemm_mfma_g<4, 2>(n, U, ld, k, St, q, lds, s); break;
+      case 9: launch_tsgemm_mfma_g<3, 3>(n, U, ld, k, St, q, lds, s); break;
+      default: launch_tsgemm_mfma_g<4, 3>(n, U, ld, k, St, q, lds, s); break;
     }
     HIP_LAUNCH_CHECK();
     return;
