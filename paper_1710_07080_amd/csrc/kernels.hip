@@ -249,9 +249,9 @@ __device__ __forceinline__ T edge_val(const void* vals, int j) {
   if constexpr (VM == kUnitNeg) {
     return T(1);
   } else if constexpr (VM == kF64Neg || VM == kF64Pos) {
-    return (T)((const double*)vals)[j];
+    return (T)__builtin_nontemporal_load((const double*)vals + j);
   } else {
-    return (T)((const float*)vals)[j];
+    return (T)__builtin_nontemporal_load((const float*)vals + j);
   }
 }
 
@@ -340,7 +340,8 @@ __device__ __forceinline__ void gather_slots(const int (&ci)[PT], const T* __res
 // coalesced batch, gathers x for all its nonzeros and stages the products in LDS; each row
 // is then summed from LDS by G lanes into a row sum in LDS, and every thread finishes the
 // rows it loaded (coalesced stores).  A chunk unit of a long row sums its nonzeros into one
-// partial.  Two shapes: 256 threads / 2048-nonzero units (8 workgroups per CU), and, for
+// partial.  Column indices and edge weights, read once per launch, are loaded
+// non-temporally so that they do not displace lines of x from the L2.  Two shapes: 256 threads / 2048-nonzero units (8 workgroups per CU), and, for
 // power-law graphs, 1024 threads / 8192-nonzero units with x of the HUB highest-degree
 // columns (the first HUB labels after relabelling) staged once per workgroup in LDS, so
 // that those gathers never reach L2.  A thread's slots of the next unit are loaded as soon
@@ -399,7 +400,7 @@ __global__ __launch_bounds__(NT) void k_spmv(SpmvArgs<T> a, const int4* __restri
     for (int k = 0; k < PT; ++k) {
       const int e = d.y + tid + k * NT;
       const bool in = e < d.z;
-      sl.ci[k] = in ? col[e] : -1;
+      sl.ci[k] = in ? __builtin_nontemporal_load(col + e) : -1;
       sl.v[k] = in ? edge_val<VM, T>(a.vals, e) : T(0);
     }
     const int nr = d.w >= 0 ? (d.w >> 8) : -1;

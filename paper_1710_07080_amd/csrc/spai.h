@@ -19,6 +19,7 @@ struct SpaiWork {
   float* agg = nullptr;      // n x H  neighbour mean of h
   float* sdiag = nullptr;    // n      diagonal head pre-activation
   int32_t* rowidx = nullptr; // nnz    row of each stored entry
+  float* nm_part = nullptr;  // neighbour mean: H sums per piece of a long row
   float* scratch = nullptr;  // training scratch
   size_t scratch_elems = 0;
   double* gpart = nullptr;   // gradient partials

@@ -7,7 +7,7 @@ namespace spai {
 
 void free_work(SpaiWork& w) {
   if (!w.mem) return;  // nothing was ever allocated
-  for (float** p : {&w.diag32, &w.offd, &w.feat, &w.t1, &w.h, &w.agg, &w.sdiag, &w.scratch})
+  for (float** p : {&w.diag32, &w.offd, &w.feat, &w.t1, &w.h, &w.agg, &w.sdiag, &w.scratch, &w.nm_part})
     dfree(*w.mem, *p);
   dfree(*w.mem, w.diag64);
   dfree(*w.mem, w.rowidx);

@@ -30,6 +30,9 @@ constexpr int oW1 = 0, ob1 = oW1 + H * F, oW2 = ob1 + H, ob2 = oW2 + H * H, owd 
 constexpr int NV_VERT = obd + 1;      // gradients reduced over vertices: params [0, oWe)
 constexpr int NV_EDGE = NP - oWe;     // gradients reduced over edges:    params [oWe, NP)
 constexpr float kEps = 0.05f;
+// the neighbour mean sums rows longer than kNmChunk entries in pieces of kNmChunk entries
+constexpr int kNmChunk = 1024;
+static int64_t nm_part_elems(int64_t nnz) { return 2 * ((nnz + kNmChunk - 1) / kNmChunk) * H; }
 static_assert(NV_VERT == oWe, "layout");
 static_assert(NV_EDGE <= kSpaiRedValues && NV_VERT <= kSpaiRedValues && 64 <= kSpaiRedValues,
               "gradient reductions must fit the partials buffer");
@@ -142,8 +145,17 @@ __global__ __launch_bounds__(kBlock) void k_vertex_mlp(int n, const float* __res
   }
 }
 
-// a_i = mean_j h_j: H lanes per vertex, 64/H vertices per wave.  With scale_by_count = 0 it
-// computes the plain gather-sum of x_j / n_j (used by the backward pass).
+// a_i = mean_j h_j.  With divide_by_source = 1 it computes the plain gather-sum of x_j / n_j
+// (used by the backward pass).  Rows of at most kNmChunk entries: H lanes per vertex, 64/H
+// vertices per wave, four entries' loads issued together and summed in entry order.  Longer
+// rows are skipped here and summed by k_nm_pieces + k_nm_long.
+__device__ __forceinline__ float nm_term(const int32_t* __restrict__ rp,
+                                         const float* __restrict__ x, int c, int k,
+                                         int divide_by_source) {
+  const float v = x[(size_t)c * H + k];
+  return divide_by_source ? v / (float)(rp[c + 1] - rp[c]) : v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_neighbour_mean(int n, const int32_t* __restrict__ rp,
                                                            const int32_t* __restrict__ col,
                                                            const float* __restrict__ x,
@@ -154,14 +166,119 @@ __global__ __launch_bounds__(kBlock) void k_neighbour_mean(int n, const int32_t*
   const int nslots = (gridDim.x * kBlock) / H;
   for (int i = slot; i < n; i += nslots) {
     const int b = rp[i], e = rp[i + 1];
+    if (e - b > kNmChunk) continue;
     float s = 0.0f;
-    for (int j = b; j < e; ++j) {
-      const int c = col[j];
-      const float v = x[(size_t)c * H + k];
-      s += divide_by_source ? v / (float)(rp[c + 1] - rp[c]) : v;
+    int j = b;
+    for (; j + 4 <= e; j += 4) {
+      const int c0 = col[j], c1 = col[j + 1], c2 = col[j + 2], c3 = col[j + 3];
+      const float v0 = nm_term(rp, x, c0, k, divide_by_source);
+      const float v1 = nm_term(rp, x, c1, k, divide_by_source);
+      const float v2 = nm_term(rp, x, c2, k, divide_by_source);
+      const float v3 = nm_term(rp, x, c3, k, divide_by_source);
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; j < e; ++j) s += nm_term(rp, x, col[j], k, divide_by_source);
+    out[(size_t)i * H + k] = divide_by_source ? s : s / (float)(e - b);
+  }
+}
+
+// Long rows (more than kNmChunk entries), first pass.  Stored entries are cut into chunks of
+// kNmChunk; a chunk meets at most two long rows (one holding its first entry, one holding
+// its last), since a long row cannot lie inside one chunk.  One wave per chunk: four groups
+// of H lanes take every fourth entry of each long piece, the groups' sums are combined, and
+// the piece's H sums go to part[(2 q + p) H ...] (p = 0: the row of the first entry, p = 1:
+// the row of the last entry when it is another row).
+__global__ __launch_bounds__(kBlock) void k_nm_pieces(int64_t nnz, const int32_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col,
+                                                      const int32_t* __restrict__ rowidx,
+                                                      const float* __restrict__ x,
+                                                      float* __restrict__ part,
+                                                      int divide_by_source) {
+  const int lane = threadIdx.x & 63, k = lane % H, g = lane / H;
+  constexpr int G = 64 / H;
+  const int64_t nch = (nnz + kNmChunk - 1) / kNmChunk;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  for (int64_t q = wave; q < nch; q += nwaves) {
+    const int64_t j0 = q * kNmChunk;
+    const int64_t j1 = (j0 + kNmChunk < nnz) ? j0 + kNmChunk : nnz;
+    const int r0 = rowidx[j0], r1 = rowidx[j1 - 1];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int r = p ? r1 : r0;
+      if (p && r1 == r0) break;
+      if (rp[r + 1] - rp[r] <= kNmChunk) continue;
+      const int64_t a = rp[r] > j0 ? rp[r] : j0;
+      const int64_t e = rp[r + 1] < j1 ? rp[r + 1] : j1;
+      float s = 0.0f;
+      int64_t j = a + g;
+      for (; j + 3 * G < e; j += 4 * G) {  // four entries' loads in flight, summed in order
+        const int c0 = col[j], c1 = col[j + G], c2 = col[j + 2 * G], c3 = col[j + 3 * G];
+        const float v0 = nm_term(rp, x, c0, k, divide_by_source);
+        const float v1 = nm_term(rp, x, c1, k, divide_by_source);
+        const float v2 = nm_term(rp, x, c2, k, divide_by_source);
+        const float v3 = nm_term(rp, x, c3, k, divide_by_source);
+        s += v0;
+        s += v1;
+        s += v2;
+        s += v3;
+      }
+      for (; j < e; j += G) s += nm_term(rp, x, col[j], k, divide_by_source);
+#pragma unroll
+      for (int o = H; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+      if (g == 0) part[((size_t)(2 * q + p)) * H + k] = s;
+    }
+  }
+}
+
+// Long rows, second pass: a row's H sums are its pieces' sums in chunk order (a thread per
+// row and lane k of H; rows of at most kNmChunk entries are left to k_neighbour_mean).
+__global__ __launch_bounds__(kBlock) void k_nm_long(int n, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ rowidx,
+                                                    const float* __restrict__ part,
+                                                    float* __restrict__ out,
+                                                    int divide_by_source) {
+  const int k = threadIdx.x % H;
+  const int slot = (blockIdx.x * kBlock + threadIdx.x) / H;
+  const int nslots = (gridDim.x * kBlock) / H;
+  for (int i = slot; i < n; i += nslots) {
+    const int b = rp[i], e = rp[i + 1];
+    if (e - b <= kNmChunk) continue;
+    const int q0 = b / kNmChunk, q1 = (e - 1) / kNmChunk;
+    float s = 0.0f;
+    int q = q0;
+    for (; q + 4 <= q1 + 1; q += 4) {  // four pieces' loads in flight, summed in chunk order
+      float v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int pp = rowidx[(size_t)(q + t) * kNmChunk] == i ? 0 : 1;
+        v[t] = part[((size_t)(2 * (q + t) + pp)) * H + k];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) s += v[t];
+    }
+    for (; q <= q1; ++q) {
+      const int pp = rowidx[(size_t)q * kNmChunk] == i ? 0 : 1;
+      s += part[((size_t)(2 * q + pp)) * H + k];
     }
     out[(size_t)i * H + k] = divide_by_source ? s : s / (float)(e - b);
   }
+}
+
+// out_i for every row: short rows by k_neighbour_mean, long rows by pieces of kNmChunk
+static void neighbour_mean(const SpaiWork& w, int n, int64_t nnz, const int32_t* rp,
+                           const int32_t* col, const float* x, float* out, int divide_by_source,
+                           hipStream_t s) {
+  k_neighbour_mean<<<grid_for(n, kBlock / H, 8192), kBlock, 0, s>>>(n, rp, col, x, out,
+                                                                    divide_by_source);
+  const int64_t nch = (nnz + kNmChunk - 1) / kNmChunk;
+  k_nm_pieces<<<grid_for(nch, kBlock / 64, 8192), kBlock, 0, s>>>(nnz, rp, col, w.rowidx, x,
+                                                                  w.nm_part, divide_by_source);
+  k_nm_long<<<grid_for(n, kBlock / H, 8192), kBlock, 0, s>>>(n, rp, w.rowidx, w.nm_part, out,
+                                                             divide_by_source);
 }
 
 __global__ __launch_bounds__(kBlock) void k_diag_head(int n, const float* __restrict__ h,
@@ -692,7 +809,8 @@ int ensure(SpaiWork& w, int64_t n, int64_t nnz) {
   int rc;
   if ((rc = dalloc(m, &w.diag32, n)) || (rc = dalloc(m, &w.diag64, n)) || (rc = dalloc(m, &w.offd, nnz)) ||
       (rc = dalloc(m, &w.feat, n * F)) || (rc = dalloc(m, &w.t1, n * H)) || (rc = dalloc(m, &w.h, n * H)) ||
-      (rc = dalloc(m, &w.agg, n * H)) || (rc = dalloc(m, &w.sdiag, n)) || (rc = dalloc(m, &w.rowidx, nnz))) {
+      (rc = dalloc(m, &w.agg, n * H)) || (rc = dalloc(m, &w.sdiag, n)) || (rc = dalloc(m, &w.rowidx, nnz)) ||
+      (rc = dalloc(m, &w.nm_part, nm_part_elems(nnz)))) {
     free_work(w);
     return rc;
   }
@@ -702,7 +820,8 @@ int ensure(SpaiWork& w, int64_t n, int64_t nnz) {
 // bytes of the buffers ensure() allocates
 size_t work_bytes(int64_t n, int64_t nnz) {
   return dev_round(n * 4) + dev_round(n * 8) + dev_round(nnz * 4) + dev_round(n * F * 4) +
-         3 * dev_round(n * H * 4) + dev_round(n * 4) + dev_round(nnz * 4);
+         3 * dev_round(n * H * 4) + dev_round(n * 4) + dev_round(nnz * 4) +
+         dev_round(nm_part_elems(nnz) * 4);
 }
 
 static int scratch(SpaiWork& w, size_t elems, float** out) {
@@ -728,7 +847,7 @@ int forward(SpaiWork& w, const int32_t* rp, const int32_t* col, const void* wts,
   k_features<<<gw, kBlock, 0, s>>>(n, rp, col, deg, trim, sigma, w.feat);
   const int gv = grid_for(n, kBlock, 2048);
   k_vertex_mlp<<<gv, kBlock, 0, s>>>(n, w.feat, params, w.t1, w.h);
-  k_neighbour_mean<<<grid_for(n, kBlock / H, 8192), kBlock, 0, s>>>(n, rp, col, w.h, w.agg, 0);
+  neighbour_mean(w, n, nnz, rp, col, w.h, w.agg, 0, s);
   k_diag_head<<<gv, kBlock, 0, s>>>(n, w.h, w.agg, deg, sigma, trim, params, w.sdiag, w.diag32,
                                     w.diag64);
   k_edge_values<<<grid_for(nnz, kBlock, 8192), kBlock, 0, s>>>(nnz, w.rowidx, rp, col, wts, wdt,
@@ -786,7 +905,7 @@ int loss_grad(SpaiWork& w, const int32_t* rp, const int32_t* col, const void* wt
   const int gv = grid_for(n, kBlock, 2048);
   k_vertex_backward1<<<gv, kBlock, 0, s>>>(n, S, Gt, Rt, cM, w.sdiag, deg, sigma, trim, dh_edge,
                                            params, ds, dh, da);
-  k_neighbour_mean<<<grid_for(n, kBlock / H, 8192), kBlock, 0, s>>>(n, rp, col, da, dagg, 1);
+  neighbour_mean(w, n, nnz, rp, col, da, dagg, 1, s);
   k_vertex_backward2<<<gv, kBlock, 0, s>>>(n, dh, dagg, w.h, w.t1, params, dpre2, dpre1);
   k_vertex_param_grad<<<grid_for(n, kRT, kSpaiRedGrid), kBlock, 0, s>>>(n, w.feat, w.t1, w.h, w.agg, ds,
                                                                dpre1, dpre2, rb.partials,

@@ -33,6 +33,8 @@ GRAPHS = {
     "rmat12": lambda: gg.rmat(12, 8, seed=21),
     "grid3d_w": lambda: gg.grid3d(10, 9, 8, weights=(0.5, 1.5), seed=3),
     "hubs": lambda: gg.chung_lu(6000, 2.1, 12.0, seed=8),
+    # 15 rows longer than the neighbour mean's 1024-entry pieces, the longest (3638) in 4-5
+    "rmat14_long_rows": lambda: gg.rmat(14, 16, seed=23),
 }
 
 
@@ -61,7 +63,7 @@ def test_forward_matches_oracle(P, name):
     assert np.all(rowsum[mask] < diag[mask])
 
 
-@pytest.mark.parametrize("name", ["rmat12", "grid3d_w"])
+@pytest.mark.parametrize("name", ["rmat12", "grid3d_w", "rmat14_long_rows"])
 def test_loss_and_gradient_match_oracle(P, name):
     g = GRAPHS[name]()
     ctx = P.Context.from_graph(g)
