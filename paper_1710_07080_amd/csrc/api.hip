@@ -239,13 +239,13 @@ struct isira_ctx {
 };
 
 // Power-law test on the degree-sorted labels: at least a quarter of the gathers hit the
-// kHubX64 highest-degree vertices (the hub-cached product shape is then used).
+// kHubTestCols highest-degree vertices (the hub-cached product shape is then used).
 static bool power_law(int64_t n, const int32_t* rp, const int32_t* col,
                       const std::vector<int32_t>& rank) {
-  if (n <= 4 * (int64_t)kHubX64) return false;
+  if (n <= 4 * (int64_t)kHubTestCols) return false;
   int64_t hits = 0;
   const int64_t nnz = rp[n];
-  for (int64_t j = 0; j < nnz; ++j) hits += rank[col[j]] < kHubX64;
+  for (int64_t j = 0; j < nnz; ++j) hits += rank[col[j]] < kHubTestCols;
   return (double)hits >= 0.25 * (double)nnz;
 }
 
@@ -292,13 +292,13 @@ static void rcm_order(int64_t n, const int32_t* rp, const int32_t* col,
 // order): a row longer than the unit size is cut into chunks; runs of the other rows are
 // packed greedily, in order, into stream units of at most unit-size nonzeros and a row
 // limit.  A stream unit sums each row with G lanes, G the smallest power of two >=
-// (longest row) / 8, capped at 64.  Matrices whose gathers concentrate on the first kHubX64
+// (longest row) / 8, capped at 64.  Matrices whose gathers concentrate on the first kHubTestCols
 // columns (the highest-degree vertices after relabelling) use the hub-cached shape.
 int isira::build_spmv_plan(DevMem& mem, int n, const int32_t* rp, const int32_t* col, SpmvPlan& P) {
   const int64_t nnz = rp[n];
   int64_t hits = 0;
-  for (int64_t j = 0; j < nnz; ++j) hits += col[j] < kHubX64;
-  P.hub = (n > 4 * kHubX64 && (double)hits >= 0.25 * (double)nnz) ? 1 : 0;
+  for (int64_t j = 0; j < nnz; ++j) hits += col[j] < kHubTestCols;
+  P.hub = (n > 4 * kHubTestCols && (double)hits >= 0.25 * (double)nnz) ? 1 : 0;
   const int unnz = P.hub ? kHubUnitNnz : kUnitNnz;
   const int urows = P.hub ? kHubUnitRows : kUnitRows;
   const int chunk = unnz;  // nonzeros per piece of a long row

@@ -66,19 +66,27 @@ constexpr int kSpmvGrid = 2048;       // max workgroups of the persistent SpMV g
 #endif
 constexpr int kUnitNnz = ISIRA_UNIT_NNZ;    // nonzeros per SpMV unit (stream unit or long-row chunk)
 constexpr int kUnitRows = ISIRA_UNIT_ROWS;  // rows per stream unit at most
-// hub-cached shape for power-law graphs (one 1024-thread workgroup per CU)
-constexpr int kHubThreads = 1024;
+// hub-cached shape for power-law graphs: two 512-thread workgroups per CU, each with x of
+// the highest-degree labels in LDS (about 78 KB of LDS per workgroup in either precision)
+#ifndef ISIRA_HUB_THREADS
+#define ISIRA_HUB_THREADS 512
+#define ISIRA_HUB_GRID 512
+#endif
+constexpr int kHubThreads = ISIRA_HUB_THREADS;
 #ifndef ISIRA_HUB_UNNZ
-#define ISIRA_HUB_UNNZ 8192
-#define ISIRA_HUB_UROWS 2048
-#define ISIRA_HUB_X64 8192
-#define ISIRA_HUB_X32 24576
+#define ISIRA_HUB_UNNZ 4096
+#define ISIRA_HUB_UROWS 1024
+#define ISIRA_HUB_X64 4352
+#define ISIRA_HUB_X32 13312
 #endif
 constexpr int kHubUnitNnz = ISIRA_HUB_UNNZ;
 constexpr int kHubUnitRows = ISIRA_HUB_UROWS;
 constexpr int kHubX64 = ISIRA_HUB_X64;  // FP64 x entries staged in LDS
 constexpr int kHubX32 = ISIRA_HUB_X32;  // FP32 x entries staged in LDS
-constexpr int kHubGrid = 256;
+constexpr int kHubGrid = ISIRA_HUB_GRID;
+// the hub-cached shape is chosen when a quarter of the gathers hit the kHubTestCols
+// highest-degree labels
+constexpr int kHubTestCols = 8192;
 constexpr int kMaxC = ISIRA_MAX_K;     // deflation columns in the inner solve
 constexpr int kTile = 512;             // rows per tile of the column-dot kernels
 constexpr int kMaxCols = 2 * ISIRA_MAX_BASIS + 2;  // columns of one multi-dot

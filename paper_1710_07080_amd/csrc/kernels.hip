@@ -244,14 +244,24 @@ struct SplitInfo {
   int32_t nslots;
 };
 
-template <int VM, typename T>
+// a load of data read once per launch: non-temporal when NT
+template <bool NT, typename P>
+__device__ __forceinline__ P stream_ld(const P* p) {
+  if constexpr (NT) {
+    return __builtin_nontemporal_load(p);
+  } else {
+    return *p;
+  }
+}
+
+template <int VM, typename T, bool NT>
 __device__ __forceinline__ T edge_val(const void* vals, int j) {
   if constexpr (VM == kUnitNeg) {
     return T(1);
   } else if constexpr (VM == kF64Neg || VM == kF64Pos) {
-    return (T)__builtin_nontemporal_load((const double*)vals + j);
+    return (T)stream_ld<NT>((const double*)vals + j);
   } else {
-    return (T)__builtin_nontemporal_load((const float*)vals + j);
+    return (T)stream_ld<NT>((const float*)vals + j);
   }
 }
 
@@ -340,11 +350,14 @@ __device__ __forceinline__ void gather_slots(const int (&ci)[PT], const T* __res
 // coalesced batch, gathers x for all its nonzeros and stages the products in LDS; each row
 // is then summed from LDS by G lanes into a row sum in LDS, and every thread finishes the
 // rows it loaded (coalesced stores).  A chunk unit of a long row sums its nonzeros into one
-// partial.  Column indices and edge weights, read once per launch, are loaded
-// non-temporally so that they do not displace lines of x from the L2.  Two shapes: 256 threads / 2048-nonzero units (8 workgroups per CU), and, for
-// power-law graphs, 1024 threads / 8192-nonzero units with x of the HUB highest-degree
-// columns (the first HUB labels after relabelling) staged once per workgroup in LDS, so
-// that those gathers never reach L2.  A thread's slots of the next unit are loaded as soon
+// partial.  Two shapes: 256 threads / 2048-nonzero units (8 workgroups per CU), and, for
+// power-law graphs, 512 threads / 4096-nonzero units (2 workgroups per CU) with x of the
+// HUB highest-degree columns (the first HUB labels after relabelling) staged once per
+// workgroup in LDS, so that those gathers never reach L2.  In the hub shape, column
+// indices and edge weights, read once per launch, are loaded non-temporally so that they
+// do not displace lines of x from the L2 (the stream shape keeps ordinary loads: its
+// matrix can stay in the memory-side cache between launches, which non-temporal loads
+// bypass).  A thread's slots of the next unit are loaded as soon
 // as the current unit is finished.  TAG only separates the symbol of the bandwidth probe
 // (isira_time_spmv) from the solver's launches in profiler summaries.
 template <typename T, int VM, int TAG, int NT, int UNNZ, int UROWS, int HUB>
@@ -352,6 +365,7 @@ __global__ __launch_bounds__(NT) void k_spmv(SpmvArgs<T> a, const int4* __restri
                                              int n_units, double* partials,
                                              double* __restrict__ chunk_part) {
   if (a.check_done && a.st->done) return;
+  constexpr bool kNT = HUB > 0;  // non-temporal column and weight loads (see above)
   constexpr int PT = UNNZ / NT;           // nonzeros per thread and unit
   constexpr int RPT = (UROWS + NT) / NT;  // row pointers per thread (UROWS + 1 entries)
   constexpr int RRT = UROWS / NT;         // rows finished per thread
@@ -400,8 +414,8 @@ __global__ __launch_bounds__(NT) void k_spmv(SpmvArgs<T> a, const int4* __restri
     for (int k = 0; k < PT; ++k) {
       const int e = d.y + tid + k * NT;
       const bool in = e < d.z;
-      sl.ci[k] = in ? __builtin_nontemporal_load(col + e) : -1;
-      sl.v[k] = in ? edge_val<VM, T>(a.vals, e) : T(0);
+      sl.ci[k] = in ? stream_ld<kNT>(col + e) : -1;
+      sl.v[k] = in ? edge_val<VM, T, kNT>(a.vals, e) : T(0);
     }
     const int nr = d.w >= 0 ? (d.w >> 8) : -1;
 #pragma unroll

@@ -1,7 +1,8 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
 
-Every case is seeded; sizes span several tiles, ragged tails, split hub rows (> 4096
-nonzeros) and rows handled by a whole workgroup (1024-4096 nonzeros).
+Every case is seeded; sizes span several tiles, ragged tails, rows split into chunks (longer
+than a work unit of the product: 2048 nonzeros, 4096 in the hub-cached shape) and rows
+summed by a whole workgroup.
 """
 import math
 
@@ -31,8 +32,9 @@ def _dev(a, dtype=torch.float64):
 
 
 def _hub_graph():
-    # a hub of degree 9000 (split into 3 chunks), a few rows of 1024-4096 nonzeros, and
-    # a random sparse remainder -- every SpMV row class at once
+    # a hub of degree 9000 (split into 5 chunks of the 2048-nonzero units), rows of about
+    # 1500 and 2000 nonzeros (one unit each), and a random sparse remainder -- every SpMV
+    # row class of the stream shape at once
     n = 12000
     rng = np.random.default_rng(77)
     u = [np.zeros(9000, dtype=np.int64), np.full(2000, 1), np.full(1500, 2)]
@@ -53,7 +55,8 @@ GRAPHS = {
     "hubs": _hub_graph,
     "star": lambda: gg.star_graph(5000),
     "path": lambda: gg.path_graph(1001),
-    # n > 4 * 10240 with hub-concentrated gathers: the hub-cached SpMV shape
+    # n > 4 * 8192 with a quarter of the gathers on the 8192 highest-degree labels: the
+    # hub-cached SpMV shape
     "rmat17": lambda: gg.rmat(17, 8, seed=13),
     "chunglu": lambda: gg.chung_lu(120000, 2.1, 12.0, seed=14),
 }

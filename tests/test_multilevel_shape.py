@@ -78,7 +78,7 @@ def test_galerkin_levels_match_oracle_entrywise(P, name, make, cm, trim):
     """Every level's matrix A_{l+1} = P_l^T A_l P_l of the library's set-up against the
     oracle's, entry by entry: both sum the same fine entries in other orders, so each entry
     differs by at most 2 (K - 1) u times the sum of the absolute values of its K fine terms
-    (u = 2^-53).  The coarse vertices are matched through the aggregates (same rule, other
+    (u = 2^-53); the test allows 2 K u.  The coarse vertices are matched through the aggregates (same rule, other
     numbering)."""
     import scipy.sparse as sp
 
