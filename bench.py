@@ -157,40 +157,82 @@ def cpu_model():
 
 def cpu_baseline(g, cfg, ref_stats, u0, inner_rtol, budget):
     """The FP64 oracle (plain method, same graph, start block and tolerances) on one host
-    core for a bounded sample: its set-up, then outer iterations until `budget` seconds.  Each
-    sampled outer iteration's time is fitted (non-negative least squares) as a * (inner
-    iterations) + b * (columns of U and V) + c, and the fit is applied to the counts of the
-    GPU's plain FP64 solve of the same workload (inner iterations, summed basis columns,
-    outer iterations) to estimate the oracle's time to k pairs."""
+    core for a bounded sample, turned into an estimate of its time to k pairs.
+
+    * Sample: the oracle's set-up, then outer iterations until `budget` seconds.  Each outer
+      iteration logs its seconds, its inner iterations, the columns of U and V it worked
+      with, and the seconds of its inner solve.
+    * Inner solves: the sample gives the cost per inner iteration, referred to c = 0 locked
+      pairs with the slope below (the sample usually locks none): a0.  The growth with c locked pairs (deflation columns) is
+      timed apart: the oracle's own inner solve with c orthonormal columns, 7 iterations
+      minus 2 iterations, at c = 0 and c = min(k - 1, 24), gives a1 per iteration and
+      column.  Pair j
+      of the GPU's plain FP64 solve is computed with j locked pairs, so its inner
+      iterations cost a0 + a1 j each.
+    * The rest of an outer iteration (Ritz residual, CGS2, the new W and H columns, the
+      dense eigensolver) is fitted, by non-negative least squares, as b (columns of U and
+      V) + e, and applied to the GPU solve's summed basis columns and outer iterations."""
     from scipy.optimize import nnls
     from threadpoolctl import threadpool_limits
 
     from oracle import isira_oracle as O
 
+    k = cfg["k"]
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        res = O.isira(g, cfg["k"], cfg["sigma"], cfg["tol"], u0, inner_rtol=inner_rtol,
+        res = O.isira(g, k, cfg["sigma"], cfg["tol"], u0, inner_rtol=inner_rtol,
                       time_budget=budget)
         el = time.perf_counter() - t0
-    rows = np.array(res.outer_log, dtype=np.float64).reshape(-1, 3)
-    if len(rows) < 3:
-        return {"value": None, "unit": "s", "cores": 1, "kind": "oracle", "cpu": cpu_model(),
-                "sample": f"too few outer iterations in {el:.1f} s"}
-    A = np.column_stack([rows[:, 1], rows[:, 2], np.ones(len(rows))])
-    coef, _ = nnls(A, rows[:, 0])
-    counts = np.array([ref_stats["inner_total"], ref_stats["basis_cols_total"], ref_stats["outer_total"]],
-                      dtype=np.float64)
-    est = res.setup_seconds + float(coef @ counts)
+        rows = np.array(res.outer_log, dtype=np.float64).reshape(-1, 4)
+        if len(rows) < 3:
+            return {"value": None, "unit": "s", "cores": 1, "kind": "oracle", "cpu": cpu_model(),
+                    "sample": f"too few outer iterations in {el:.1f} s"}
+        a0 = float(rows[:, 3].sum() / max(1.0, rows[:, 1].sum()))
+        # per-iteration growth of the oracle's inner solve with the deflation columns
+        L = O.laplacian(g)
+        d = O.degrees(g)
+        i = O.trim_index(d)
+        delta = 2.0 * float(d.max())
+        Lhat = O.trimmed_matrix(L, i)
+        rng = np.random.default_rng(11)
+        r = rng.standard_normal(g.n)
+        r -= r.mean()
+
+        def per_it(c):
+            V = np.linalg.qr(rng.standard_normal((g.n, c)))[0] if c else np.zeros((g.n, 0))
+            ts = []
+            for its in (2, 7):
+                t = time.perf_counter()
+                _, done_its, _ = O.inner_solve(L, d, r, i, cfg["sigma"], delta, V, 1e-30, its, None, Lhat)
+                ts.append((time.perf_counter() - t, done_its))
+            return (ts[1][0] - ts[0][0]) / max(1, ts[1][1] - ts[0][1])
+
+        c_hi = max(1, min(k - 1, 24))
+        p0, p1 = per_it(0), per_it(c_hi)
+        a1 = max(0.0, (p1 - p0) / c_hi)
+    dense = rows[:, 0] - rows[:, 3]
+    A = np.column_stack([rows[:, 2], np.ones(len(rows))])
+    (b, e), _ = nnls(A, dense)
+    # the sample's inner iterations ran with 0, 1, ... locked pairs: refer a0 to c = 0
+    smp = np.asarray(res.inner_its, dtype=np.float64)
+    c_smp = float(np.sum(smp * np.arange(len(smp))) / max(1.0, smp.sum()))
+    a0 = max(0.0, a0 - a1 * c_smp)
+    per_pair = np.asarray(ref_stats["inner_per_pair"], dtype=np.float64)
+    inner_est = float(np.sum(per_pair * (a0 + a1 * np.arange(len(per_pair)))))
+    dense_est = b * ref_stats["basis_cols_total"] + e * ref_stats["outer_total"]
+    est = res.setup_seconds + inner_est + dense_est
     return {
         "value": est, "unit": "s", "cores": 1, "kind": "oracle", "cpu": cpu_model(),
         "sample": (f"oracle iSIRA (plain FP64, numpy/scipy on 1 thread) on the same graph, start block and "
                    f"tolerances: set-up {res.setup_seconds:.1f} s, then {len(rows)} outer iterations in "
-                   f"{el - res.setup_seconds:.1f} s ({int(rows[:, 1].sum())} inner iterations, "
-                   f"{res.converged} pairs locked); per outer iteration {coef[0]:.3g} s per inner "
-                   f"iteration + {coef[1]:.3g} s per basis column + {coef[2]:.3g} s, applied to the GPU "
-                   f"plain FP64 solve's {ref_stats['inner_total']} inner iterations, "
+                   f"{el - res.setup_seconds:.1f} s ({int(rows[:, 1].sum())} inner iterations in "
+                   f"{rows[:, 3].sum():.1f} s, {res.converged} pairs locked); inner iteration "
+                   f"{a0:.3g} s + {a1:.3g} s per locked pair (the oracle's inner solve timed at 0 and "
+                   f"{c_hi} deflation columns: {p0:.3g} / {p1:.3g} s per iteration); rest of an outer "
+                   f"iteration {b:.3g} s per basis column + {e:.3g} s; applied to the GPU plain FP64 "
+                   f"solve's inner iterations per pair (total {ref_stats['inner_total']}), "
                    f"{ref_stats['basis_cols_total']} basis columns and {ref_stats['outer_total']} outer "
-                   f"iterations"),
+                   f"iterations: inner {inner_est:.1f} s, rest {dense_est:.1f} s"),
     }
 
 

@@ -306,8 +306,9 @@ class IsiraResult:
     breakdowns: int = 0
     refreshes: int = 0
     history: list = dataclasses.field(default_factory=list)  # ||r|| per outer iteration
-    # per outer iteration: (seconds, inner iterations, basis width + locked pairs); set-up
-    # seconds before the first one (timing records for cost models, no arithmetic)
+    # per outer iteration: (seconds, inner iterations, basis width + locked pairs, seconds of
+    # its inner solve); set-up seconds before the first one (timing records for cost models,
+    # no arithmetic)
     outer_log: list = dataclasses.field(default_factory=list)
     setup_seconds: float = 0.0
 
@@ -371,17 +372,18 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
     evals, evecs, outer_its, inner_its, history = [], [], [], [], []
     restarts = refreshes = 0
     outer = 0
-    # timing records (no arithmetic): per outer iteration its seconds, inner iterations and
-    # the columns of U and V it worked with
+    # timing records (no arithmetic): per outer iteration its seconds, inner iterations, the
+    # columns of U and V it worked with, and the seconds of its inner solve
     setup_s = _time.perf_counter() - t_start
     log, mark = [], None
+    inner_clock = [0.0]
 
     def tick(inner_so_far, cols):
         nonlocal mark
         now = _time.perf_counter()
         if mark is not None:
-            log.append((now - mark[0], inner_so_far - mark[1], mark[2]))
-        mark = (now, inner_so_far, cols)
+            log.append((now - mark[0], inner_so_far - mark[1], mark[2], inner_clock[0] - mark[3]))
+        mark = (now, inner_so_far, cols, inner_clock[0])
 
     def done(res):
         res.outer_log, res.setup_seconds = log, setup_s
@@ -436,8 +438,10 @@ def isira(g, k: int, sigma: float, tol: float, U0: np.ndarray, *, m: Optional[in
                 H = np.diag(theta[:q])
             # subspace expansion: trimmed (deflated) inner solve and enlargement
             rr = r - np.mean(r)  # Lemma 2.1: the right-hand side must be orthogonal to 1
+            t_in = _time.perf_counter()
             zstar, its, _ = inner_solve(L, dvec, rr, i, sigma, dl, V, inner_rtol, max_inner, minv_hat, Lhat,
                                         rank_one, "minres" if moving_shift else "pcg")
+            inner_clock[0] += _time.perf_counter() - t_in
             inner_here += its
             # orthonormalize against U and V (and 1/sqrt(n))
             Q = np.column_stack([U, V, ones])
