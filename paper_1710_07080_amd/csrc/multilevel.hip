@@ -17,10 +17,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "multilevel.h"
@@ -55,6 +57,108 @@ template <typename T>
 void dfr(DevMem& m, T*& p) {
   dfree(m, p);
 }
+
+// Host threads for the set-up: up to 16, one for small inputs.
+int setup_threads(int64_t items) {
+  unsigned hc = std::thread::hardware_concurrency();
+  return items < 65536 ? 1 : (hc == 0 ? 1 : (hc > 16 ? 16 : (int)hc));
+}
+
+// f(t, begin, end) over nt contiguous ranges of [0, n), one thread each.
+template <typename F>
+void run_ranges(int n, int nt, F f) {
+  const int chunk = (n + nt - 1) / nt;
+  if (nt == 1) {
+    f(0, 0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) th.emplace_back([&, t] { f(t, t * chunk, std::min(n, t * chunk + chunk)); });
+  for (auto& x : th) x.join();
+}
+
+// f(begin, end) over chunks of [0, n) (64 per thread), which the threads take in turn.
+template <typename F>
+void for_chunks(int n, int nt, F f) {
+  const int nchunk = nt == 1 ? 1 : std::min(n, 64 * nt);
+  const int csize = nchunk ? (n + nchunk - 1) / nchunk : 0;
+  std::atomic<int> next(0);
+  run_ranges(nt, nt, [&](int, int, int) {
+    for (int c = next++; c < nchunk; c = next++) f(c * csize, std::min(n, c * csize + csize));
+  });
+}
+
+// Rows [0, nrows) of a CSR matrix built by up to 16 host threads.  The rows are cut into
+// chunks of consecutive rows (many more than threads, since a few rows near the hubs carry
+// much of the work); threads take chunks in turn from a shared counter and emit each
+// chunk's rows into the chunk's own buffers through emit(row, cols, vals), a worker made
+// per thread by make() that holds the thread's scratch.  The chunks are then concatenated in
+// order.  Each row depends only on its own inputs, so the result is the serial build's, bit
+// for bit.
+template <typename V, typename Make>
+void build_rows(int nrows, std::vector<int32_t>& rp, std::vector<int32_t>& col,
+                std::vector<V>& val, Make make) {
+  const int nt = setup_threads(nrows);
+  const int nchunk = nt == 1 ? 1 : std::min(nrows, 64 * nt);
+  const int csize = (nrows + nchunk - 1) / nchunk;
+  std::vector<std::vector<int32_t>> cs(nchunk);
+  std::vector<std::vector<V>> vs(nchunk);
+  rp.assign((size_t)nrows + 1, 0);
+  std::atomic<int> next(0);
+  run_ranges(nt, nt, [&](int, int, int) {
+    auto emit = make();
+    for (int c = next++; c < nchunk; c = next++) {
+      const int b = c * csize, e = std::min(nrows, b + csize);
+      for (int r = b; r < e; ++r) {
+        emit(r, cs[c], vs[c]);
+        rp[r + 1] = (int32_t)cs[c].size();  // offset within the chunk; made global below
+      }
+    }
+  });
+  std::vector<size_t> base(nchunk + 1, 0);
+  for (int c = 0; c < nchunk; ++c) base[c + 1] = base[c] + cs[c].size();
+  col.resize(base[nchunk]);
+  val.resize(base[nchunk]);
+  std::atomic<int> next2(0);
+  run_ranges(nt, nt, [&](int, int, int) {
+    for (int c = next2++; c < nchunk; c = next2++) {
+      std::copy(cs[c].begin(), cs[c].end(), col.begin() + base[c]);
+      std::copy(vs[c].begin(), vs[c].end(), val.begin() + base[c]);
+      const int b = c * csize, e = std::min(nrows, b + csize);
+      for (int r = b; r < e; ++r) rp[r + 1] += (int32_t)base[c];
+      std::vector<int32_t>().swap(cs[c]);
+      std::vector<V>().swap(vs[c]);
+    }
+  });
+}
+
+// Accumulates a row's entries by column; flush() appends them in increasing column order.
+template <typename V>
+struct RowAccumulator {
+  std::vector<int32_t> pos, touched;
+  std::vector<V> acc;
+  explicit RowAccumulator(int ncols) : pos(ncols, -1) {}
+  void add(int b, V v) {
+    if (pos[b] < 0) {
+      pos[b] = (int)touched.size();
+      touched.push_back(b);
+      acc.push_back(V(0));
+    }
+    acc[pos[b]] += v;
+  }
+  void flush(std::vector<int32_t>& col, std::vector<V>& val) {
+    std::vector<int32_t> idx(touched.size());
+    for (size_t t = 0; t < idx.size(); ++t) idx[t] = (int32_t)t;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return touched[x] < touched[y]; });
+    for (int t : idx) {
+      col.push_back(touched[t]);
+      val.push_back(acc[t]);
+    }
+    for (int b : touched) pos[b] = -1;
+    touched.clear();
+    acc.clear();
+  }
+};
 
 // One level on the host: A_ij = -w for the stored off-diagonal entries, A_ii = diag.
 struct HostLevel {
@@ -129,43 +233,27 @@ HostLevel coarsen(const HostLevel& A, const std::vector<int32_t>& agg, int nc) {
     for (int i = 0; i < A.n; ++i)
       if (agg[i] >= 0) mem[fill[agg[i]]++] = i;
   }
-  C.rp.assign((size_t)nc + 1, 0);
   C.diag.assign(nc, 0.0);
   C.active.assign(nc, 1);
-  std::vector<int32_t> pos(nc, -1), touched;
-  std::vector<double> acc;
-  for (int a = 0; a < nc; ++a) {
-    double dg = 0.0;
-    touched.clear();
-    acc.clear();
-    for (int k = mptr[a]; k < mptr[a + 1]; ++k) {
-      const int i = mem[k];
-      dg += A.diag[i];
-      for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) {
-        const int b = agg[A.col[e]];
-        if (b == a) {
-          dg -= A.w[e];
-        } else {
-          if (pos[b] < 0) {
-            pos[b] = (int)touched.size();
-            touched.push_back(b);
-            acc.push_back(0.0);
-          }
-          acc[pos[b]] += A.w[e];
+  build_rows<double>(nc, C.rp, C.col, C.w, [&] {
+    return [&, ra = RowAccumulator<double>(nc)](int a, std::vector<int32_t>& col,
+                                                std::vector<double>& val) mutable {
+      double dg = 0.0;
+      for (int k = mptr[a]; k < mptr[a + 1]; ++k) {
+        const int i = mem[k];
+        dg += A.diag[i];
+        for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+          const int b = agg[A.col[e]];
+          if (b == a)
+            dg -= A.w[e];
+          else
+            ra.add(b, A.w[e]);
         }
       }
-    }
-    C.diag[a] = dg;
-    std::vector<int32_t> idx(touched.size());
-    for (size_t t = 0; t < idx.size(); ++t) idx[t] = (int32_t)t;
-    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return touched[x] < touched[y]; });
-    for (int t : idx) {
-      C.col.push_back(touched[t]);
-      C.w.push_back(acc[t]);
-    }
-    C.rp[a + 1] = (int32_t)C.col.size();
-    for (int b : touched) pos[b] = -1;
-  }
+      C.diag[a] = dg;
+      ra.flush(col, val);
+    };
+  });
   return C;
 }
 
@@ -244,65 +332,67 @@ HostMats build_level_mats(const HostLevel& A, const std::vector<int32_t>& agg, i
   for (int i = 0; i < n; ++i)
     if (A.active[i]) s[i] = (A.rowlen(i) > 0 ? omega : 1.0) / A.diag[i];
   // Q = (I - S A) P: row i, column b: [agg_i == b] (1 - s_i A_ii) + s_i sum_{j in b} w_ij
-  std::vector<int32_t> qrp((size_t)n + 1, 0), qcol;
+  std::vector<int32_t> qrp, qcol;
   std::vector<double> qval;
-  std::vector<int32_t> pos(nc, -1), touched;
-  std::vector<double> acc;
-  for (int i = 0; i < n; ++i) {
-    if (agg[i] >= 0) {
-      touched.clear();
-      acc.clear();
-      auto add = [&](int b, double v) {
-        if (pos[b] < 0) {
-          pos[b] = (int)touched.size();
-          touched.push_back(b);
-          acc.push_back(0.0);
-        }
-        acc[pos[b]] += v;
-      };
-      add(agg[i], 1.0 - s[i] * A.diag[i]);
-      for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) add(agg[A.col[e]], s[i] * A.w[e]);
-      std::vector<int32_t> idx(touched.size());
-      for (size_t t = 0; t < idx.size(); ++t) idx[t] = (int32_t)t;
-      std::sort(idx.begin(), idx.end(), [&](int x, int y) { return touched[x] < touched[y]; });
-      for (int t : idx) {
-        qcol.push_back(touched[t]);
-        qval.push_back(acc[t]);
-      }
-      for (int b : touched) pos[b] = -1;
-    }
-    qrp[i + 1] = (int32_t)qcol.size();
-  }
-  // up = [M | Q], M = 2S - S A S: off-diagonal s_i w_ij s_j, diagonal 2 s_i - s_i^2 A_ii
+  build_rows<double>(n, qrp, qcol, qval, [&] {
+    return [&, ra = RowAccumulator<double>(nc)](int i, std::vector<int32_t>& col,
+                                                std::vector<double>& val) mutable {
+      if (agg[i] < 0) return;
+      ra.add(agg[i], 1.0 - s[i] * A.diag[i]);
+      for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) ra.add(agg[A.col[e]], s[i] * A.w[e]);
+      ra.flush(col, val);
+    };
+  });
+  // up = [M | Q], M = 2S - S A S: off-diagonal s_i w_ij s_j, diagonal 2 s_i - s_i^2 A_ii;
+  // row i holds A's row, then Q's row, so its offset is known and the rows fill in parallel
   M.urp.assign((size_t)n + 1, 0);
   M.udiag.assign(n, 0.0);
-  M.ucol.reserve(A.col.size() + qcol.size());
-  M.uval.reserve(A.col.size() + qcol.size());
-  for (int i = 0; i < n; ++i) {
-    for (int e = A.rp[i]; e < A.rp[i + 1]; ++e) {
-      M.ucol.push_back(A.col[e]);
-      M.uval.push_back(s[i] * A.w[e] * s[A.col[e]]);
+  for (int i = 0; i < n; ++i) M.urp[i + 1] = A.rp[i + 1] + qrp[i + 1];
+  M.ucol.resize(M.urp[n]);
+  M.uval.resize(M.urp[n]);
+  for_chunks(n, setup_threads(n), [&](int b, int e) {
+    for (int i = b; i < e; ++i) {
+      int o = M.urp[i];
+      for (int k = A.rp[i]; k < A.rp[i + 1]; ++k, ++o) {
+        M.ucol[o] = A.col[k];
+        M.uval[o] = s[i] * A.w[k] * s[A.col[k]];
+      }
+      for (int k = qrp[i]; k < qrp[i + 1]; ++k, ++o) {
+        M.ucol[o] = M.ld + qcol[k];
+        M.uval[o] = qval[k];
+      }
+      if (A.active[i]) M.udiag[i] = 2.0 * s[i] - s[i] * s[i] * A.diag[i];
     }
-    for (int e = qrp[i]; e < qrp[i + 1]; ++e) {
-      M.ucol.push_back(M.ld + qcol[e]);
-      M.uval.push_back(qval[e]);
-    }
-    M.urp[i + 1] = (int32_t)M.ucol.size();
-    if (A.active[i]) M.udiag[i] = 2.0 * s[i] - s[i] * s[i] * A.diag[i];
-  }
-  // down = Q^T (rows = aggregates, columns increasing)
+  });
+  // down = Q^T (rows = aggregates, columns increasing): each thread counts the entries of
+  // its range of Q's rows per aggregate, so that it writes its part of every row of Q^T
+  // after the earlier ranges' parts, in increasing order of Q's rows
+  const int nt = setup_threads(n);
+  std::vector<std::vector<int32_t>> cnt(nt, std::vector<int32_t>(nc, 0));
+  run_ranges(n, nt, [&](int t, int b, int e) {
+    for (int k = qrp[b]; k < qrp[e]; ++k) cnt[t][qcol[k]]++;
+  });
   M.drp.assign((size_t)nc + 1, 0);
+  for (int a = 0; a < nc; ++a) {
+    int off = M.drp[a];
+    for (int t = 0; t < nt; ++t) {
+      const int c = cnt[t][a];
+      cnt[t][a] = off;  // thread t's first slot in row a
+      off += c;
+    }
+    M.drp[a + 1] = off;
+  }
   M.dcol.assign(qcol.size(), 0);
   M.dval.assign(qcol.size(), 0.0);
-  for (int32_t b : qcol) M.drp[b + 1]++;
-  for (int b = 0; b < nc; ++b) M.drp[b + 1] += M.drp[b];
-  std::vector<int32_t> fill(M.drp.begin(), M.drp.end() - 1);
-  for (int i = 0; i < n; ++i)
-    for (int e = qrp[i]; e < qrp[i + 1]; ++e) {
-      const int k = fill[qcol[e]]++;
-      M.dcol[k] = i;
-      M.dval[k] = qval[e];
-    }
+  run_ranges(n, nt, [&](int t, int b, int e) {
+    std::vector<int32_t>& fill = cnt[t];
+    for (int i = b; i < e; ++i)
+      for (int k = qrp[i]; k < qrp[i + 1]; ++k) {
+        const int slot = fill[qcol[k]]++;
+        M.dcol[slot] = i;
+        M.dval[slot] = qval[k];
+      }
+  });
   return M;
 }
 
@@ -356,21 +446,35 @@ int build_host(int n, const int32_t* rp, const int32_t* col, const double* w,
     A.diag.assign(n, 0.0);
     A.active.assign(n, 1);
     A.active[trim] = 0;
-    A.col.reserve(rp[n]);
-    A.w.reserve(rp[n]);
-    for (int i = 0; i < n; ++i) {
-      double d = 0.0;
-      for (int e = rp[i]; e < rp[i + 1]; ++e) {
-        const double we = w ? w[e] : 1.0;
-        d += we;
-        if (i != trim && col[e] != trim) {
-          A.col.push_back(col[e]);
-          A.w.push_back(we);
-        }
+    // row lengths without the trimmed vertex, then the rows in parallel
+    const int nt = setup_threads(n);
+    for_chunks(n, nt, [&](int b, int e) {
+      for (int i = b; i < e; ++i) {
+        int len = 0;
+        if (i != trim)
+          for (int k = rp[i]; k < rp[i + 1]; ++k) len += col[k] != trim;
+        A.rp[i + 1] = len;
       }
-      A.diag[i] = i == trim ? 0.0 : d;
-      A.rp[i + 1] = (int32_t)A.col.size();
-    }
+    });
+    for (int i = 0; i < n; ++i) A.rp[i + 1] += A.rp[i];
+    A.col.resize(A.rp[n]);
+    A.w.resize(A.rp[n]);
+    for_chunks(n, nt, [&](int b, int e) {
+      for (int i = b; i < e; ++i) {
+        double d = 0.0;
+        int o = A.rp[i];
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+          const double we = w ? w[k] : 1.0;
+          d += we;
+          if (i != trim && col[k] != trim) {
+            A.col[o] = col[k];
+            A.w[o] = we;
+            ++o;
+          }
+        }
+        A.diag[i] = i == trim ? 0.0 : d;
+      }
+    });
   }
   std::vector<int32_t> by_key(n);
   for (int i = 0; i < n; ++i) by_key[perm[i]] = i;  // increasing caller label

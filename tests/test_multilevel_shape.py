@@ -40,6 +40,9 @@ CASES = [
     ("star", lambda: gg.star_graph(300), 8, None),
     ("chunglu", lambda: gg.chung_lu(20000, 2.1, 8.0, seed=14), 128, None),
     ("rmat12_trim_min", lambda: gg.rmat(12, 8, seed=3), 16, "min"),
+    # above 65,536 rows the library builds the levels with several host threads
+    ("grid3d_big", lambda: gg.grid3d(48, 48, 40, weights=(0.5, 1.5), seed=5), 64, None),
+    ("rmat17", lambda: gg.rmat(17, 8, seed=13), 64, None),
 ]
 
 
@@ -70,7 +73,8 @@ def test_shape_errors(P):
     assert e.value.code == P.isira.ISIRA_E_PRECOND
 
 
-GALERKIN = [c for c in CASES if c[0] in ("grid3d_w", "rmat14", "rand_w", "star_paths", "chunglu", "rmat12_trim_min")]
+GALERKIN = [c for c in CASES if c[0] in ("grid3d_w", "rmat14", "rand_w", "star_paths", "chunglu", "rmat12_trim_min",
+                                         "grid3d_big", "rmat17")]
 
 
 @pytest.mark.parametrize("name,make,cm,trim", GALERKIN, ids=[c[0] for c in GALERKIN])
