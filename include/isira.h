@@ -42,6 +42,8 @@ extern "C" {
 #define ISIRA_E_PRECOND (-5)    /* the learned preconditioner is missing or not usable */
 #define ISIRA_E_STATE (-6)      /* entry point called in the wrong state */
 #define ISIRA_E_WORKSPACE (-7)  /* the caller's workspace is too small for this call */
+#define ISIRA_E_HOST (-8)       /* host-side failure, e.g. host memory exhausted (no C++ exception
+                                   crosses an entry point) */
 
 /* ---- weight dtypes ---- */
 #define ISIRA_W_NONE 0 /* unit weights (plain adjacency A) */

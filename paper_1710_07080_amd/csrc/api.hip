@@ -48,6 +48,9 @@ int hw_threads() {
   return h == 0 ? 1 : (h > 16 ? 16 : (int)h);
 }
 
+// f(begin, end) over contiguous ranges of [0, n), one host thread each (a range whose
+// thread cannot be started runs on the calling thread); an exception in any range is
+// rethrown after every thread has joined.
 template <typename F>
 void parallel_for(int64_t n, F f) {
   const int nt = hw_threads();
@@ -55,13 +58,29 @@ void parallel_for(int64_t n, F f) {
     f(0, n);
     return;
   }
+  std::vector<std::exception_ptr> ex(nt);
   std::vector<std::thread> th;
+  th.reserve(nt);
   const int64_t chunk = (n + nt - 1) / nt;
   for (int t = 0; t < nt; ++t) {
     const int64_t b = t * chunk, e = std::min(n, b + chunk);
-    if (b < e) th.emplace_back([=] { f(b, e); });
+    if (b >= e) continue;
+    auto job = [&, t, b, e] {
+      try {
+        f(b, e);
+      } catch (...) {
+        ex[t] = std::current_exception();
+      }
+    };
+    try {
+      th.emplace_back(job);
+    } catch (...) {
+      job();
+    }
   }
   for (auto& x : th) x.join();
+  for (auto& x : ex)
+    if (x) std::rethrow_exception(x);
 }
 
 }  // namespace
@@ -503,7 +522,9 @@ static int create_impl(isira_ctx** out, int64_t n, int64_t nnz, const int32_t* r
 extern "C" int isira_create(isira_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
                             const int32_t* col, const void* w, int32_t w_dtype, void* stream,
                             int32_t validate) {
-  return create_impl(out, n, nnz, row_ptr, col, w, w_dtype, stream, validate, nullptr, 0);
+  return guarded([&]() -> int {
+    return create_impl(out, n, nnz, row_ptr, col, w, w_dtype, stream, validate, nullptr, 0);
+  });
 }
 
 static int create_impl(isira_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
@@ -692,50 +713,54 @@ extern "C" int isira_create_ws(isira_ctx** out, int64_t n, int64_t nnz, const in
                                int32_t csr_on_device, void* workspace, size_t ws_bytes,
                                int32_t k, const isira_options* opt, void* stream,
                                int32_t validate) {
-  if (!out) return fail(ISIRA_E_ARG, "out is NULL");
-  *out = nullptr;
-  if (!workspace || ws_bytes == 0) return fail(ISIRA_E_ARG, "workspace is NULL or empty");
-  if (k < 1 || k > ISIRA_MAX_K) return fail(ISIRA_E_ARG, "need 1 <= k <= 64");
-  int m = 0;
-  solve_sizes(k, opt, &m);
-  if (m < 2 || m > ISIRA_MAX_BASIS) return fail(ISIRA_E_ARG, "need 2 <= m <= 192");
-  if (n < 3 || n >= (1ll << 31) - 64 || nnz < 2 || nnz >= (1ll << 31) || !row_ptr || !col)
-    return fail(ISIRA_E_ARG, "need 3 <= n < 2^31, 2 <= nnz < 2^31 and non-NULL CSR arrays");
-  // device CSR: the host-side validation, connectivity check and relabelling read a host copy
-  std::vector<int32_t> hrp, hcol;
-  std::vector<unsigned char> hw;
-  if (csr_on_device) {
-    hrp.resize(n + 1);
-    hcol.resize(nnz);
-    CKH(hipMemcpy(hrp.data(), row_ptr, (n + 1) * 4, hipMemcpyDeviceToHost));
-    CKH(hipMemcpy(hcol.data(), col, nnz * 4, hipMemcpyDeviceToHost));
-    if (w_dtype != ISIRA_W_NONE && w) {
-      hw.resize(nnz * (w_dtype == ISIRA_W_F32 ? 4 : 8));
-      CKH(hipMemcpy(hw.data(), w, hw.size(), hipMemcpyDeviceToHost));
+  return guarded([&]() -> int {
+    if (!out) return fail(ISIRA_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!workspace || ws_bytes == 0) return fail(ISIRA_E_ARG, "workspace is NULL or empty");
+    if (k < 1 || k > ISIRA_MAX_K) return fail(ISIRA_E_ARG, "need 1 <= k <= 64");
+    int m = 0;
+    solve_sizes(k, opt, &m);
+    if (m < 2 || m > ISIRA_MAX_BASIS) return fail(ISIRA_E_ARG, "need 2 <= m <= 192");
+    if (n < 3 || n >= (1ll << 31) - 64 || nnz < 2 || nnz >= (1ll << 31) || !row_ptr || !col)
+      return fail(ISIRA_E_ARG, "need 3 <= n < 2^31, 2 <= nnz < 2^31 and non-NULL CSR arrays");
+    // device CSR: the host-side validation, connectivity check and relabelling read a host copy
+    std::vector<int32_t> hrp, hcol;
+    std::vector<unsigned char> hw;
+    if (csr_on_device) {
+      hrp.resize(n + 1);
+      hcol.resize(nnz);
+      CKH(hipMemcpy(hrp.data(), row_ptr, (n + 1) * 4, hipMemcpyDeviceToHost));
+      CKH(hipMemcpy(hcol.data(), col, nnz * 4, hipMemcpyDeviceToHost));
+      if (w_dtype != ISIRA_W_NONE && w) {
+        hw.resize(nnz * (w_dtype == ISIRA_W_F32 ? 4 : 8));
+        CKH(hipMemcpy(hw.data(), w, hw.size(), hipMemcpyDeviceToHost));
+      }
+      row_ptr = hrp.data();
+      col = hcol.data();
+      if (!hw.empty()) w = hw.data();
     }
-    row_ptr = hrp.data();
-    col = hcol.data();
-    if (!hw.empty()) w = hw.data();
-  }
-  isira_ctx* ctx = nullptr;
-  int rc = create_impl(&ctx, n, nnz, row_ptr, col, w, w_dtype, stream, validate, workspace, ws_bytes);
-  if (rc) return rc;
-  // the solve workspace for (k, m) now, so that later calls carve nothing more
-  if ((rc = ensure_workspace(ctx, m, k))) {
-    isira_destroy(ctx);
-    return rc;
-  }
-  *out = ctx;
-  return ISIRA_OK;
+    isira_ctx* ctx = nullptr;
+    int rc = create_impl(&ctx, n, nnz, row_ptr, col, w, w_dtype, stream, validate, workspace, ws_bytes);
+    if (rc) return rc;
+    // the solve workspace for (k, m) now, so that later calls carve nothing more
+    if ((rc = ensure_workspace(ctx, m, k))) {
+      isira_destroy(ctx);
+      return rc;
+    }
+    *out = ctx;
+    return ISIRA_OK;
+  });
 }
 
 extern "C" int isira_memory_info(const isira_ctx* c, size_t* in_use, size_t* peak,
                                  size_t* capacity) {
-  if (!c) return fail(ISIRA_E_ARG, "NULL context");
-  if (in_use) *in_use = c->mem.in_use();
-  if (peak) *peak = c->mem.peak();
-  if (capacity) *capacity = c->mem.capacity();
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c) return fail(ISIRA_E_ARG, "NULL context");
+    if (in_use) *in_use = c->mem.in_use();
+    if (peak) *peak = c->mem.peak();
+    if (capacity) *capacity = c->mem.capacity();
+    return ISIRA_OK;
+  });
 }
 
 extern "C" void isira_destroy(isira_ctx* c) {
@@ -755,19 +780,21 @@ extern "C" void isira_destroy(isira_ctx* c) {
 }
 
 extern "C" int isira_get_info(const isira_ctx* c, isira_info* info) {
-  if (!c || !info) return fail(ISIRA_E_ARG, "NULL argument");
-  info->n = c->n;
-  info->nnz = c->nnz;
-  info->trim_index = c->trim_label;
-  info->max_degree = c->max_deg;
-  info->min_degree = c->min_deg;
-  info->delta_default = 2.0 * c->max_deg;
-  info->norm1 = 2.0 * c->max_deg;
-  info->n_spmv_units = c->plan.n_units;
-  info->n_spmv_blocks = c->plan.grid;
-  info->n_split_rows = c->plan.n_split_rows;
-  info->has_learned = c->has_learned ? 1 : 0;
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c || !info) return fail(ISIRA_E_ARG, "NULL argument");
+    info->n = c->n;
+    info->nnz = c->nnz;
+    info->trim_index = c->trim_label;
+    info->max_degree = c->max_deg;
+    info->min_degree = c->min_deg;
+    info->delta_default = 2.0 * c->max_deg;
+    info->norm1 = 2.0 * c->max_deg;
+    info->n_spmv_units = c->plan.n_units;
+    info->n_spmv_blocks = c->plan.grid;
+    info->n_split_rows = c->plan.n_split_rows;
+    info->has_learned = c->has_learned ? 1 : 0;
+    return ISIRA_OK;
+  });
 }
 
 // ------------------------------------------------------------------------------ helpers
@@ -1132,628 +1159,640 @@ int cgs2(isira_ctx* c, const double* U, int nu, const double* V, int nv, double*
 extern "C" int isira_solve(isira_ctx* c, int32_t k, double sigma, double tol,
                            const isira_options* optp, double* evals, double* evecs,
                            double* resid, isira_stats* stats) {
-  if (!c) return fail(ISIRA_E_ARG, "NULL context");
-  isira_options opt;
-  if (optp) opt = *optp; else isira_default_options(&opt);
-  const int n = (int)c->n;
-  const int q = opt.q > 0 ? opt.q : k + 10;
-  const int m = opt.m > 0 ? opt.m : 2 * q;
-  const int k0 = opt.k0 > 0 ? opt.k0 : 4;
-  if (k < 1 || k > ISIRA_MAX_K || k > n - 2) return fail(ISIRA_E_ARG, "need 1 <= k <= min(64, n-2)");
-  if (!(tol > 0.0)) return fail(ISIRA_E_ARG, "tol must be > 0");
-  if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
-  if (q < k || m <= q || m > ISIRA_MAX_BASIS || m + k > n - 1 || k0 >= m || k0 > n - 2)
-    return fail(ISIRA_E_ARG, "need k <= q < m <= 192, m + k <= n - 1 and k0 < m");
-  if (!evals || !evecs || !resid) return fail(ISIRA_E_ARG, "NULL output");
-  if (opt.inner_prec != ISIRA_FP64 && opt.inner_prec != ISIRA_FP32) return fail(ISIRA_E_ARG, "bad inner_prec");
-  if (opt.precond == ISIRA_PC_LEARNED && (!c->has_learned)) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
-  if (opt.precond != ISIRA_PC_JACOBI && opt.precond != ISIRA_PC_LEARNED && opt.precond != ISIRA_PC_MULTILEVEL)
-    return fail(ISIRA_E_ARG, "bad precond");
-  int trim = c->trim_default;
-  if (opt.trim_index >= 0) {
-    if (opt.trim_index >= n) return fail(ISIRA_E_ARG, "trim_index out of range");
-    trim = c->iperm[opt.trim_index];
-  }
-  if (opt.precond == ISIRA_PC_LEARNED && (c->spai_trim != trim || c->spai_sigma != sigma))
-    return fail(ISIRA_E_PRECOND, "learned preconditioner was installed for another sigma or trim index");
-  if (opt.shift_mode != ISIRA_SHIFT_FIXED && opt.shift_mode != ISIRA_SHIFT_MOVING)
-    return fail(ISIRA_E_ARG, "bad shift_mode");
-  const bool moving = opt.shift_mode == ISIRA_SHIFT_MOVING;
-  if (moving && opt.precond == ISIRA_PC_LEARNED)
-    return fail(ISIRA_E_PRECOND, "the learned preconditioner is built for one shift; it cannot follow a moving shift");
-  if (opt.precond == ISIRA_PC_MULTILEVEL && (!c->ml.ready || c->ml.trim != trim))
-    return fail(ISIRA_E_PRECOND, "no multilevel hierarchy set up for this trim index");
-  if (moving && opt.precond == ISIRA_PC_MULTILEVEL)
-    return fail(ISIRA_E_PRECOND, "the moving shift runs MINRES with the Jacobi preconditioner only");
-  const double delta = opt.delta > 0 ? opt.delta : 2.0 * c->max_deg;
-  int rc = ensure_workspace(c, m, k);
-  if (rc) return rc;
-  hipStream_t s = c->stream;
-  const int ld = c->ld;
-  isira_stats S{};
-  const double t_start = now_ms();
-  // events around the Ritz residual kernel: its own time goes to ms_residual, the rest of the
-  // wait that follows it (the first inner batch queued behind it) to ms_inner
-  struct EventPair {
-    hipEvent_t a = nullptr, b = nullptr;
-    ~EventPair() {
-      if (a) (void)hipEventDestroy(a);
-      if (b) (void)hipEventDestroy(b);
+  return guarded([&]() -> int {
+    if (!c) return fail(ISIRA_E_ARG, "NULL context");
+    isira_options opt;
+    if (optp) opt = *optp; else isira_default_options(&opt);
+    const int n = (int)c->n;
+    const int q = opt.q > 0 ? opt.q : k + 10;
+    const int m = opt.m > 0 ? opt.m : 2 * q;
+    const int k0 = opt.k0 > 0 ? opt.k0 : 4;
+    if (k < 1 || k > ISIRA_MAX_K || k > n - 2) return fail(ISIRA_E_ARG, "need 1 <= k <= min(64, n-2)");
+    if (!(tol > 0.0)) return fail(ISIRA_E_ARG, "tol must be > 0");
+    if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
+    if (q < k || m <= q || m > ISIRA_MAX_BASIS || m + k > n - 1 || k0 >= m || k0 > n - 2)
+      return fail(ISIRA_E_ARG, "need k <= q < m <= 192, m + k <= n - 1 and k0 < m");
+    if (!evals || !evecs || !resid) return fail(ISIRA_E_ARG, "NULL output");
+    if (opt.inner_prec != ISIRA_FP64 && opt.inner_prec != ISIRA_FP32) return fail(ISIRA_E_ARG, "bad inner_prec");
+    if (opt.precond == ISIRA_PC_LEARNED && (!c->has_learned)) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
+    if (opt.precond != ISIRA_PC_JACOBI && opt.precond != ISIRA_PC_LEARNED && opt.precond != ISIRA_PC_MULTILEVEL)
+      return fail(ISIRA_E_ARG, "bad precond");
+    int trim = c->trim_default;
+    if (opt.trim_index >= 0) {
+      if (opt.trim_index >= n) return fail(ISIRA_E_ARG, "trim_index out of range");
+      trim = c->iperm[opt.trim_index];
     }
-  } ev;
-  CKH(hipEventCreate(&ev.a));
-  CKH(hipEventCreate(&ev.b));
-  InnerCfg cfg;
-  cfg.prec = opt.inner_prec;
-  cfg.precond = opt.precond;
-  cfg.sigma = sigma;
-  cfg.delta = delta;
-  cfg.rtol = opt.inner_rtol > 0 ? opt.inner_rtol : 1e-1;
-  cfg.trim = trim;
-  cfg.maxit = opt.max_inner > 0 ? opt.max_inner : 1000;
-  cfg.check_every = opt.check_every > 0 ? opt.check_every : 8;
-  cfg.rank_one = opt.drop_rank_one == 0;
-  // a moving shift can make the trimmed system indefinite (Thm 2.8), so it is solved by MINRES
-  cfg.solver = moving ? ISIRA_SOLVER_MINRES : ISIRA_SOLVER_PCG;
-  const double sigma_cap = 0.5 * c->min_deg;  // keeps diag(d - sigma) positive
-  const int max_outer = opt.max_outer > 0 ? opt.max_outer : 20000;
-  // Jacobi inverse diagonal (Remark 3.2) in both precisions
-  launch_dinv<double>(n, c->deg, sigma, trim, c->dinv64, s);
-  launch_dinv<float>(n, c->deg, sigma, trim, c->dinv32, s);
-  uint64_t draws = 0;
-  int capture_count = 0;
+    if (opt.precond == ISIRA_PC_LEARNED && (c->spai_trim != trim || c->spai_sigma != sigma))
+      return fail(ISIRA_E_PRECOND, "learned preconditioner was installed for another sigma or trim index");
+    if (opt.shift_mode != ISIRA_SHIFT_FIXED && opt.shift_mode != ISIRA_SHIFT_MOVING)
+      return fail(ISIRA_E_ARG, "bad shift_mode");
+    const bool moving = opt.shift_mode == ISIRA_SHIFT_MOVING;
+    if (moving && opt.precond == ISIRA_PC_LEARNED)
+      return fail(ISIRA_E_PRECOND, "the learned preconditioner is built for one shift; it cannot follow a moving shift");
+    if (opt.precond == ISIRA_PC_MULTILEVEL && (!c->ml.ready || c->ml.trim != trim))
+      return fail(ISIRA_E_PRECOND, "no multilevel hierarchy set up for this trim index");
+    if (moving && opt.precond == ISIRA_PC_MULTILEVEL)
+      return fail(ISIRA_E_PRECOND, "the moving shift runs MINRES with the Jacobi preconditioner only");
+    const double delta = opt.delta > 0 ? opt.delta : 2.0 * c->max_deg;
+    int rc = ensure_workspace(c, m, k);
+    if (rc) return rc;
+    hipStream_t s = c->stream;
+    const int ld = c->ld;
+    isira_stats S{};
+    const double t_start = now_ms();
+    // events around the Ritz residual kernel: its own time goes to ms_residual, the rest of the
+    // wait that follows it (the first inner batch queued behind it) to ms_inner
+    struct EventPair {
+      hipEvent_t a = nullptr, b = nullptr;
+      ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+      }
+    } ev;
+    CKH(hipEventCreate(&ev.a));
+    CKH(hipEventCreate(&ev.b));
+    InnerCfg cfg;
+    cfg.prec = opt.inner_prec;
+    cfg.precond = opt.precond;
+    cfg.sigma = sigma;
+    cfg.delta = delta;
+    cfg.rtol = opt.inner_rtol > 0 ? opt.inner_rtol : 1e-1;
+    cfg.trim = trim;
+    cfg.maxit = opt.max_inner > 0 ? opt.max_inner : 1000;
+    cfg.check_every = opt.check_every > 0 ? opt.check_every : 8;
+    cfg.rank_one = opt.drop_rank_one == 0;
+    // a moving shift can make the trimmed system indefinite (Thm 2.8), so it is solved by MINRES
+    cfg.solver = moving ? ISIRA_SOLVER_MINRES : ISIRA_SOLVER_PCG;
+    const double sigma_cap = 0.5 * c->min_deg;  // keeps diag(d - sigma) positive
+    const int max_outer = opt.max_outer > 0 ? opt.max_outer : 20000;
+    // Jacobi inverse diagonal (Remark 3.2) in both precisions
+    launch_dinv<double>(n, c->deg, sigma, trim, c->dinv64, s);
+    launch_dinv<float>(n, c->deg, sigma, trim, c->dinv32, s);
+    uint64_t draws = 0;
+    int capture_count = 0;
 
-  // ---- start block: column means removed, orthonormalized (CGS2 against 1 and previous)
-  if (opt.u0) {
-    std::vector<double> col(n);
-    for (int j = 0; j < k0; ++j) {
-      CKH(hipMemcpyAsync(c->tmp64, opt.u0 + (size_t)j * n, (size_t)n * 8, hipMemcpyHostToDevice, s));
-      launch_gather<double, double>(n, c->tmp64, c->d_perm, c->z64, s);
-      // z64[new] = u0[perm[new]]
-      double nrm[2];
-      if ((rc = cgs2(c, c->U, j, c->Vout, 0, c->z64, nrm))) return rc;
-      while (!(nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0)) {
-        S.breakdowns++;
-        launch_fill_replacement(n, opt.seed, draws++, c->d_perm, c->z64, s);
+    // ---- start block: column means removed, orthonormalized (CGS2 against 1 and previous)
+    if (opt.u0) {
+      std::vector<double> col(n);
+      for (int j = 0; j < k0; ++j) {
+        CKH(hipMemcpyAsync(c->tmp64, opt.u0 + (size_t)j * n, (size_t)n * 8, hipMemcpyHostToDevice, s));
+        launch_gather<double, double>(n, c->tmp64, c->d_perm, c->z64, s);
+        // z64[new] = u0[perm[new]]
+        double nrm[2];
         if ((rc = cgs2(c, c->U, j, c->Vout, 0, c->z64, nrm))) return rc;
+        while (!(nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0)) {
+          S.breakdowns++;
+          launch_fill_replacement(n, opt.seed, draws++, c->d_perm, c->z64, s);
+          if ((rc = cgs2(c, c->U, j, c->Vout, 0, c->z64, nrm))) return rc;
+        }
+        launch_scale(n, c->z64, 1.0 / nrm[1], c->U + (size_t)j * ld, s);
       }
-      launch_scale(n, c->z64, 1.0 / nrm[1], c->U + (size_t)j * ld, s);
-    }
-  } else {
-    for (int j = 0; j < k0; ++j) {
-      double nrm[2];
-      do {
-        launch_fill_replacement(n, opt.seed, draws++, c->d_perm, c->z64, s);
-        if ((rc = cgs2(c, c->U, j, c->Vout, 0, c->z64, nrm))) return rc;
-      } while (!(nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0));
-      launch_scale(n, c->z64, 1.0 / nrm[1], c->U + (size_t)j * ld, s);
-    }
-  }
-  int kk = k0;  // current basis size
-  std::vector<double> H((size_t)m * m, 0.0);  // column-major, leading dimension m
-  for (int j = 0; j < kk; ++j) {
-    spmv64(c, c->U + (size_t)j * ld, c->W + (size_t)j * ld, nullptr, 0, nullptr, 0.0, 0, 0.0);
-    S.spmv_total++;
-  }
-  for (int j = 0; j < kk; ++j) {
-    launch_multidot<double>(n, c->U, ld, kk, nullptr, ld, 0, c->W + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
-    if ((rc = read_h(c, kk))) return rc;
-    SYNC_OR_RETURN(c);
-    for (int i = 0; i < kk; ++i) H[i + (size_t)j * m] = c->hbuf_host[i];
-  }
-  for (int i = 0; i < kk; ++i)
-    for (int j = 0; j < i; ++j) {
-      const double v = 0.5 * (H[i + (size_t)j * m] + H[j + (size_t)i * m]);
-      H[i + (size_t)j * m] = H[j + (size_t)i * m] = v;
-    }
-
-  int nconv = 0;
-  std::vector<double> Hk, theta, Sm, Spack;
-  std::vector<double> Cmat;  // c x c Gram V-hat^T M^-1 V-hat (column-major, ld kMaxC)
-  Cmat.assign((size_t)kMaxC * kMaxC, 0.0);
-  int outer = 0;
-  int its_pair = 0;
-  int64_t inner_pair = 0;
-  bool not_conv = false;
-
-  auto refresh_smw = [&](int cnew) -> int {
-    // new column cnew of C = V-hat^T P0 V-hat (P0 = M^-1 Jacobi or learned M); then G^-1
-    const int cc = cnew + 1;
-    if (cfg.precond == ISIRA_PC_MULTILEVEL) {
-      if (cfg.prec == ISIRA_FP64) {
-        ml::apply<double>(c->ml, c->Vin64 + (size_t)cnew * ld, c->Y64 + (size_t)cnew * ld, 0, c->st, c->rb, s);
-        launch_multidot<double>(n, c->Vin64, ld, cc, nullptr, ld, 0, c->Y64 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
-      } else {
-        ml::apply<float>(c->ml, c->Vin32 + (size_t)cnew * ld, c->Y32 + (size_t)cnew * ld, 0, c->st, c->rb, s);
-        launch_multidot<float>(n, c->Vin32, ld, cc, nullptr, ld, 0, c->Y32 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
-      }
-    } else if (cfg.precond == ISIRA_PC_LEARNED) {
-      if (cfg.prec == ISIRA_FP64) {
-        spai::apply_plain<double>(c->spw, c->plan, c->rp, c->col,
-                                  c->Vin64 + (size_t)cnew * ld, c->Y64 + (size_t)cnew * ld, n, trim, s);
-        launch_multidot<double>(n, c->Vin64, ld, cc, nullptr, ld, 0, c->Y64 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
-      } else {
-        spai::apply_plain<float>(c->spw, c->plan, c->rp, c->col,
-                                 c->Vin32 + (size_t)cnew * ld, c->Y32 + (size_t)cnew * ld, n, trim, s);
-        launch_multidot<float>(n, c->Vin32, ld, cc, nullptr, ld, 0, c->Y32 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
-      }
-    } else if (cfg.prec == ISIRA_FP64) {
-      launch_multidot<double>(n, c->Vin64, ld, cc, nullptr, ld, 0, c->Vin64 + (size_t)cnew * ld, c->dinv64, 0, 0, c->hbuf, c->rb, s);
     } else {
-      launch_multidot<float>(n, c->Vin32, ld, cc, nullptr, ld, 0, c->Vin32 + (size_t)cnew * ld, c->dinv32, 0, 0, c->hbuf, c->rb, s);
+      for (int j = 0; j < k0; ++j) {
+        double nrm[2];
+        do {
+          launch_fill_replacement(n, opt.seed, draws++, c->d_perm, c->z64, s);
+          if ((rc = cgs2(c, c->U, j, c->Vout, 0, c->z64, nrm))) return rc;
+        } while (!(nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0));
+        launch_scale(n, c->z64, 1.0 / nrm[1], c->U + (size_t)j * ld, s);
+      }
     }
-    int r2 = read_h(c, cc);
-    if (r2) return r2;
-    SYNC_OR_RETURN(c);
-    for (int i = 0; i < cc; ++i) {
-      Cmat[i + (size_t)cnew * kMaxC] = c->hbuf_host[i];
-      Cmat[cnew + (size_t)i * kMaxC] = c->hbuf_host[i];
-    }
-    std::vector<double> G((size_t)cc * cc), Gi;
-    for (int j = 0; j < cc; ++j)
-      for (int i = 0; i < cc; ++i)
-        G[i + (size_t)j * cc] = (i == j ? 1.0 : 0.0) + delta * Cmat[i + (size_t)j * kMaxC];
-    if (!spd_inverse(cc, G, Gi)) return fail(ISIRA_E_PRECOND, "SMW capacitance matrix not positive definite");
-    return upload(c, c->Ginv, Gi.data(), Gi.size() * 8);
-  };
-
-  auto expand_with = [&](double* z) -> int {
-    // orthonormalize z against [U V 1] and append u, w = (L + delta V V^T) u and the new
-    // column of H.  Everything is queued behind one wait; on a CGS2 breakdown (rare) the
-    // queued results are discarded and a replacement vector is expanded instead.
-    double nrm[2];
-    int r2;
-    double t0 = now_ms();
-    double* u = c->U + (size_t)kk * ld;
-    double* w = c->W + (size_t)kk * ld;
-    for (;;) {
-      if ((r2 = cgs2_queue(c, c->U, kk, c->Vout, nconv, z, /*selective=*/true))) return r2;
-      launch_scale_dev(n, z, c->st->red + 2, u, s);
-      if (nconv > 0)
-        launch_multidot<double>(n, c->Vout, ld, nconv, nullptr, ld, 0, u, nullptr, 0, 0, c->hbuf, c->rb, s);
-      spmv64(c, u, w, c->Vout, nconv, c->hbuf, delta, 0, 0.0);
-      launch_multidot<double>(n, c->U, ld, kk + 1, nullptr, ld, 0, w, nullptr, 0, 0, c->hbuf, c->rb, s);
-      if ((r2 = read_h(c, kk + 1))) return r2;
-      if ((r2 = sync_state(c))) return r2;
+    int kk = k0;  // current basis size
+    std::vector<double> H((size_t)m * m, 0.0);  // column-major, leading dimension m
+    for (int j = 0; j < kk; ++j) {
+      spmv64(c, c->U + (size_t)j * ld, c->W + (size_t)j * ld, nullptr, 0, nullptr, 0.0, 0, 0.0);
       S.spmv_total++;
-      cgs2_norms(c, kk + nconv, nrm);
-      if (nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0) break;
-      S.breakdowns++;
-      launch_fill_replacement(n, opt.seed, draws++, c->d_perm, z, s);
     }
-    for (int i = 0; i <= kk; ++i) {
-      H[i + (size_t)kk * m] = c->hbuf_host[i];
-      H[kk + (size_t)i * m] = c->hbuf_host[i];
+    for (int j = 0; j < kk; ++j) {
+      launch_multidot<double>(n, c->U, ld, kk, nullptr, ld, 0, c->W + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+      if ((rc = read_h(c, kk))) return rc;
+      SYNC_OR_RETURN(c);
+      for (int i = 0; i < kk; ++i) H[i + (size_t)j * m] = c->hbuf_host[i];
     }
-    kk += 1;
-    S.ms_ortho += now_ms() - t0;
-    return ISIRA_OK;
-  };
+    for (int i = 0; i < kk; ++i)
+      for (int j = 0; j < i; ++j) {
+        const double v = 0.5 * (H[i + (size_t)j * m] + H[j + (size_t)i * m]);
+        H[i + (size_t)j * m] = H[j + (size_t)i * m] = v;
+      }
 
-  int recent_its[4];
-  std::fill(recent_its, recent_its + 4, cfg.check_every);
-  int n_inner = 0;
-  auto start_inner = [&]() {
-    // the right-hand side is the Ritz residual in r64; its sum is st->red[1]
-    if (cfg.prec == ISIRA_FP64) {
-      inner_pcg_start<double>(c, cfg, c->r64, 0.0, c->st->red + 1, nconv);
-    } else {
-      inner_pcg_start<float>(c, cfg, c->r64, 0.0, c->st->red + 1, nconv);
-    }
-  };
+    int nconv = 0;
+    std::vector<double> Hk, theta, Sm, Spack;
+    std::vector<double> Cmat;  // c x c Gram V-hat^T M^-1 V-hat (column-major, ld kMaxC)
+    Cmat.assign((size_t)kMaxC * kMaxC, 0.0);
+    int outer = 0;
+    int its_pair = 0;
+    int64_t inner_pair = 0;
+    bool not_conv = false;
 
-  while (nconv < k) {
-    if (outer >= max_outer) {
-      not_conv = true;
-      break;
-    }
-    outer++;
-    its_pair++;
-    S.basis_cols_total += kk + nconv;
-    // ---- Rayleigh-Ritz: the eigenvalues of H (ascending) and the eigenvector of the
-    // smallest; all eigenvectors only when a pair is locked or the basis restarts
-    double t0 = now_ms();
-    Hk.assign((size_t)kk * kk, 0.0);
-    for (int j = 0; j < kk; ++j)
-      for (int i = 0; i < kk; ++i) Hk[i + (size_t)j * kk] = H[i + (size_t)j * m];
-    theta.assign(kk, 0.0);
-    Sm.assign((size_t)kk * kk, 0.0);
-    if ((rc = isira_symeig_lowest(kk, Hk.data(), theta.data(), Sm.data())))
-      return fail(rc, "Rayleigh-Ritz eigensolver did not converge");
-    bool all_vectors = false;
-    auto rayleigh_ritz_all = [&]() -> int {
-      if (all_vectors) return ISIRA_OK;
-      const double t1 = now_ms();
-      const int r2 = isira_symeig(kk, Hk.data(), theta.data(), Sm.data());
-      S.ms_rr_host += now_ms() - t1;
-      if (r2) return fail(r2, "Rayleigh-Ritz eigensolver did not converge");
-      all_vectors = true;
+    auto refresh_smw = [&](int cnew) -> int {
+      // new column cnew of C = V-hat^T P0 V-hat (P0 = M^-1 Jacobi or learned M); then G^-1
+      const int cc = cnew + 1;
+      if (cfg.precond == ISIRA_PC_MULTILEVEL) {
+        if (cfg.prec == ISIRA_FP64) {
+          ml::apply<double>(c->ml, c->Vin64 + (size_t)cnew * ld, c->Y64 + (size_t)cnew * ld, 0, c->st, c->rb, s);
+          launch_multidot<double>(n, c->Vin64, ld, cc, nullptr, ld, 0, c->Y64 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+        } else {
+          ml::apply<float>(c->ml, c->Vin32 + (size_t)cnew * ld, c->Y32 + (size_t)cnew * ld, 0, c->st, c->rb, s);
+          launch_multidot<float>(n, c->Vin32, ld, cc, nullptr, ld, 0, c->Y32 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+        }
+      } else if (cfg.precond == ISIRA_PC_LEARNED) {
+        if (cfg.prec == ISIRA_FP64) {
+          spai::apply_plain<double>(c->spw, c->plan, c->rp, c->col,
+                                    c->Vin64 + (size_t)cnew * ld, c->Y64 + (size_t)cnew * ld, n, trim, s);
+          launch_multidot<double>(n, c->Vin64, ld, cc, nullptr, ld, 0, c->Y64 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+        } else {
+          spai::apply_plain<float>(c->spw, c->plan, c->rp, c->col,
+                                   c->Vin32 + (size_t)cnew * ld, c->Y32 + (size_t)cnew * ld, n, trim, s);
+          launch_multidot<float>(n, c->Vin32, ld, cc, nullptr, ld, 0, c->Y32 + (size_t)cnew * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+        }
+      } else if (cfg.prec == ISIRA_FP64) {
+        launch_multidot<double>(n, c->Vin64, ld, cc, nullptr, ld, 0, c->Vin64 + (size_t)cnew * ld, c->dinv64, 0, 0, c->hbuf, c->rb, s);
+      } else {
+        launch_multidot<float>(n, c->Vin32, ld, cc, nullptr, ld, 0, c->Vin32 + (size_t)cnew * ld, c->dinv32, 0, 0, c->hbuf, c->rb, s);
+      }
+      int r2 = read_h(c, cc);
+      if (r2) return r2;
+      SYNC_OR_RETURN(c);
+      for (int i = 0; i < cc; ++i) {
+        Cmat[i + (size_t)cnew * kMaxC] = c->hbuf_host[i];
+        Cmat[cnew + (size_t)i * kMaxC] = c->hbuf_host[i];
+      }
+      std::vector<double> G((size_t)cc * cc), Gi;
+      for (int j = 0; j < cc; ++j)
+        for (int i = 0; i < cc; ++i)
+          G[i + (size_t)j * cc] = (i == j ? 1.0 : 0.0) + delta * Cmat[i + (size_t)j * kMaxC];
+      if (!spd_inverse(cc, G, Gi)) return fail(ISIRA_E_PRECOND, "SMW capacitance matrix not positive definite");
+      return upload(c, c->Ginv, Gi.data(), Gi.size() * 8);
+    };
+
+    auto expand_with = [&](double* z) -> int {
+      // orthonormalize z against [U V 1] and append u, w = (L + delta V V^T) u and the new
+      // column of H.  Everything is queued behind one wait; on a CGS2 breakdown (rare) the
+      // queued results are discarded and a replacement vector is expanded instead.
+      double nrm[2];
+      int r2;
+      double t0 = now_ms();
+      double* u = c->U + (size_t)kk * ld;
+      double* w = c->W + (size_t)kk * ld;
+      for (;;) {
+        if ((r2 = cgs2_queue(c, c->U, kk, c->Vout, nconv, z, /*selective=*/true))) return r2;
+        launch_scale_dev(n, z, c->st->red + 2, u, s);
+        if (nconv > 0)
+          launch_multidot<double>(n, c->Vout, ld, nconv, nullptr, ld, 0, u, nullptr, 0, 0, c->hbuf, c->rb, s);
+        spmv64(c, u, w, c->Vout, nconv, c->hbuf, delta, 0, 0.0);
+        launch_multidot<double>(n, c->U, ld, kk + 1, nullptr, ld, 0, w, nullptr, 0, 0, c->hbuf, c->rb, s);
+        if ((r2 = read_h(c, kk + 1))) return r2;
+        if ((r2 = sync_state(c))) return r2;
+        S.spmv_total++;
+        cgs2_norms(c, kk + nconv, nrm);
+        if (nrm[1] > 1e-10 * nrm[0] && nrm[1] > 0.0) break;
+        S.breakdowns++;
+        launch_fill_replacement(n, opt.seed, draws++, c->d_perm, z, s);
+      }
+      for (int i = 0; i <= kk; ++i) {
+        H[i + (size_t)kk * m] = c->hbuf_host[i];
+        H[kk + (size_t)i * m] = c->hbuf_host[i];
+      }
+      kk += 1;
+      S.ms_ortho += now_ms() - t0;
       return ISIRA_OK;
     };
-    S.ms_rr_host += now_ms() - t0;
-    // ---- Ritz residual r = W s1 - theta1 U s1.  The inner solve for it is queued at once,
-    // behind the same wait: when the pair turns out converged that work is simply dropped.
-    t0 = now_ms();
-    if ((rc = upload(c, c->svec, Sm.data(), kk * 8))) return rc;
-    CKH(hipEventRecord(ev.a, s));
-    launch_ritz_residual(n, c->U, c->W, ld, kk, c->svec, theta[0], c->r64, c->st, c->rb, s);
-    CKH(hipEventRecord(ev.b, s));
-    start_inner();
-    if ((rc = sync_state(c))) return rc;
-    const double rn = std::sqrt(std::max(0.0, c->st_host->red[0]));
-    {
-      float ms_res = 0.0f;
-      CKH(hipEventElapsedTime(&ms_res, ev.a, ev.b));
-      const double window = now_ms() - t0;
-      S.ms_residual += std::min((double)ms_res, window);
-      S.ms_inner += std::max(0.0, window - (double)ms_res);
-    }
-    if (rn < tol) {
-      // the lock purges with S(:, 2:kk), so the locked vector is taken from the same full
-      // decomposition; its fresh FP64 residual decides
-      if ((rc = rayleigh_ritz_all())) return rc;
+
+    int recent_its[4];
+    std::fill(recent_its, recent_its + 4, cfg.check_every);
+    int n_inner = 0;
+    auto start_inner = [&]() {
+      // the right-hand side is the Ritz residual in r64; its sum is st->red[1]
+      if (cfg.prec == ISIRA_FP64) {
+        inner_pcg_start<double>(c, cfg, c->r64, 0.0, c->st->red + 1, nconv);
+      } else {
+        inner_pcg_start<float>(c, cfg, c->r64, 0.0, c->st->red + 1, nconv);
+      }
+    };
+
+    while (nconv < k) {
+      if (outer >= max_outer) {
+        not_conv = true;
+        break;
+      }
+      outer++;
+      its_pair++;
+      S.basis_cols_total += kk + nconv;
+      // ---- Rayleigh-Ritz: the eigenvalues of H (ascending) and the eigenvector of the
+      // smallest; all eigenvectors only when a pair is locked or the basis restarts
+      double t0 = now_ms();
+      Hk.assign((size_t)kk * kk, 0.0);
+      for (int j = 0; j < kk; ++j)
+        for (int i = 0; i < kk; ++i) Hk[i + (size_t)j * kk] = H[i + (size_t)j * m];
+      theta.assign(kk, 0.0);
+      Sm.assign((size_t)kk * kk, 0.0);
+      if ((rc = isira_symeig_lowest(kk, Hk.data(), theta.data(), Sm.data())))
+        return fail(rc, "Rayleigh-Ritz eigensolver did not converge");
+      bool all_vectors = false;
+      auto rayleigh_ritz_all = [&]() -> int {
+        if (all_vectors) return ISIRA_OK;
+        const double t1 = now_ms();
+        const int r2 = isira_symeig(kk, Hk.data(), theta.data(), Sm.data());
+        S.ms_rr_host += now_ms() - t1;
+        if (r2) return fail(r2, "Rayleigh-Ritz eigensolver did not converge");
+        all_vectors = true;
+        return ISIRA_OK;
+      };
+      S.ms_rr_host += now_ms() - t0;
+      // ---- Ritz residual r = W s1 - theta1 U s1.  The inner solve for it is queued at once,
+      // behind the same wait: when the pair turns out converged that work is simply dropped.
+      t0 = now_ms();
       if ((rc = upload(c, c->svec, Sm.data(), kk * 8))) return rc;
-      double* v = c->Vout + (size_t)nconv * ld;
-      launch_ritz_vector(n, c->U, ld, kk, c->svec, v, s);
-      spmv64(c, v, c->tmp64, nullptr, 0, nullptr, 0.0, 2, theta[0]);
-      S.spmv_total++;
+      CKH(hipEventRecord(ev.a, s));
+      launch_ritz_residual(n, c->U, c->W, ld, kk, c->svec, theta[0], c->r64, c->st, c->rb, s);
+      CKH(hipEventRecord(ev.b, s));
+      start_inner();
       if ((rc = sync_state(c))) return rc;
-      const double true_r = std::sqrt(std::max(0.0, c->st_host->red[0]));
-      if (true_r < tol) {
-        evals[nconv] = theta[0];
-        resid[nconv] = true_r;
-        if (nconv < ISIRA_STATS_MAX) {
-          S.outer_per_pair[nconv] = its_pair;
-          S.inner_per_pair[nconv] = (int32_t)inner_pair;
-        }
-        if (opt.verbose)
-          fprintf(stderr, "isira: pair %d lambda=%.15g resid=%.3e outer=%d inner=%lld\n", nconv,
-                  theta[0], true_r, its_pair, (long long)inner_pair);
-        its_pair = 0;
-        inner_pair = 0;
-        launch_masked_copy<double>(n, v, trim, c->Vin64 + (size_t)nconv * ld, s);
-        launch_masked_copy<float>(n, v, trim, c->Vin32 + (size_t)nconv * ld, s);
-        // eigenvector purging: U <- U S(:, 2:k), W <- W S(:, 2:k), H <- diag(theta_2..)
-        t0 = now_ms();
-        if (kk > 1) {
-          // S(:, 2:kk) row by row for the tall-skinny product
-          Spack.assign((size_t)kk * (kk - 1), 0.0);
-          for (int j = 1; j < kk; ++j)
-            for (int i = 0; i < kk; ++i) Spack[(size_t)i * (kk - 1) + (j - 1)] = Sm[i + (size_t)j * kk];
-          if ((rc = upload(c, c->Sdev, Spack.data(), Spack.size() * 8))) return rc;
-          launch_tsgemm_inplace(n, c->U, ld, kk, c->Sdev, kk - 1, s);
-          launch_tsgemm_inplace(n, c->W, ld, kk, c->Sdev, kk - 1, s);
-        }
-        std::fill(H.begin(), H.end(), 0.0);
-        for (int j = 1; j < kk; ++j) H[(j - 1) + (size_t)(j - 1) * m] = theta[j];
-        kk -= 1;
-        S.ms_restart += now_ms() - t0;
-        nconv += 1;
-        if (nconv < k) {
-          // the purge step's moving shift: sigma <- theta_2 (capped); the Jacobi diagonal
-          // and the whole SMW capacitance matrix then change with it
-          const double sigma_new = (moving && kk >= 1) ? std::min(theta[1], sigma_cap) : cfg.sigma;
-          if (sigma_new != cfg.sigma) {
-            cfg.sigma = sigma_new;
-            launch_dinv<double>(n, c->deg, cfg.sigma, trim, c->dinv64, s);
-            launch_dinv<float>(n, c->deg, cfg.sigma, trim, c->dinv32, s);
-            for (int j = 0; j < nconv; ++j)
-              if ((rc = refresh_smw(j))) return rc;
-          } else if ((rc = refresh_smw(nconv - 1))) {
-            return rc;
+      const double rn = std::sqrt(std::max(0.0, c->st_host->red[0]));
+      {
+        float ms_res = 0.0f;
+        CKH(hipEventElapsedTime(&ms_res, ev.a, ev.b));
+        const double window = now_ms() - t0;
+        S.ms_residual += std::min((double)ms_res, window);
+        S.ms_inner += std::max(0.0, window - (double)ms_res);
+      }
+      if (rn < tol) {
+        // the lock purges with S(:, 2:kk), so the locked vector is taken from the same full
+        // decomposition; its fresh FP64 residual decides
+        if ((rc = rayleigh_ritz_all())) return rc;
+        if ((rc = upload(c, c->svec, Sm.data(), kk * 8))) return rc;
+        double* v = c->Vout + (size_t)nconv * ld;
+        launch_ritz_vector(n, c->U, ld, kk, c->svec, v, s);
+        spmv64(c, v, c->tmp64, nullptr, 0, nullptr, 0.0, 2, theta[0]);
+        S.spmv_total++;
+        if ((rc = sync_state(c))) return rc;
+        const double true_r = std::sqrt(std::max(0.0, c->st_host->red[0]));
+        if (true_r < tol) {
+          evals[nconv] = theta[0];
+          resid[nconv] = true_r;
+          if (nconv < ISIRA_STATS_MAX) {
+            S.outer_per_pair[nconv] = its_pair;
+            S.inner_per_pair[nconv] = (int32_t)inner_pair;
           }
-          if (kk == 0) {  // empty basis: start again from a replacement vector
-            launch_fill_replacement(n, opt.seed, draws++, c->d_perm, c->z64, s);
-            if ((rc = expand_with(c->z64))) return rc;
+          if (opt.verbose)
+            fprintf(stderr, "isira: pair %d lambda=%.15g resid=%.3e outer=%d inner=%lld\n", nconv,
+                    theta[0], true_r, its_pair, (long long)inner_pair);
+          its_pair = 0;
+          inner_pair = 0;
+          launch_masked_copy<double>(n, v, trim, c->Vin64 + (size_t)nconv * ld, s);
+          launch_masked_copy<float>(n, v, trim, c->Vin32 + (size_t)nconv * ld, s);
+          // eigenvector purging: U <- U S(:, 2:k), W <- W S(:, 2:k), H <- diag(theta_2..)
+          t0 = now_ms();
+          if (kk > 1) {
+            // S(:, 2:kk) row by row for the tall-skinny product
+            Spack.assign((size_t)kk * (kk - 1), 0.0);
+            for (int j = 1; j < kk; ++j)
+              for (int i = 0; i < kk; ++i) Spack[(size_t)i * (kk - 1) + (j - 1)] = Sm[i + (size_t)j * kk];
+            if ((rc = upload(c, c->Sdev, Spack.data(), Spack.size() * 8))) return rc;
+            launch_tsgemm_inplace(n, c->U, ld, kk, c->Sdev, kk - 1, s);
+            launch_tsgemm_inplace(n, c->W, ld, kk, c->Sdev, kk - 1, s);
           }
+          std::fill(H.begin(), H.end(), 0.0);
+          for (int j = 1; j < kk; ++j) H[(j - 1) + (size_t)(j - 1) * m] = theta[j];
+          kk -= 1;
+          S.ms_restart += now_ms() - t0;
+          nconv += 1;
+          if (nconv < k) {
+            // the purge step's moving shift: sigma <- theta_2 (capped); the Jacobi diagonal
+            // and the whole SMW capacitance matrix then change with it
+            const double sigma_new = (moving && kk >= 1) ? std::min(theta[1], sigma_cap) : cfg.sigma;
+            if (sigma_new != cfg.sigma) {
+              cfg.sigma = sigma_new;
+              launch_dinv<double>(n, c->deg, cfg.sigma, trim, c->dinv64, s);
+              launch_dinv<float>(n, c->deg, cfg.sigma, trim, c->dinv32, s);
+              for (int j = 0; j < nconv; ++j)
+                if ((rc = refresh_smw(j))) return rc;
+            } else if ((rc = refresh_smw(nconv - 1))) {
+              return rc;
+            }
+            if (kk == 0) {  // empty basis: start again from a replacement vector
+              launch_fill_replacement(n, opt.seed, draws++, c->d_perm, c->z64, s);
+              if ((rc = expand_with(c->z64))) return rc;
+            }
+          }
+          continue;
         }
+        // the carried W has drifted: recompute W = (L + delta V V^T) U and H = U^T W
+        S.refreshes++;
+        for (int j = 0; j < kk; ++j) {
+          if (nconv > 0)
+            launch_multidot<double>(n, c->Vout, ld, nconv, nullptr, ld, 0, c->U + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+          spmv64(c, c->U + (size_t)j * ld, c->W + (size_t)j * ld, c->Vout, nconv, c->hbuf, delta, 0, 0.0);
+          S.spmv_total++;
+        }
+        for (int j = 0; j < kk; ++j) {
+          launch_multidot<double>(n, c->U, ld, kk, nullptr, ld, 0, c->W + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+          if ((rc = read_h(c, kk))) return rc;
+          if ((rc = stream_sync(c))) return rc;
+          for (int i = 0; i < kk; ++i) H[i + (size_t)j * m] = c->hbuf_host[i];
+        }
+        for (int i = 0; i < kk; ++i)
+          for (int j = 0; j < i; ++j) {
+            const double v2 = 0.5 * (H[i + (size_t)j * m] + H[j + (size_t)i * m]);
+            H[i + (size_t)j * m] = H[j + (size_t)i * m] = v2;
+          }
         continue;
       }
-      // the carried W has drifted: recompute W = (L + delta V V^T) U and H = U^T W
-      S.refreshes++;
-      for (int j = 0; j < kk; ++j) {
-        if (nconv > 0)
-          launch_multidot<double>(n, c->Vout, ld, nconv, nullptr, ld, 0, c->U + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
-        spmv64(c, c->U + (size_t)j * ld, c->W + (size_t)j * ld, c->Vout, nconv, c->hbuf, delta, 0, 0.0);
-        S.spmv_total++;
+      if (kk == m) {
+        // subspace restart: U <- U S(:, 1:q), W <- W S(:, 1:q), H <- diag(theta_1..theta_q)
+        // (the queued inner solve reads neither U nor W)
+        if ((rc = rayleigh_ritz_all())) return rc;
+        t0 = now_ms();
+        S.restarts++;
+        Spack.assign((size_t)kk * q, 0.0);
+        for (int j = 0; j < q; ++j)
+          for (int i = 0; i < kk; ++i) Spack[(size_t)i * q + j] = Sm[i + (size_t)j * kk];
+        if ((rc = upload(c, c->Sdev, Spack.data(), Spack.size() * 8))) return rc;
+        launch_tsgemm_inplace(n, c->U, ld, kk, c->Sdev, q, s);
+        launch_tsgemm_inplace(n, c->W, ld, kk, c->Sdev, q, s);
+        std::fill(H.begin(), H.end(), 0.0);
+        for (int j = 0; j < q; ++j) H[j + (size_t)j * m] = theta[j];
+        kk = q;
+        S.ms_restart += now_ms() - t0;
       }
-      for (int j = 0; j < kk; ++j) {
-        launch_multidot<double>(n, c->U, ld, kk, nullptr, ld, 0, c->W + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
-        if ((rc = read_h(c, kk))) return rc;
-        if ((rc = stream_sync(c))) return rc;
-        for (int i = 0; i < kk; ++i) H[i + (size_t)j * m] = c->hbuf_host[i];
-      }
-      for (int i = 0; i < kk; ++i)
-        for (int j = 0; j < i; ++j) {
-          const double v2 = 0.5 * (H[i + (size_t)j * m] + H[j + (size_t)i * m]);
-          H[i + (size_t)j * m] = H[j + (size_t)i * m] = v2;
-        }
-      continue;
-    }
-    if (kk == m) {
-      // subspace restart: U <- U S(:, 1:q), W <- W S(:, 1:q), H <- diag(theta_1..theta_q)
-      // (the queued inner solve reads neither U nor W)
-      if ((rc = rayleigh_ritz_all())) return rc;
+      // ---- subspace expansion: trimmed deflated inner solve, enlargement (2.5)
       t0 = now_ms();
-      S.restarts++;
-      Spack.assign((size_t)kk * q, 0.0);
-      for (int j = 0; j < q; ++j)
-        for (int i = 0; i < kk; ++i) Spack[(size_t)i * q + j] = Sm[i + (size_t)j * kk];
-      if ((rc = upload(c, c->Sdev, Spack.data(), Spack.size() * 8))) return rc;
-      launch_tsgemm_inplace(n, c->U, ld, kk, c->Sdev, q, s);
-      launch_tsgemm_inplace(n, c->W, ld, kk, c->Sdev, q, s);
-      std::fill(H.begin(), H.end(), 0.0);
-      for (int j = 0; j < q; ++j) H[j + (size_t)j * m] = theta[j];
-      kk = q;
-      S.ms_restart += now_ms() - t0;
-    }
-    // ---- subspace expansion: trimmed deflated inner solve, enlargement (2.5)
-    t0 = now_ms();
-    int its = 0, status = 0;
-    double rel = 0.0;
-    if (cfg.prec == ISIRA_FP64) {
-      rc = inner_pcg_finish<double>(c, cfg, nconv, true, &its, &status, &rel);
-    } else {
-      rc = inner_pcg_finish<float>(c, cfg, nconv, true, &its, &status, &rel);
-    }
-    if (rc) return rc;
-    // the next inner solve queues as many iterations with its set-up as the most any of
-    // the last four took: launches past convergence return at once, each round trip
-    // to the host for another batch costs a wait
-    recent_its[n_inner++ & 3] = its;
-    cfg.first_batch = std::max(1, std::min(cfg.check_every,
-                                           *std::max_element(recent_its, recent_its + 4)));
-    if (status == kPcgBreakdown) S.inner_fallbacks++;
-    if (status == kPcgCapped) S.inner_capped++;
-    S.inner_total += its;
-    S.spmv_total += its;
-    inner_pair += its;
-    if (cfg.prec == ISIRA_FP64) {
-      launch_enlarge<double>(n, c->x64, c->z64, c->st, c->rb, s);
-    } else {
-      launch_enlarge<float>(n, c->x32, c->z64, c->st, c->rb, s);
-    }
-    if (opt.capture_r && opt.capture_z && opt.capture_count && capture_count < opt.capture_cap) {
-      double* cr = opt.capture_r + (size_t)capture_count * n;
-      double* cz = opt.capture_z + (size_t)capture_count * n;
-      // z_hat (trimmed entry 0) and r' = (L-hat - sigma I) z_hat: the pair that an
-      // approximate inverse of L-hat - sigma I should map onto each other
-      const double* zin = c->x64;
-      if (cfg.prec != ISIRA_FP64) {
-        launch_gather<float, double>(n, c->x32, c->d_iperm, cz, s);
-        launch_gather<double, double>(n, cz, c->d_perm, c->y64, s);
-        zin = c->y64;
+      int its = 0, status = 0;
+      double rel = 0.0;
+      if (cfg.prec == ISIRA_FP64) {
+        rc = inner_pcg_finish<double>(c, cfg, nconv, true, &its, &status, &rel);
       } else {
-        launch_gather<double, double>(n, c->x64, c->d_iperm, cz, s);
+        rc = inner_pcg_finish<float>(c, cfg, nconv, true, &its, &status, &rel);
       }
-      SpmvArgs<double> ca{};
-      ca.rp = c->rp; ca.col = c->col; ca.vals = c->w64; ca.x = zin; ca.y = c->tmp64;
-      ca.diag = c->deg; ca.n = n; ca.trim = trim; ca.sigma = cfg.sigma;
-      launch_spmv<double>(c->plan, valmode64(c), ca, c->rb, s);
-      launch_gather<double, double>(n, c->tmp64, c->d_iperm, cr, s);
-      capture_count++;
-      *opt.capture_count = capture_count;
+      if (rc) return rc;
+      // the next inner solve queues as many iterations with its set-up as the most any of
+      // the last four took: launches past convergence return at once, each round trip
+      // to the host for another batch costs a wait
+      recent_its[n_inner++ & 3] = its;
+      cfg.first_batch = std::max(1, std::min(cfg.check_every,
+                                             *std::max_element(recent_its, recent_its + 4)));
+      if (status == kPcgBreakdown) S.inner_fallbacks++;
+      if (status == kPcgCapped) S.inner_capped++;
+      S.inner_total += its;
+      S.spmv_total += its;
+      inner_pair += its;
+      if (cfg.prec == ISIRA_FP64) {
+        launch_enlarge<double>(n, c->x64, c->z64, c->st, c->rb, s);
+      } else {
+        launch_enlarge<float>(n, c->x32, c->z64, c->st, c->rb, s);
+      }
+      if (opt.capture_r && opt.capture_z && opt.capture_count && capture_count < opt.capture_cap) {
+        double* cr = opt.capture_r + (size_t)capture_count * n;
+        double* cz = opt.capture_z + (size_t)capture_count * n;
+        // z_hat (trimmed entry 0) and r' = (L-hat - sigma I) z_hat: the pair that an
+        // approximate inverse of L-hat - sigma I should map onto each other
+        const double* zin = c->x64;
+        if (cfg.prec != ISIRA_FP64) {
+          launch_gather<float, double>(n, c->x32, c->d_iperm, cz, s);
+          launch_gather<double, double>(n, cz, c->d_perm, c->y64, s);
+          zin = c->y64;
+        } else {
+          launch_gather<double, double>(n, c->x64, c->d_iperm, cz, s);
+        }
+        SpmvArgs<double> ca{};
+        ca.rp = c->rp; ca.col = c->col; ca.vals = c->w64; ca.x = zin; ca.y = c->tmp64;
+        ca.diag = c->deg; ca.n = n; ca.trim = trim; ca.sigma = cfg.sigma;
+        launch_spmv<double>(c->plan, valmode64(c), ca, c->rb, s);
+        launch_gather<double, double>(n, c->tmp64, c->d_iperm, cr, s);
+        capture_count++;
+        *opt.capture_count = capture_count;
+      }
+      S.ms_inner += now_ms() - t0;
+      if ((rc = expand_with(c->z64))) return rc;
     }
-    S.ms_inner += now_ms() - t0;
-    if ((rc = expand_with(c->z64))) return rc;
-  }
-  // ---- outputs: sign-normalized eigenvectors in caller labels
-  for (int j = 0; j < nconv; ++j) {
-    double* v = c->Vout + (size_t)j * ld;
-    launch_signed_gather(n, v, c->d_perm, c->d_iperm, evecs + (size_t)j * n, c->scal4, c->rb, s);
-  }
-  SYNC_OR_RETURN(c);
-  S.n_converged = nconv;
-  S.outer_total = outer;
-  S.ms_total = now_ms() - t_start;
-  S.trim_index = c->perm[trim];
-  S.delta = delta;
-  S.sigma_last = cfg.sigma;
-  if (stats) *stats = S;
-  return not_conv ? ISIRA_NOT_CONVERGED : ISIRA_OK;
+    // ---- outputs: sign-normalized eigenvectors in caller labels
+    for (int j = 0; j < nconv; ++j) {
+      double* v = c->Vout + (size_t)j * ld;
+      launch_signed_gather(n, v, c->d_perm, c->d_iperm, evecs + (size_t)j * n, c->scal4, c->rb, s);
+    }
+    SYNC_OR_RETURN(c);
+    S.n_converged = nconv;
+    S.outer_total = outer;
+    S.ms_total = now_ms() - t_start;
+    S.trim_index = c->perm[trim];
+    S.delta = delta;
+    S.sigma_last = cfg.sigma;
+    if (stats) *stats = S;
+    return not_conv ? ISIRA_NOT_CONVERGED : ISIRA_OK;
+  });
 }
 
 // ------------------------------------------------------------------------------ operators
 
 extern "C" int isira_laplacian_apply(isira_ctx* c, const double* x, double* y) {
-  if (!c || !x || !y) return fail(ISIRA_E_ARG, "NULL argument");
-  int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
-  if (rc) return rc;
-  const int n = (int)c->n;
-  launch_gather<double, double>(n, x, c->d_perm, c->x64, c->stream);
-  spmv64(c, c->x64, c->y64, nullptr, 0, nullptr, 0.0, 0, 0.0);
-  launch_gather<double, double>(n, c->y64, c->d_iperm, y, c->stream);
-  SYNC_OR_RETURN(c);
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c || !x || !y) return fail(ISIRA_E_ARG, "NULL argument");
+    int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
+    if (rc) return rc;
+    const int n = (int)c->n;
+    launch_gather<double, double>(n, x, c->d_perm, c->x64, c->stream);
+    spmv64(c, c->x64, c->y64, nullptr, 0, nullptr, 0.0, 0, 0.0);
+    launch_gather<double, double>(n, c->y64, c->d_iperm, y, c->stream);
+    SYNC_OR_RETURN(c);
+    return ISIRA_OK;
+  });
 }
 
 extern "C" int isira_laplacian_apply_f32(isira_ctx* c, const float* x, float* y) {
-  if (!c || !x || !y) return fail(ISIRA_E_ARG, "NULL argument");
-  int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
-  if (rc) return rc;
-  const int n = (int)c->n;
-  launch_gather<float, float>(n, x, c->d_perm, c->x32, c->stream);
-  SpmvArgs<float> a{};
-  a.rp = c->rp;
-  a.col = c->col;
-  a.vals = c->w32;
-  a.x = c->x32;
-  a.y = c->y32;
-  a.diag = c->deg32;
-  a.n = n;
-  a.trim = -1;
-  launch_spmv<float>(c->plan, valmode32(c), a, c->rb, c->stream);
-  launch_gather<float, float>(n, c->y32, c->d_iperm, y, c->stream);
-  SYNC_OR_RETURN(c);
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c || !x || !y) return fail(ISIRA_E_ARG, "NULL argument");
+    int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
+    if (rc) return rc;
+    const int n = (int)c->n;
+    launch_gather<float, float>(n, x, c->d_perm, c->x32, c->stream);
+    SpmvArgs<float> a{};
+    a.rp = c->rp;
+    a.col = c->col;
+    a.vals = c->w32;
+    a.x = c->x32;
+    a.y = c->y32;
+    a.diag = c->deg32;
+    a.n = n;
+    a.trim = -1;
+    launch_spmv<float>(c->plan, valmode32(c), a, c->rb, c->stream);
+    launch_gather<float, float>(n, c->y32, c->d_iperm, y, c->stream);
+    SYNC_OR_RETURN(c);
+    return ISIRA_OK;
+  });
 }
 
 extern "C" int isira_time_spmv(isira_ctx* c, int32_t prec, int32_t reps, int32_t cold,
                                double* ms_per) {
-  if (!c || reps < 1 || !ms_per) return fail(ISIRA_E_ARG, "bad argument");
-  int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
-  if (rc) return rc;
-  const int n = (int)c->n;
-  hipStream_t s = c->stream;
-  launch_fill_replacement(n, 7, 0, c->d_perm, c->x64, s);
-  launch_gather<double, float>(n, c->x64, c->d_iperm, c->x32, s);  // any FP32 data will do
-  // cold: before every timed launch, read and write a buffer of twice the 256 MB memory-side
-  // cache, so that no launch finds the graph or x in a cache left warm by the one before
-  constexpr size_t kFlush = (size_t)512 << 20;
-  double* flush = nullptr;
-  if (cold && (rc = dalloc(c->mem, &flush, kFlush / 8))) return rc;
-  if (flush) CKH(hipMemsetAsync(flush, 0, kFlush, s));
-  hipEvent_t e0, e1;
-  CKH(hipEventCreate(&e0));
-  CKH(hipEventCreate(&e1));
-  SpmvArgs<float> a32{};
-  a32.rp = c->rp; a32.col = c->col; a32.vals = c->w32; a32.x = c->x32; a32.y = c->y32;
-  a32.diag = c->deg32; a32.n = n; a32.trim = -1;
-  SpmvArgs<double> a64{};
-  a64.rp = c->rp; a64.col = c->col; a64.vals = c->w64; a64.x = c->x64; a64.y = c->y64;
-  a64.diag = c->deg; a64.n = n; a64.trim = -1;
-  auto launch = [&]() {
-    if (prec == ISIRA_FP64) launch_spmv_probe<double>(c->plan, valmode64(c), a64, c->rb.partials, s);
-    else launch_spmv_probe<float>(c->plan, valmode32(c), a32, c->rb.partials, s);
-  };
-  for (int w = 0; w < 3; ++w) launch();
-  double total = 0.0;
-  float ms = 0;
-  if (!cold) {
-    CKH(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) launch();
-    CKH(hipEventRecord(e1, s));
-    CKH(hipEventSynchronize(e1));
-    CKH(hipEventElapsedTime(&ms, e0, e1));
-    total = ms;
-  } else {
-    for (int r = 0; r < reps; ++r) {
-      launch_scale((int)(kFlush / 8), flush, 1.0, flush, s);
+  return guarded([&]() -> int {
+    if (!c || reps < 1 || !ms_per) return fail(ISIRA_E_ARG, "bad argument");
+    int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
+    if (rc) return rc;
+    const int n = (int)c->n;
+    hipStream_t s = c->stream;
+    launch_fill_replacement(n, 7, 0, c->d_perm, c->x64, s);
+    launch_gather<double, float>(n, c->x64, c->d_iperm, c->x32, s);  // any FP32 data will do
+    // cold: before every timed launch, read and write a buffer of twice the 256 MB memory-side
+    // cache, so that no launch finds the graph or x in a cache left warm by the one before
+    constexpr size_t kFlush = (size_t)512 << 20;
+    double* flush = nullptr;
+    if (cold && (rc = dalloc(c->mem, &flush, kFlush / 8))) return rc;
+    if (flush) CKH(hipMemsetAsync(flush, 0, kFlush, s));
+    hipEvent_t e0, e1;
+    CKH(hipEventCreate(&e0));
+    CKH(hipEventCreate(&e1));
+    SpmvArgs<float> a32{};
+    a32.rp = c->rp; a32.col = c->col; a32.vals = c->w32; a32.x = c->x32; a32.y = c->y32;
+    a32.diag = c->deg32; a32.n = n; a32.trim = -1;
+    SpmvArgs<double> a64{};
+    a64.rp = c->rp; a64.col = c->col; a64.vals = c->w64; a64.x = c->x64; a64.y = c->y64;
+    a64.diag = c->deg; a64.n = n; a64.trim = -1;
+    auto launch = [&]() {
+      if (prec == ISIRA_FP64) launch_spmv_probe<double>(c->plan, valmode64(c), a64, c->rb.partials, s);
+      else launch_spmv_probe<float>(c->plan, valmode32(c), a32, c->rb.partials, s);
+    };
+    for (int w = 0; w < 3; ++w) launch();
+    double total = 0.0;
+    float ms = 0;
+    if (!cold) {
       CKH(hipEventRecord(e0, s));
-      launch();
+      for (int r = 0; r < reps; ++r) launch();
       CKH(hipEventRecord(e1, s));
       CKH(hipEventSynchronize(e1));
       CKH(hipEventElapsedTime(&ms, e0, e1));
-      total += ms;
+      total = ms;
+    } else {
+      for (int r = 0; r < reps; ++r) {
+        launch_scale((int)(kFlush / 8), flush, 1.0, flush, s);
+        CKH(hipEventRecord(e0, s));
+        launch();
+        CKH(hipEventRecord(e1, s));
+        CKH(hipEventSynchronize(e1));
+        CKH(hipEventElapsedTime(&ms, e0, e1));
+        total += ms;
+      }
     }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  dfree(c->mem, flush);
-  *ms_per = total / reps;
-  return ISIRA_OK;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dfree(c->mem, flush);
+    *ms_per = total / reps;
+    return ISIRA_OK;
+  });
 }
 
 extern "C" int isira_inner_solve(isira_ctx* c, const double* r, const double* V, int32_t nc,
                                  double sigma, double delta, int64_t trim, double rtol,
                                  int32_t max_it, int32_t prec, int32_t precond, int32_t solver,
                                  double* z, int32_t* iters, double* relres) {
-  if (!c || !r || !z || (nc > 0 && !V)) return fail(ISIRA_E_ARG, "NULL argument");
-  if (nc < 0 || nc > kMaxC || nc > c->n - 3) return fail(ISIRA_E_ARG, "bad c");
-  if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
-  if (prec != ISIRA_FP64 && prec != ISIRA_FP32) return fail(ISIRA_E_ARG, "bad prec");
-  if (precond == ISIRA_PC_LEARNED && !c->has_learned) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
-  if (solver != ISIRA_SOLVER_PCG && solver != ISIRA_SOLVER_MINRES) return fail(ISIRA_E_ARG, "bad solver");
-  if (solver == ISIRA_SOLVER_MINRES && precond != ISIRA_PC_JACOBI)
-    return fail(ISIRA_E_ARG, "MINRES runs with the Jacobi preconditioner only");
-  if (precond != ISIRA_PC_JACOBI && precond != ISIRA_PC_LEARNED && precond != ISIRA_PC_MULTILEVEL)
-    return fail(ISIRA_E_ARG, "bad precond");
-  int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, std::max(1, (int)nc)));
-  if (rc) return rc;
-  const int n = (int)c->n;
-  const int ld = c->ld;
-  hipStream_t s = c->stream;
-  InnerCfg cfg;
-  cfg.prec = prec;
-  cfg.precond = precond;
-  cfg.sigma = sigma;
-  cfg.delta = delta > 0 ? delta : 2.0 * c->max_deg;
-  cfg.rtol = rtol;
-  cfg.trim = trim >= 0 ? c->iperm[trim] : c->trim_default;
-  if (precond == ISIRA_PC_LEARNED && (c->spai_trim != cfg.trim || c->spai_sigma != sigma))
-    return fail(ISIRA_E_PRECOND, "learned preconditioner was installed for another sigma or trim index");
-  if (precond == ISIRA_PC_MULTILEVEL && (!c->ml.ready || c->ml.trim != cfg.trim))
-    return fail(ISIRA_E_PRECOND, "no multilevel hierarchy set up for this trim index");
-  cfg.maxit = max_it > 0 ? max_it : 1000;
-  cfg.check_every = 8;
-  cfg.solver = solver;
-  launch_dinv<double>(n, c->deg, sigma, cfg.trim, c->dinv64, s);
-  launch_dinv<float>(n, c->deg, sigma, cfg.trim, c->dinv32, s);
-  // deflation columns (internal order, trimmed row zeroed) and the SMW capacitance
-  std::vector<double> Cm((size_t)nc * nc);
-  for (int j = 0; j < nc; ++j) {
-    launch_gather<double, double>(n, V + (size_t)j * n, c->d_perm, c->tmp64, s);
-    launch_masked_copy<double>(n, c->tmp64, cfg.trim, c->Vin64 + (size_t)j * ld, s);
-    launch_masked_copy<float>(n, c->tmp64, cfg.trim, c->Vin32 + (size_t)j * ld, s);
-  }
-  for (int j = 0; j < nc; ++j) {
-    if (precond == ISIRA_PC_MULTILEVEL) {
-      if (prec == ISIRA_FP64) {
-        ml::apply<double>(c->ml, c->Vin64 + (size_t)j * ld, c->Y64 + (size_t)j * ld, 0, c->st, c->rb, s);
-        launch_multidot<double>(n, c->Vin64, ld, nc, nullptr, ld, 0, c->Y64 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
-      } else {
-        ml::apply<float>(c->ml, c->Vin32 + (size_t)j * ld, c->Y32 + (size_t)j * ld, 0, c->st, c->rb, s);
-        launch_multidot<float>(n, c->Vin32, ld, nc, nullptr, ld, 0, c->Y32 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
-      }
-    } else if (precond == ISIRA_PC_LEARNED) {
-      if (prec == ISIRA_FP64) {
-        spai::apply_plain<double>(c->spw, c->plan, c->rp, c->col,
-                                  c->Vin64 + (size_t)j * ld, c->Y64 + (size_t)j * ld, n, cfg.trim, s);
-        launch_multidot<double>(n, c->Vin64, ld, nc, nullptr, ld, 0, c->Y64 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
-      } else {
-        spai::apply_plain<float>(c->spw, c->plan, c->rp, c->col,
-                                 c->Vin32 + (size_t)j * ld, c->Y32 + (size_t)j * ld, n, cfg.trim, s);
-        launch_multidot<float>(n, c->Vin32, ld, nc, nullptr, ld, 0, c->Y32 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
-      }
-    } else if (prec == ISIRA_FP64) {
-      launch_multidot<double>(n, c->Vin64, ld, nc, nullptr, ld, 0, c->Vin64 + (size_t)j * ld, c->dinv64, 0, 0, c->hbuf, c->rb, s);
-    } else {
-      launch_multidot<float>(n, c->Vin32, ld, nc, nullptr, ld, 0, c->Vin32 + (size_t)j * ld, c->dinv32, 0, 0, c->hbuf, c->rb, s);
+  return guarded([&]() -> int {
+    if (!c || !r || !z || (nc > 0 && !V)) return fail(ISIRA_E_ARG, "NULL argument");
+    if (nc < 0 || nc > kMaxC || nc > c->n - 3) return fail(ISIRA_E_ARG, "bad c");
+    if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
+    if (prec != ISIRA_FP64 && prec != ISIRA_FP32) return fail(ISIRA_E_ARG, "bad prec");
+    if (precond == ISIRA_PC_LEARNED && !c->has_learned) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
+    if (solver != ISIRA_SOLVER_PCG && solver != ISIRA_SOLVER_MINRES) return fail(ISIRA_E_ARG, "bad solver");
+    if (solver == ISIRA_SOLVER_MINRES && precond != ISIRA_PC_JACOBI)
+      return fail(ISIRA_E_ARG, "MINRES runs with the Jacobi preconditioner only");
+    if (precond != ISIRA_PC_JACOBI && precond != ISIRA_PC_LEARNED && precond != ISIRA_PC_MULTILEVEL)
+      return fail(ISIRA_E_ARG, "bad precond");
+    int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, std::max(1, (int)nc)));
+    if (rc) return rc;
+    const int n = (int)c->n;
+    const int ld = c->ld;
+    hipStream_t s = c->stream;
+    InnerCfg cfg;
+    cfg.prec = prec;
+    cfg.precond = precond;
+    cfg.sigma = sigma;
+    cfg.delta = delta > 0 ? delta : 2.0 * c->max_deg;
+    cfg.rtol = rtol;
+    cfg.trim = trim >= 0 ? c->iperm[trim] : c->trim_default;
+    if (precond == ISIRA_PC_LEARNED && (c->spai_trim != cfg.trim || c->spai_sigma != sigma))
+      return fail(ISIRA_E_PRECOND, "learned preconditioner was installed for another sigma or trim index");
+    if (precond == ISIRA_PC_MULTILEVEL && (!c->ml.ready || c->ml.trim != cfg.trim))
+      return fail(ISIRA_E_PRECOND, "no multilevel hierarchy set up for this trim index");
+    cfg.maxit = max_it > 0 ? max_it : 1000;
+    cfg.check_every = 8;
+    cfg.solver = solver;
+    launch_dinv<double>(n, c->deg, sigma, cfg.trim, c->dinv64, s);
+    launch_dinv<float>(n, c->deg, sigma, cfg.trim, c->dinv32, s);
+    // deflation columns (internal order, trimmed row zeroed) and the SMW capacitance
+    std::vector<double> Cm((size_t)nc * nc);
+    for (int j = 0; j < nc; ++j) {
+      launch_gather<double, double>(n, V + (size_t)j * n, c->d_perm, c->tmp64, s);
+      launch_masked_copy<double>(n, c->tmp64, cfg.trim, c->Vin64 + (size_t)j * ld, s);
+      launch_masked_copy<float>(n, c->tmp64, cfg.trim, c->Vin32 + (size_t)j * ld, s);
     }
-    if ((rc = read_h(c, nc))) return rc;
+    for (int j = 0; j < nc; ++j) {
+      if (precond == ISIRA_PC_MULTILEVEL) {
+        if (prec == ISIRA_FP64) {
+          ml::apply<double>(c->ml, c->Vin64 + (size_t)j * ld, c->Y64 + (size_t)j * ld, 0, c->st, c->rb, s);
+          launch_multidot<double>(n, c->Vin64, ld, nc, nullptr, ld, 0, c->Y64 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+        } else {
+          ml::apply<float>(c->ml, c->Vin32 + (size_t)j * ld, c->Y32 + (size_t)j * ld, 0, c->st, c->rb, s);
+          launch_multidot<float>(n, c->Vin32, ld, nc, nullptr, ld, 0, c->Y32 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+        }
+      } else if (precond == ISIRA_PC_LEARNED) {
+        if (prec == ISIRA_FP64) {
+          spai::apply_plain<double>(c->spw, c->plan, c->rp, c->col,
+                                    c->Vin64 + (size_t)j * ld, c->Y64 + (size_t)j * ld, n, cfg.trim, s);
+          launch_multidot<double>(n, c->Vin64, ld, nc, nullptr, ld, 0, c->Y64 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+        } else {
+          spai::apply_plain<float>(c->spw, c->plan, c->rp, c->col,
+                                   c->Vin32 + (size_t)j * ld, c->Y32 + (size_t)j * ld, n, cfg.trim, s);
+          launch_multidot<float>(n, c->Vin32, ld, nc, nullptr, ld, 0, c->Y32 + (size_t)j * ld, nullptr, 0, 0, c->hbuf, c->rb, s);
+        }
+      } else if (prec == ISIRA_FP64) {
+        launch_multidot<double>(n, c->Vin64, ld, nc, nullptr, ld, 0, c->Vin64 + (size_t)j * ld, c->dinv64, 0, 0, c->hbuf, c->rb, s);
+      } else {
+        launch_multidot<float>(n, c->Vin32, ld, nc, nullptr, ld, 0, c->Vin32 + (size_t)j * ld, c->dinv32, 0, 0, c->hbuf, c->rb, s);
+      }
+      if ((rc = read_h(c, nc))) return rc;
+      SYNC_OR_RETURN(c);
+      for (int i = 0; i < nc; ++i) Cm[i + (size_t)j * nc] = c->hbuf_host[i];
+    }
+    if (nc > 0) {
+      std::vector<double> G((size_t)nc * nc), Gi;
+      for (int j = 0; j < nc; ++j)
+        for (int i = 0; i < nc; ++i)
+          G[i + (size_t)j * nc] = (i == j ? 1.0 : 0.0) + cfg.delta * 0.5 * (Cm[i + (size_t)j * nc] + Cm[j + (size_t)i * nc]);
+      if (!spd_inverse(nc, G, Gi)) return fail(ISIRA_E_PRECOND, "SMW capacitance matrix not positive definite");
+      if ((rc = upload(c, c->Ginv, Gi.data(), Gi.size() * 8))) return rc;
+    }
+    CKH(hipMemcpyAsync(c->tmp64, r, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+    launch_gather<double, double>(n, c->tmp64, c->d_perm, c->r64, s);
+    int its = 0, status = 0;
+    double rel = 0.0;
+    if (prec == ISIRA_FP64) rc = inner_pcg<double>(c, cfg, c->r64, 0.0, nc, &its, &status, &rel);
+    else rc = inner_pcg<float>(c, cfg, c->r64, 0.0, nc, &its, &status, &rel);
+    if (rc) return rc;
+    if (prec == ISIRA_FP64) launch_enlarge<double>(n, c->x64, c->z64, c->st, c->rb, s);
+    else launch_enlarge<float>(n, c->x32, c->z64, c->st, c->rb, s);
+    launch_gather<double, double>(n, c->z64, c->d_iperm, z, s);
     SYNC_OR_RETURN(c);
-    for (int i = 0; i < nc; ++i) Cm[i + (size_t)j * nc] = c->hbuf_host[i];
-  }
-  if (nc > 0) {
-    std::vector<double> G((size_t)nc * nc), Gi;
-    for (int j = 0; j < nc; ++j)
-      for (int i = 0; i < nc; ++i)
-        G[i + (size_t)j * nc] = (i == j ? 1.0 : 0.0) + cfg.delta * 0.5 * (Cm[i + (size_t)j * nc] + Cm[j + (size_t)i * nc]);
-    if (!spd_inverse(nc, G, Gi)) return fail(ISIRA_E_PRECOND, "SMW capacitance matrix not positive definite");
-    if ((rc = upload(c, c->Ginv, Gi.data(), Gi.size() * 8))) return rc;
-  }
-  CKH(hipMemcpyAsync(c->tmp64, r, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
-  launch_gather<double, double>(n, c->tmp64, c->d_perm, c->r64, s);
-  int its = 0, status = 0;
-  double rel = 0.0;
-  if (prec == ISIRA_FP64) rc = inner_pcg<double>(c, cfg, c->r64, 0.0, nc, &its, &status, &rel);
-  else rc = inner_pcg<float>(c, cfg, c->r64, 0.0, nc, &its, &status, &rel);
-  if (rc) return rc;
-  if (prec == ISIRA_FP64) launch_enlarge<double>(n, c->x64, c->z64, c->st, c->rb, s);
-  else launch_enlarge<float>(n, c->x32, c->z64, c->st, c->rb, s);
-  launch_gather<double, double>(n, c->z64, c->d_iperm, z, s);
-  SYNC_OR_RETURN(c);
-  if (iters) *iters = its;
-  if (relres) *relres = rel;
-  return ISIRA_OK;
+    if (iters) *iters = its;
+    if (relres) *relres = rel;
+    return ISIRA_OK;
+  });
 }
 
 extern "C" int isira_orthonormalize(isira_ctx* c, const double* Q, int32_t ncols,
                                     const double* z, double* u, double* norms) {
-  if (!c || !z || !u || !norms || (ncols > 0 && !Q)) return fail(ISIRA_E_ARG, "NULL argument");
-  if (ncols < 0 || ncols > ISIRA_MAX_BASIS) return fail(ISIRA_E_ARG, "bad ncols");
-  int rc = ensure_workspace(c, std::max(c->ws_m, ncols + 1), std::max(c->ws_k, 1));
-  if (rc) return rc;
-  const int n = (int)c->n;
-  const int ld = c->ld;
-  hipStream_t s = c->stream;
-  for (int j = 0; j < ncols; ++j) launch_gather<double, double>(n, Q + (size_t)j * n, c->d_perm, c->U + (size_t)j * ld, s);
-  launch_gather<double, double>(n, z, c->d_perm, c->z64, s);
-  if ((rc = cgs2(c, c->U, ncols, c->Vout, 0, c->z64, norms))) return rc;
-  launch_scale(n, c->z64, norms[1] > 0 ? 1.0 / norms[1] : 0.0, c->tmp64, s);
-  launch_gather<double, double>(n, c->tmp64, c->d_iperm, u, s);
-  SYNC_OR_RETURN(c);
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c || !z || !u || !norms || (ncols > 0 && !Q)) return fail(ISIRA_E_ARG, "NULL argument");
+    if (ncols < 0 || ncols > ISIRA_MAX_BASIS) return fail(ISIRA_E_ARG, "bad ncols");
+    int rc = ensure_workspace(c, std::max(c->ws_m, ncols + 1), std::max(c->ws_k, 1));
+    if (rc) return rc;
+    const int n = (int)c->n;
+    const int ld = c->ld;
+    hipStream_t s = c->stream;
+    for (int j = 0; j < ncols; ++j) launch_gather<double, double>(n, Q + (size_t)j * n, c->d_perm, c->U + (size_t)j * ld, s);
+    launch_gather<double, double>(n, z, c->d_perm, c->z64, s);
+    if ((rc = cgs2(c, c->U, ncols, c->Vout, 0, c->z64, norms))) return rc;
+    launch_scale(n, c->z64, norms[1] > 0 ? 1.0 / norms[1] : 0.0, c->tmp64, s);
+    launch_gather<double, double>(n, c->tmp64, c->d_iperm, u, s);
+    SYNC_OR_RETURN(c);
+    return ISIRA_OK;
+  });
 }
 
 // Allocation-free variant of isira_orthonormalize for callers that cannot allocate: the
@@ -1763,35 +1802,37 @@ extern "C" int isira_orthonormalize(isira_ctx* c, const double* Q, int32_t ncols
 // cleared; calls that overlap on one GPU share scratch and race.
 extern "C" int isira_orthonormalize_noalloc(isira_ctx* c, const double* Q, int32_t ncols,
                                             const double* z, double* u, double* norms) {
-  if (!c || !z || !u || !norms || (ncols > 0 && !Q)) return fail(ISIRA_E_ARG, "NULL argument");
-  if (ncols < 0 || ncols > kNoAllocMaxCols)
-    return fail(ISIRA_E_ARG, "ncols must be 0.." + std::to_string(kNoAllocMaxCols) +
-                                 " (the allocation-free scratch holds the partials of at most " +
-                                 std::to_string(kNoAllocMaxCols) + " columns)");
-  if (!c->scratch_dev) return fail(ISIRA_E_STATE, "no scratch address for this context");
-  const int n = (int)c->n;
-  hipStream_t s = c->stream;
-  double* base = (double*)c->scratch_dev;
-  RedBuf rb{base, nullptr};
-  double* h = base + kNoAllocH;
-  double* norm0 = base + kNoAllocNorm0;
-  DevState* st = (DevState*)(base + kNoAllocState);
-  CKH(hipMemcpyAsync(u, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  // first pass: h = [Q 1]^T u and u^T u, then u -= Q h_Q + 1 (1^T u) / n
-  launch_multidot<double>(n, Q, n, ncols, nullptr, n, 0, u, nullptr, 1, 1, h, rb, s);
-  CKH(hipMemcpyAsync(norm0, h + ncols + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
-  launch_gemv_sub(n, Q, n, ncols, nullptr, n, 0, h, 1, u, 0, st, rb, s);
-  // second pass, with ||u||^2 into st->red[2]
-  launch_multidot<double>(n, Q, n, ncols, nullptr, n, 0, u, nullptr, 1, 0, h, rb, s);
-  launch_gemv_sub(n, Q, n, ncols, nullptr, n, 0, h, 1, u, 1, st, rb, s);
-  launch_scale_dev(n, u, st->red + 2, u, s);
-  double sq[2];
-  CKH(hipMemcpyAsync(&sq[0], norm0, sizeof(double), hipMemcpyDeviceToHost, s));
-  CKH(hipMemcpyAsync(&sq[1], st->red + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-  CKH(hipStreamSynchronize(s));
-  norms[0] = std::sqrt(std::max(0.0, sq[0]));
-  norms[1] = std::sqrt(std::max(0.0, sq[1]));
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c || !z || !u || !norms || (ncols > 0 && !Q)) return fail(ISIRA_E_ARG, "NULL argument");
+    if (ncols < 0 || ncols > kNoAllocMaxCols)
+      return fail(ISIRA_E_ARG, "ncols must be 0.." + std::to_string(kNoAllocMaxCols) +
+                                   " (the allocation-free scratch holds the partials of at most " +
+                                   std::to_string(kNoAllocMaxCols) + " columns)");
+    if (!c->scratch_dev) return fail(ISIRA_E_STATE, "no scratch address for this context");
+    const int n = (int)c->n;
+    hipStream_t s = c->stream;
+    double* base = (double*)c->scratch_dev;
+    RedBuf rb{base, nullptr};
+    double* h = base + kNoAllocH;
+    double* norm0 = base + kNoAllocNorm0;
+    DevState* st = (DevState*)(base + kNoAllocState);
+    CKH(hipMemcpyAsync(u, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // first pass: h = [Q 1]^T u and u^T u, then u -= Q h_Q + 1 (1^T u) / n
+    launch_multidot<double>(n, Q, n, ncols, nullptr, n, 0, u, nullptr, 1, 1, h, rb, s);
+    CKH(hipMemcpyAsync(norm0, h + ncols + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_gemv_sub(n, Q, n, ncols, nullptr, n, 0, h, 1, u, 0, st, rb, s);
+    // second pass, with ||u||^2 into st->red[2]
+    launch_multidot<double>(n, Q, n, ncols, nullptr, n, 0, u, nullptr, 1, 0, h, rb, s);
+    launch_gemv_sub(n, Q, n, ncols, nullptr, n, 0, h, 1, u, 1, st, rb, s);
+    launch_scale_dev(n, u, st->red + 2, u, s);
+    double sq[2];
+    CKH(hipMemcpyAsync(&sq[0], norm0, sizeof(double), hipMemcpyDeviceToHost, s));
+    CKH(hipMemcpyAsync(&sq[1], st->red + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    CKH(hipStreamSynchronize(s));
+    norms[0] = std::sqrt(std::max(0.0, sq[0]));
+    norms[1] = std::sqrt(std::max(0.0, sq[1]));
+    return ISIRA_OK;
+  });
 }
 
 // ------------------------------------------------------------------------------ multilevel
@@ -1821,64 +1862,70 @@ static void fill_ml_info(const ml::Hierarchy& H, isira_ml_info* info) {
 }
 
 extern "C" int isira_ml_setup(isira_ctx* c, const isira_ml_options* opt, isira_ml_info* info) {
-  if (!c) return fail(ISIRA_E_ARG, "NULL context");
-  isira_ml_options o;
-  isira_ml_default_options(&o);
-  if (opt) o = *opt;
-  if (!(o.omega > 0.0 && o.omega < 1.0)) return fail(ISIRA_E_ARG, "need 0 < omega < 1");
-  if (o.coarse_max < 0 || o.coarse_max > 2048) return fail(ISIRA_E_ARG, "need 0 <= coarse_max <= 2048");
-  if (o.max_levels < 1 || o.max_levels > ISIRA_ML_MAX_LEVELS) return fail(ISIRA_E_ARG, "need 1 <= max_levels <= ISIRA_ML_MAX_LEVELS");
-  if (o.trim_index >= c->n) return fail(ISIRA_E_ARG, "trim_index out of range");
-  const int n = (int)c->n;
-  const int trim = o.trim_index >= 0 ? c->iperm[o.trim_index] : c->trim_default;
-  std::vector<int32_t> rp((size_t)n + 1), col((size_t)c->nnz);
-  std::vector<double> w;
-  CKH(hipStreamSynchronize(c->stream));
-  CKH(hipMemcpy(rp.data(), c->rp, rp.size() * 4, hipMemcpyDeviceToHost));
-  CKH(hipMemcpy(col.data(), c->col, col.size() * 4, hipMemcpyDeviceToHost));
-  if (c->wdt != ISIRA_W_NONE) {
-    w.resize((size_t)c->nnz);
-    CKH(hipMemcpy(w.data(), c->w64, w.size() * 8, hipMemcpyDeviceToHost));
-  }
-  ml::Params prm{o.omega, o.coarse_max, o.max_levels};
-  const int rc = ml::setup(c->ml, n, rp.data(), col.data(), w.empty() ? nullptr : w.data(),
-                           c->perm.data(), trim, prm);
-  if (rc) return rc;
-  // the in-place cycle needs room for the second level after the inner residual
-  c->ri_tail = c->ml.lv.empty() ? 0 : c->ml.lv[0].nc;
-  if (c->ws_tail < c->ri_tail) free_workspace(c);
-  if (info) fill_ml_info(c->ml, info);
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c) return fail(ISIRA_E_ARG, "NULL context");
+    isira_ml_options o;
+    isira_ml_default_options(&o);
+    if (opt) o = *opt;
+    if (!(o.omega > 0.0 && o.omega < 1.0)) return fail(ISIRA_E_ARG, "need 0 < omega < 1");
+    if (o.coarse_max < 0 || o.coarse_max > 2048) return fail(ISIRA_E_ARG, "need 0 <= coarse_max <= 2048");
+    if (o.max_levels < 1 || o.max_levels > ISIRA_ML_MAX_LEVELS) return fail(ISIRA_E_ARG, "need 1 <= max_levels <= ISIRA_ML_MAX_LEVELS");
+    if (o.trim_index >= c->n) return fail(ISIRA_E_ARG, "trim_index out of range");
+    const int n = (int)c->n;
+    const int trim = o.trim_index >= 0 ? c->iperm[o.trim_index] : c->trim_default;
+    std::vector<int32_t> rp((size_t)n + 1), col((size_t)c->nnz);
+    std::vector<double> w;
+    CKH(hipStreamSynchronize(c->stream));
+    CKH(hipMemcpy(rp.data(), c->rp, rp.size() * 4, hipMemcpyDeviceToHost));
+    CKH(hipMemcpy(col.data(), c->col, col.size() * 4, hipMemcpyDeviceToHost));
+    if (c->wdt != ISIRA_W_NONE) {
+      w.resize((size_t)c->nnz);
+      CKH(hipMemcpy(w.data(), c->w64, w.size() * 8, hipMemcpyDeviceToHost));
+    }
+    ml::Params prm{o.omega, o.coarse_max, o.max_levels};
+    const int rc = ml::setup(c->ml, n, rp.data(), col.data(), w.empty() ? nullptr : w.data(),
+                             c->perm.data(), trim, prm);
+    if (rc) return rc;
+    // the in-place cycle needs room for the second level after the inner residual
+    c->ri_tail = c->ml.lv.empty() ? 0 : c->ml.lv[0].nc;
+    if (c->ws_tail < c->ri_tail) free_workspace(c);
+    if (info) fill_ml_info(c->ml, info);
+    return ISIRA_OK;
+  });
 }
 
 extern "C" int isira_ml_apply(isira_ctx* c, int32_t prec, const double* x, double* y) {
-  if (!c || !x || !y) return fail(ISIRA_E_ARG, "NULL argument");
-  if (prec != ISIRA_FP64 && prec != ISIRA_FP32) return fail(ISIRA_E_ARG, "bad prec");
-  if (!c->ml.ready) return fail(ISIRA_E_STATE, "no multilevel hierarchy set up");
-  int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
-  if (rc) return rc;
-  const int n = (int)c->n;
-  hipStream_t s = c->stream;
-  launch_gather<double, double>(n, x, c->d_perm, c->tmp64, s);
-  if (prec == ISIRA_FP64) {
-    launch_masked_copy<double>(n, c->tmp64, c->ml.trim, c->ri64, s);
-    ml::apply<double>(c->ml, c->ri64, c->y64, 0, c->st, c->rb, s);
-    launch_gather<double, double>(n, c->y64, c->d_iperm, y, s);
-  } else {
-    launch_masked_copy<float>(n, c->tmp64, c->ml.trim, c->ri32, s);
-    ml::apply<float>(c->ml, c->ri32, c->y32, 0, c->st, c->rb, s);
-    launch_gather<float, double>(n, c->y32, c->d_iperm, y, s);
-  }
-  CKH(hipGetLastError());
-  SYNC_OR_RETURN(c);
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c || !x || !y) return fail(ISIRA_E_ARG, "NULL argument");
+    if (prec != ISIRA_FP64 && prec != ISIRA_FP32) return fail(ISIRA_E_ARG, "bad prec");
+    if (!c->ml.ready) return fail(ISIRA_E_STATE, "no multilevel hierarchy set up");
+    int rc = ensure_workspace(c, std::max(c->ws_m, 2), std::max(c->ws_k, 1));
+    if (rc) return rc;
+    const int n = (int)c->n;
+    hipStream_t s = c->stream;
+    launch_gather<double, double>(n, x, c->d_perm, c->tmp64, s);
+    if (prec == ISIRA_FP64) {
+      launch_masked_copy<double>(n, c->tmp64, c->ml.trim, c->ri64, s);
+      ml::apply<double>(c->ml, c->ri64, c->y64, 0, c->st, c->rb, s);
+      launch_gather<double, double>(n, c->y64, c->d_iperm, y, s);
+    } else {
+      launch_masked_copy<float>(n, c->tmp64, c->ml.trim, c->ri32, s);
+      ml::apply<float>(c->ml, c->ri32, c->y32, 0, c->st, c->rb, s);
+      launch_gather<float, double>(n, c->y32, c->d_iperm, y, s);
+    }
+    CKH(hipGetLastError());
+    SYNC_OR_RETURN(c);
+    return ISIRA_OK;
+  });
 }
 
 extern "C" int isira_ml_get_info(const isira_ctx* c, isira_ml_info* info) {
-  if (!c || !info) return fail(ISIRA_E_ARG, "NULL argument");
-  if (!c->ml.ready) return fail(ISIRA_E_STATE, "no multilevel hierarchy set up");
-  fill_ml_info(c->ml, info);
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c || !info) return fail(ISIRA_E_ARG, "NULL argument");
+    if (!c->ml.ready) return fail(ISIRA_E_STATE, "no multilevel hierarchy set up");
+    fill_ml_info(c->ml, info);
+    return ISIRA_OK;
+  });
 }
 
 // ------------------------------------------------------------------------------ learned SPAI
@@ -1892,144 +1939,154 @@ static int spai_trim_internal(const isira_ctx* c, int64_t trim, int* out) {
 }
 
 extern "C" int isira_spai_install(isira_ctx* c, const float* params, double sigma, int64_t trim) {
-  if (!c || !params) return fail(ISIRA_E_ARG, "NULL argument");
-  if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
-  int t, rc;
-  if ((rc = spai_trim_internal(c, trim, &t))) return rc;
-  const void* wts = c->wdt == ISIRA_W_NONE ? nullptr : (const void*)c->w32;
-  const int wdt = c->wdt == ISIRA_W_NONE ? ISIRA_W_NONE : ISIRA_W_F32;
-  const int frc = spai::forward(c->spw, c->rp, c->col, wts, wdt, c->deg, (int)c->n, c->nnz, sigma, t,
-                                params, c->stream);
-  if (frc == ISIRA_E_WORKSPACE) return frc;  // message set by the allocator
-  if (frc) return fail(ISIRA_E_HIP, "SPAI forward failed");
-  SYNC_OR_RETURN(c);
-  spai::free_pruned(c->spw);  // new values: any earlier pruning is void
-  c->has_learned = true;
-  c->spai_sigma = sigma;
-  c->spai_trim = t;
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c || !params) return fail(ISIRA_E_ARG, "NULL argument");
+    if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
+    int t, rc;
+    if ((rc = spai_trim_internal(c, trim, &t))) return rc;
+    const void* wts = c->wdt == ISIRA_W_NONE ? nullptr : (const void*)c->w32;
+    const int wdt = c->wdt == ISIRA_W_NONE ? ISIRA_W_NONE : ISIRA_W_F32;
+    const int frc = spai::forward(c->spw, c->rp, c->col, wts, wdt, c->deg, (int)c->n, c->nnz, sigma, t,
+                                  params, c->stream);
+    if (frc == ISIRA_E_WORKSPACE) return frc;  // message set by the allocator
+    if (frc) return fail(ISIRA_E_HIP, "SPAI forward failed");
+    SYNC_OR_RETURN(c);
+    spai::free_pruned(c->spw);  // new values: any earlier pruning is void
+    c->has_learned = true;
+    c->spai_sigma = sigma;
+    c->spai_trim = t;
+    return ISIRA_OK;
+  });
 }
 
 extern "C" int isira_spai_prune(isira_ctx* c, double tau, int64_t* kept) {
-  if (!c) return fail(ISIRA_E_ARG, "NULL context");
-  if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(ISIRA_E_ARG, "need a finite tau >= 0");
-  if (!c->has_learned) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
-  const int64_t n = c->n, nnz = c->nnz;
-  std::vector<int32_t> rp((size_t)n + 1), col((size_t)nnz);
-  std::vector<float> off((size_t)nnz), dg((size_t)n);
-  CKH(hipStreamSynchronize(c->stream));
-  CKH(hipMemcpy(rp.data(), c->rp, rp.size() * 4, hipMemcpyDeviceToHost));
-  CKH(hipMemcpy(col.data(), c->col, col.size() * 4, hipMemcpyDeviceToHost));
-  CKH(hipMemcpy(off.data(), c->spw.offd, off.size() * 4, hipMemcpyDeviceToHost));
-  CKH(hipMemcpy(dg.data(), c->spw.diag32, dg.size() * 4, hipMemcpyDeviceToHost));
-  // keep m_ij when nonzero and |m_ij| >= tau sqrt(M_ii M_jj), decided in FP64 from the
-  // stored FP32 values; symmetric in (i, j) because m_ij and m_ji are equal
-  std::vector<uint8_t> keep((size_t)nnz);
-  std::vector<int32_t> cnt((size_t)n);
-  std::atomic<int> asym{0};
-  parallel_for(n, [&](int64_t b, int64_t e) {
-    for (int64_t i = b; i < e; ++i) {
-      int k = 0;
-      for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
-        const double m = (double)off[j];
-        const bool kp = m != 0.0 && std::fabs(m) >= tau * std::sqrt((double)dg[i] * (double)dg[col[j]]);
-        keep[j] = kp;
-        k += kp;
-        if (kp) {  // the transposed entry must carry the same value
-          const int32_t o = col[j];
-          const int32_t* f = std::lower_bound(col.data() + rp[o], col.data() + rp[o + 1], (int32_t)i);
-          if (f == col.data() + rp[o + 1] || *f != (int32_t)i || off[f - col.data()] != off[j]) asym = 1;
+  return guarded([&]() -> int {
+    if (!c) return fail(ISIRA_E_ARG, "NULL context");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(ISIRA_E_ARG, "need a finite tau >= 0");
+    if (!c->has_learned) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
+    const int64_t n = c->n, nnz = c->nnz;
+    std::vector<int32_t> rp((size_t)n + 1), col((size_t)nnz);
+    std::vector<float> off((size_t)nnz), dg((size_t)n);
+    CKH(hipStreamSynchronize(c->stream));
+    CKH(hipMemcpy(rp.data(), c->rp, rp.size() * 4, hipMemcpyDeviceToHost));
+    CKH(hipMemcpy(col.data(), c->col, col.size() * 4, hipMemcpyDeviceToHost));
+    CKH(hipMemcpy(off.data(), c->spw.offd, off.size() * 4, hipMemcpyDeviceToHost));
+    CKH(hipMemcpy(dg.data(), c->spw.diag32, dg.size() * 4, hipMemcpyDeviceToHost));
+    // keep m_ij when nonzero and |m_ij| >= tau sqrt(M_ii M_jj), decided in FP64 from the
+    // stored FP32 values; symmetric in (i, j) because m_ij and m_ji are equal
+    std::vector<uint8_t> keep((size_t)nnz);
+    std::vector<int32_t> cnt((size_t)n);
+    std::atomic<int> asym{0};
+    parallel_for(n, [&](int64_t b, int64_t e) {
+      for (int64_t i = b; i < e; ++i) {
+        int k = 0;
+        for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
+          const double m = (double)off[j];
+          const bool kp = m != 0.0 && std::fabs(m) >= tau * std::sqrt((double)dg[i] * (double)dg[col[j]]);
+          keep[j] = kp;
+          k += kp;
+          if (kp) {  // the transposed entry must carry the same value
+            const int32_t o = col[j];
+            const int32_t* f = std::lower_bound(col.data() + rp[o], col.data() + rp[o + 1], (int32_t)i);
+            if (f == col.data() + rp[o + 1] || *f != (int32_t)i || off[f - col.data()] != off[j]) asym = 1;
+          }
+        }
+        cnt[i] = k;
+      }
+    });
+    if (asym) return fail(ISIRA_E_PRECOND, "learned values are not symmetric");
+    std::vector<int32_t> prp((size_t)n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) prp[i + 1] = prp[i] + cnt[i];
+    const int64_t pnnz = prp[n];
+    std::vector<int32_t> pcol((size_t)pnnz);
+    std::vector<float> pval((size_t)pnnz);
+    parallel_for(n, [&](int64_t b, int64_t e) {
+      for (int64_t i = b; i < e; ++i) {
+        int32_t o = prp[i];
+        for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
+          if (keep[j]) {
+            pcol[o] = col[j];
+            pval[o] = off[j];
+            ++o;
+          } else {
+            off[j] = 0.0f;
+          }
         }
       }
-      cnt[i] = k;
-    }
-  });
-  if (asym) return fail(ISIRA_E_PRECOND, "learned values are not symmetric");
-  std::vector<int32_t> prp((size_t)n + 1, 0);
-  for (int64_t i = 0; i < n; ++i) prp[i + 1] = prp[i] + cnt[i];
-  const int64_t pnnz = prp[n];
-  std::vector<int32_t> pcol((size_t)pnnz);
-  std::vector<float> pval((size_t)pnnz);
-  parallel_for(n, [&](int64_t b, int64_t e) {
-    for (int64_t i = b; i < e; ++i) {
-      int32_t o = prp[i];
-      for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
-        if (keep[j]) {
-          pcol[o] = col[j];
-          pval[o] = off[j];
-          ++o;
-        } else {
-          off[j] = 0.0f;
-        }
-      }
-    }
-  });
-  spai::free_pruned(c->spw);
-  int rc;
-  auto undo = [&](int code) {
+    });
     spai::free_pruned(c->spw);
-    return code;
-  };
-  if ((rc = dalloc(c->mem, &c->spw.prp, (size_t)n + 1))) return undo(rc);
-  if ((rc = dalloc(c->mem, &c->spw.pcol, (size_t)pnnz))) return undo(rc);
-  if ((rc = dalloc(c->mem, &c->spw.pval, (size_t)pnnz))) return undo(rc);
-  std::vector<int32_t> plong;
-  for (int64_t i = 0; i < n; ++i)
-    if (cnt[i] > kSpLongRow) plong.push_back((int32_t)i);
-  if ((rc = dalloc(c->mem, &c->spw.plong, plong.size()))) return undo(rc);
-  hipError_t e = hipMemcpy(c->spw.prp, prp.data(), prp.size() * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess && !plong.empty())
-    e = hipMemcpy(c->spw.plong, plong.data(), plong.size() * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess && pnnz > 0) e = hipMemcpy(c->spw.pcol, pcol.data(), pcol.size() * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess && pnnz > 0) e = hipMemcpy(c->spw.pval, pval.data(), pval.size() * 4, hipMemcpyHostToDevice);
-  // the full-pattern values follow the pruning too (export, and any product on the pattern)
-  if (e == hipSuccess) e = hipMemcpy(c->spw.offd, off.data(), off.size() * 4, hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    c->has_learned = false;  // the device values may be half updated: install again
-    return undo(fail(ISIRA_E_HIP, std::string("isira_spai_prune upload: ") + hipGetErrorString(e)));
-  }
-  c->spw.pruned = true;
-  c->spw.pnnz = pnnz;
-  c->spw.n_long = (int64_t)plong.size();
-  if (kept) *kept = pnnz;
-  return ISIRA_OK;
+    int rc;
+    auto undo = [&](int code) {
+      spai::free_pruned(c->spw);
+      return code;
+    };
+    if ((rc = dalloc(c->mem, &c->spw.prp, (size_t)n + 1))) return undo(rc);
+    if ((rc = dalloc(c->mem, &c->spw.pcol, (size_t)pnnz))) return undo(rc);
+    if ((rc = dalloc(c->mem, &c->spw.pval, (size_t)pnnz))) return undo(rc);
+    std::vector<int32_t> plong;
+    for (int64_t i = 0; i < n; ++i)
+      if (cnt[i] > kSpLongRow) plong.push_back((int32_t)i);
+    if ((rc = dalloc(c->mem, &c->spw.plong, plong.size()))) return undo(rc);
+    hipError_t e = hipMemcpy(c->spw.prp, prp.data(), prp.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !plong.empty())
+      e = hipMemcpy(c->spw.plong, plong.data(), plong.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && pnnz > 0) e = hipMemcpy(c->spw.pcol, pcol.data(), pcol.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess && pnnz > 0) e = hipMemcpy(c->spw.pval, pval.data(), pval.size() * 4, hipMemcpyHostToDevice);
+    // the full-pattern values follow the pruning too (export, and any product on the pattern)
+    if (e == hipSuccess) e = hipMemcpy(c->spw.offd, off.data(), off.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      c->has_learned = false;  // the device values may be half updated: install again
+      return undo(fail(ISIRA_E_HIP, std::string("isira_spai_prune upload: ") + hipGetErrorString(e)));
+    }
+    c->spw.pruned = true;
+    c->spw.pnnz = pnnz;
+    c->spw.n_long = (int64_t)plong.size();
+    if (kept) *kept = pnnz;
+    return ISIRA_OK;
+  });
 }
 
 extern "C" int isira_spai_export(isira_ctx* c, float* diag, float* offd) {
-  if (!c || !diag || !offd) return fail(ISIRA_E_ARG, "NULL argument");
-  if (!c->has_learned) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
-  launch_gather<float, float>((int)c->n, c->spw.diag32, c->d_iperm, diag, c->stream);
-  spai::scatter_offd(c->nnz, c->spw.offd, c->d_emap, offd, c->stream);
-  SYNC_OR_RETURN(c);
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c || !diag || !offd) return fail(ISIRA_E_ARG, "NULL argument");
+    if (!c->has_learned) return fail(ISIRA_E_PRECOND, "no learned preconditioner installed");
+    launch_gather<float, float>((int)c->n, c->spw.diag32, c->d_iperm, diag, c->stream);
+    spai::scatter_offd(c->nnz, c->spw.offd, c->d_emap, offd, c->stream);
+    SYNC_OR_RETURN(c);
+    return ISIRA_OK;
+  });
 }
 
 extern "C" int isira_spai_loss_grad(isira_ctx* c, const float* params, double sigma, int64_t trim,
                                     const float* r, const float* z, int32_t S, float* grad,
                                     double* loss) {
-  if (!c || !params || !r || !z || !grad || !loss) return fail(ISIRA_E_ARG, "NULL argument");
-  if (S < 1 || S > 64) return fail(ISIRA_E_ARG, "need 1 <= S <= 64 samples per call");
-  if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
-  int t, rc;
-  if ((rc = spai_trim_internal(c, trim, &t))) return rc;
-  const void* wts = c->wdt == ISIRA_W_NONE ? nullptr : (const void*)c->w32;
-  const int wdt = c->wdt == ISIRA_W_NONE ? ISIRA_W_NONE : ISIRA_W_F32;
-  c->has_learned = false;  // the forward pass below overwrites the installed values
-  spai::free_pruned(c->spw);
-  const int lrc = spai::loss_grad(c->spw, c->rp, c->col, wts, wdt, c->deg, (int)c->n, c->nnz, sigma, t,
-                                  params, c->d_perm, r, z, S, grad, loss, c->rb, c->stream);
-  if (lrc == ISIRA_E_WORKSPACE) return lrc;
-  if (lrc) return fail(ISIRA_E_HIP, "SPAI loss/gradient failed");
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c || !params || !r || !z || !grad || !loss) return fail(ISIRA_E_ARG, "NULL argument");
+    if (S < 1 || S > 64) return fail(ISIRA_E_ARG, "need 1 <= S <= 64 samples per call");
+    if (!(sigma >= 0.0) || !(sigma < c->min_deg)) return fail(ISIRA_E_ARG, "need 0 <= sigma < min degree");
+    int t, rc;
+    if ((rc = spai_trim_internal(c, trim, &t))) return rc;
+    const void* wts = c->wdt == ISIRA_W_NONE ? nullptr : (const void*)c->w32;
+    const int wdt = c->wdt == ISIRA_W_NONE ? ISIRA_W_NONE : ISIRA_W_F32;
+    c->has_learned = false;  // the forward pass below overwrites the installed values
+    spai::free_pruned(c->spw);
+    const int lrc = spai::loss_grad(c->spw, c->rp, c->col, wts, wdt, c->deg, (int)c->n, c->nnz, sigma, t,
+                                    params, c->d_perm, r, z, S, grad, loss, c->rb, c->stream);
+    if (lrc == ISIRA_E_WORKSPACE) return lrc;
+    if (lrc) return fail(ISIRA_E_HIP, "SPAI loss/gradient failed");
+    return ISIRA_OK;
+  });
 }
 
 extern "C" int isira_adam_step(isira_ctx* c, float* param, const float* grad, float* m, float* v,
                                int32_t count, float lr, float beta1, float beta2, float eps,
                                int32_t step) {
-  if (!c || !param || !grad || !m || !v || count < 1 || step < 1) return fail(ISIRA_E_ARG, "bad argument");
-  spai::adam(param, grad, m, v, count, lr, beta1, beta2, eps, step, c->stream);
-  SYNC_OR_RETURN(c);
-  return ISIRA_OK;
+  return guarded([&]() -> int {
+    if (!c || !param || !grad || !m || !v || count < 1 || step < 1) return fail(ISIRA_E_ARG, "bad argument");
+    spai::adam(param, grad, m, v, count, lr, beta1, beta2, eps, step, c->stream);
+    SYNC_OR_RETURN(c);
+    return ISIRA_OK;
+  });
 }
 
 extern "C" const char* isira_strerror(int code) {
@@ -2043,6 +2100,7 @@ extern "C" const char* isira_strerror(int code) {
     case ISIRA_E_PRECOND: return "preconditioner error";
     case ISIRA_E_STATE: return "invalid state";
     case ISIRA_E_WORKSPACE: return "workspace too small";
+    case ISIRA_E_HOST: return "host-side failure";
     default: return "unknown error";
   }
 }

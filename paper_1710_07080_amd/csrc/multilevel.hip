@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <string>
 #include <thread>
 #include <vector>
@@ -64,7 +65,9 @@ int setup_threads(int64_t items) {
   return items < 65536 ? 1 : (hc == 0 ? 1 : (hc > 16 ? 16 : (int)hc));
 }
 
-// f(t, begin, end) over nt contiguous ranges of [0, n), one thread each.
+// f(t, begin, end) over nt contiguous ranges of [0, n), one thread each (a range whose
+// thread cannot be started runs on the calling thread).  An exception in any range is
+// rethrown here after every thread has joined.
 template <typename F>
 void run_ranges(int n, int nt, F f) {
   const int chunk = (n + nt - 1) / nt;
@@ -72,9 +75,26 @@ void run_ranges(int n, int nt, F f) {
     f(0, 0, n);
     return;
   }
+  std::vector<std::exception_ptr> ex(nt);
   std::vector<std::thread> th;
-  for (int t = 0; t < nt; ++t) th.emplace_back([&, t] { f(t, t * chunk, std::min(n, t * chunk + chunk)); });
+  th.reserve(nt);
+  for (int t = 0; t < nt; ++t) {
+    auto job = [&, t] {
+      try {
+        f(t, t * chunk, std::min(n, t * chunk + chunk));
+      } catch (...) {
+        ex[t] = std::current_exception();
+      }
+    };
+    try {
+      th.emplace_back(job);
+    } catch (...) {
+      job();
+    }
+  }
   for (auto& x : th) x.join();
+  for (auto& e : ex)
+    if (e) std::rethrow_exception(e);
 }
 
 // f(begin, end) over chunks of [0, n) (64 per thread), which the threads take in turn.
@@ -702,33 +722,35 @@ void apply(const Hierarchy& H, const T* in, T* out, int check_done, DevState* st
 extern "C" int isira_ml_shape(int64_t n, const int32_t* row_ptr, const int32_t* col,
                               const double* w, int64_t trim, const isira_ml_options* opt,
                               isira_ml_info* info) {
-  using namespace isira::ml;
-  if (n < 3 || !row_ptr || !col || !opt || !info) return isira::set_error(ISIRA_E_ARG, "bad argument");
-  if (trim < 0 || trim >= n) return isira::set_error(ISIRA_E_ARG, "trim out of range");
-  if (!(opt->omega > 0.0 && opt->omega < 1.0) || opt->coarse_max < 0 || opt->coarse_max > 2048 ||
-      opt->max_levels < 1 || opt->max_levels > ISIRA_ML_MAX_LEVELS)
-    return isira::set_error(ISIRA_E_ARG, "options out of range");
-  std::vector<int32_t> perm((size_t)n);
-  for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
-  std::vector<HostLevel> lev;
-  std::vector<std::vector<int32_t>> aggs;
-  std::vector<HostMats> mats;
-  HostCoarsest co;
-  Params prm{opt->omega, opt->coarse_max, opt->max_levels};
-  const int rc = build_host((int)n, row_ptr, col, w, perm.data(), (int)trim, prm, lev, aggs, mats, co);
-  if (rc) return rc;
-  std::memset(info, 0, sizeof(*info));
-  info->levels = (int32_t)lev.size();
-  for (size_t l = 0; l < lev.size() && l < ISIRA_ML_MAX_LEVELS; ++l) {
-    int64_t conn = 0;
-    for (int i = 0; i < lev[l].n; ++i) conn += lev[l].rowlen(i) > 0;
-    info->rows[l] = l == 0 ? lev[l].n - 1 : lev[l].n;
-    info->offdiag_nnz[l] = (int64_t)lev[l].col.size();
-    info->connected[l] = conn;
-  }
-  info->coarsest_dense = co.m;
-  for (const HostMats& M : mats) info->stored_nnz += (int64_t)M.dcol.size() + (int64_t)M.ucol.size();
-  return ISIRA_OK;
+  return isira::guarded([&]() -> int {
+    using namespace isira::ml;
+    if (n < 3 || !row_ptr || !col || !opt || !info) return isira::set_error(ISIRA_E_ARG, "bad argument");
+    if (trim < 0 || trim >= n) return isira::set_error(ISIRA_E_ARG, "trim out of range");
+    if (!(opt->omega > 0.0 && opt->omega < 1.0) || opt->coarse_max < 0 || opt->coarse_max > 2048 ||
+        opt->max_levels < 1 || opt->max_levels > ISIRA_ML_MAX_LEVELS)
+      return isira::set_error(ISIRA_E_ARG, "options out of range");
+    std::vector<int32_t> perm((size_t)n);
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+    std::vector<HostLevel> lev;
+    std::vector<std::vector<int32_t>> aggs;
+    std::vector<HostMats> mats;
+    HostCoarsest co;
+    Params prm{opt->omega, opt->coarse_max, opt->max_levels};
+    const int rc = build_host((int)n, row_ptr, col, w, perm.data(), (int)trim, prm, lev, aggs, mats, co);
+    if (rc) return rc;
+    std::memset(info, 0, sizeof(*info));
+    info->levels = (int32_t)lev.size();
+    for (size_t l = 0; l < lev.size() && l < ISIRA_ML_MAX_LEVELS; ++l) {
+      int64_t conn = 0;
+      for (int i = 0; i < lev[l].n; ++i) conn += lev[l].rowlen(i) > 0;
+      info->rows[l] = l == 0 ? lev[l].n - 1 : lev[l].n;
+      info->offdiag_nnz[l] = (int64_t)lev[l].col.size();
+      info->connected[l] = conn;
+    }
+    info->coarsest_dense = co.m;
+    for (const HostMats& M : mats) info->stored_nnz += (int64_t)M.dcol.size() + (int64_t)M.ucol.size();
+    return ISIRA_OK;
+  });
 }
 
 // Host-only: level `level` of the same hierarchy as CSR of its off-diagonal weights (the
@@ -741,36 +763,38 @@ extern "C" int isira_ml_level_matrix(int64_t n, const int32_t* row_ptr, const in
                                      int32_t level, int64_t* rows, int64_t* nnz, int32_t* rp_out,
                                      int32_t* col_out, double* w_out, double* diag_out,
                                      int32_t* agg_out) {
-  using namespace isira::ml;
-  if (n < 3 || !row_ptr || !col || !opt || !rows || !nnz) return isira::set_error(ISIRA_E_ARG, "bad argument");
-  if (trim < 0 || trim >= n) return isira::set_error(ISIRA_E_ARG, "trim out of range");
-  if (!(opt->omega > 0.0 && opt->omega < 1.0) || opt->coarse_max < 0 || opt->coarse_max > 2048 ||
-      opt->max_levels < 1 || opt->max_levels > ISIRA_ML_MAX_LEVELS)
-    return isira::set_error(ISIRA_E_ARG, "options out of range");
-  std::vector<int32_t> perm((size_t)n);
-  for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
-  std::vector<HostLevel> lev;
-  std::vector<std::vector<int32_t>> aggs;
-  std::vector<HostMats> mats;
-  HostCoarsest co;
-  Params prm{opt->omega, opt->coarse_max, opt->max_levels};
-  const int rc = build_host((int)n, row_ptr, col, w, perm.data(), (int)trim, prm, lev, aggs, mats, co);
-  if (rc) return rc;
-  if (level < 0 || level >= (int)lev.size()) return isira::set_error(ISIRA_E_ARG, "level out of range");
-  const HostLevel& A = lev[level];
-  *rows = A.n;
-  *nnz = (int64_t)A.col.size();
-  if (!rp_out) return ISIRA_OK;
-  if (!col_out || !w_out || !diag_out || !agg_out) return isira::set_error(ISIRA_E_ARG, "NULL output");
-  std::copy(A.rp.begin(), A.rp.end(), rp_out);
-  std::copy(A.col.begin(), A.col.end(), col_out);
-  std::copy(A.w.begin(), A.w.end(), w_out);
-  std::copy(A.diag.begin(), A.diag.end(), diag_out);
-  if (level < (int)aggs.size())
-    std::copy(aggs[level].begin(), aggs[level].end(), agg_out);
-  else
-    std::fill(agg_out, agg_out + A.n, -1);
-  return ISIRA_OK;
+  return isira::guarded([&]() -> int {
+    using namespace isira::ml;
+    if (n < 3 || !row_ptr || !col || !opt || !rows || !nnz) return isira::set_error(ISIRA_E_ARG, "bad argument");
+    if (trim < 0 || trim >= n) return isira::set_error(ISIRA_E_ARG, "trim out of range");
+    if (!(opt->omega > 0.0 && opt->omega < 1.0) || opt->coarse_max < 0 || opt->coarse_max > 2048 ||
+        opt->max_levels < 1 || opt->max_levels > ISIRA_ML_MAX_LEVELS)
+      return isira::set_error(ISIRA_E_ARG, "options out of range");
+    std::vector<int32_t> perm((size_t)n);
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+    std::vector<HostLevel> lev;
+    std::vector<std::vector<int32_t>> aggs;
+    std::vector<HostMats> mats;
+    HostCoarsest co;
+    Params prm{opt->omega, opt->coarse_max, opt->max_levels};
+    const int rc = build_host((int)n, row_ptr, col, w, perm.data(), (int)trim, prm, lev, aggs, mats, co);
+    if (rc) return rc;
+    if (level < 0 || level >= (int)lev.size()) return isira::set_error(ISIRA_E_ARG, "level out of range");
+    const HostLevel& A = lev[level];
+    *rows = A.n;
+    *nnz = (int64_t)A.col.size();
+    if (!rp_out) return ISIRA_OK;
+    if (!col_out || !w_out || !diag_out || !agg_out) return isira::set_error(ISIRA_E_ARG, "NULL output");
+    std::copy(A.rp.begin(), A.rp.end(), rp_out);
+    std::copy(A.col.begin(), A.col.end(), col_out);
+    std::copy(A.w.begin(), A.w.end(), w_out);
+    std::copy(A.diag.begin(), A.diag.end(), diag_out);
+    if (level < (int)aggs.size())
+      std::copy(aggs[level].begin(), aggs[level].end(), agg_out);
+    else
+      std::fill(agg_out, agg_out + A.n, -1);
+    return ISIRA_OK;
+  });
 }
 
 namespace isira {

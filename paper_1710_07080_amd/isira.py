@@ -24,6 +24,7 @@ ISIRA_E_HIP = -4
 ISIRA_E_PRECOND = -5
 ISIRA_E_STATE = -6
 ISIRA_E_WORKSPACE = -7
+ISIRA_E_HOST = -8
 WS_LEARNED = 1
 W_NONE, W_F32, W_F64 = 0, 1, 2
 FP64, FP32 = 0, 1

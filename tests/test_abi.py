@@ -37,8 +37,9 @@ def test_defaults_and_strerror(P):
     o = P.isira.default_options()
     assert o.k0 == 4 and o.inner_rtol == 1e-1 and o.trim_index == -1 and o.check_every == 8
     lib = P.load()
-    for code in [0, 1, -1, -2, -3, -4, -5, -6]:
-        assert lib.isira_strerror(code)
+    for code in [0, 1, -1, -2, -3, -4, -5, -6, -7, -8]:
+        assert lib.isira_strerror(code) and lib.isira_strerror(code) != b"unknown error", code
+    assert lib.isira_strerror(-99) == b"unknown error"
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 7, 40, 120, 192])
