@@ -15,6 +15,7 @@
 #include <thread>
 #include <vector>
 
+#include "guard.h"
 #include "internal.h"
 #include "multilevel.h"
 #include "spai.h"

@@ -3,9 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <exception>
 #include <map>
-#include <new>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -319,20 +317,5 @@ void launch_fill_replacement(int n, uint64_t seed, uint64_t draw, const int32_t*
 void launch_signed_gather(int n, const double* v, const int32_t* perm, const int32_t* iperm,
                           double* out, double* scal4, RedBuf rb, hipStream_t s);
 int set_error(int code, const char* msg);
-
-// Runs an entry point's body and turns a C++ exception (a failed host allocation, say) into
-// ISIRA_E_HOST, so that no exception crosses the C ABI.
-template <typename F>
-int guarded(F&& f) noexcept {
-  try {
-    return f();
-  } catch (const std::bad_alloc&) {
-    return set_error(ISIRA_E_HOST, "host memory exhausted");
-  } catch (const std::exception& e) {
-    return set_error(ISIRA_E_HOST, e.what());
-  } catch (...) {
-    return set_error(ISIRA_E_HOST, "host-side failure");
-  }
-}
 
 }  // namespace isira

@@ -26,6 +26,7 @@
 #include <thread>
 #include <vector>
 
+#include "guard.h"
 #include "multilevel.h"
 
 namespace isira {
