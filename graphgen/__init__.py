@@ -13,6 +13,7 @@ from .generators import (  # noqa: F401
     star_graph,
     hypercube,
     spider,
+    whiskered_clique,
     random_connected,
     rmat,
     chung_lu,

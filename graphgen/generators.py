@@ -242,6 +242,16 @@ def spider(p: int, length: int) -> CSRGraph:
     return _csr_from_undirected(n, us, ts, lcc=False, name=f"spider{p}x{length}")
 
 
+def whiskered_clique(m: int = 12) -> CSRGraph:
+    """The complete graph on vertices 0..m-1 with two leaves (m, m+1) and two 2-paths
+    (0-(m+2)-(m+3), 0-(m+4)-(m+5)) hanging from vertex 0: R-MAT's whiskers in miniature."""
+    us = [i for i in range(m) for j in range(i + 1, m)]
+    ts = [j for i in range(m) for j in range(i + 1, m)]
+    us += [0, 0, 0, m + 2, 0, m + 4]
+    ts += [m, m + 1, m + 2, m + 3, m + 4, m + 5]
+    return _csr_from_undirected(m + 6, us, ts, lcc=False, name=f"whiskered_clique{m}")
+
+
 def random_connected(n: int, extra: int, seed: int, weights: Optional[tuple] = None) -> CSRGraph:
     """Random spanning tree plus ``extra`` random edges (duplicates/self loops dropped)."""
     rng = np.random.default_rng(seed)

@@ -298,6 +298,21 @@ def test_solve_grid64_closed_form(P):
         assert x[np.argmax(np.abs(x))] > 0
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_whisker_closed_form(P, prec):
+    """R-MAT-style whiskers in miniature (K_12 with two leaves and two 2-paths on one
+    vertex): the solve reaches the closed-form eigenvalues (3 - sqrt 5) / 2 and 1 (twice)."""
+    g = gg.whiskered_clique(12)
+    ctx = P.Context.from_graph(g)
+    ev, X, resid, st = ctx.solve(4, 0.0, 1e-11, u0=gg.start_block(g.n, 2, 4), inner_prec=prec)
+    ev = np.sort(ev)
+    golden = (3.0 - math.sqrt(5.0)) / 2.0
+    assert st["n_converged"] == 4
+    assert abs(ev[0] - golden) <= 1e-10 * golden
+    assert np.sum(np.abs(ev - 1.0) <= 1e-10) == 2
+    assert resid.max() <= 1e-11
+
+
 @pytest.mark.parametrize("case", [
     dict(g=lambda: gg.random_connected(3000, 4000, seed=31), k=8, sigma=0.0, q=12, m=20, prec=0),
     dict(g=lambda: gg.random_connected(2500, 6000, seed=32, weights=(0.5, 1.5)), k=6, sigma=0.0, q=None, m=None, prec=0),

@@ -406,6 +406,28 @@ def test_isira_spider_multiplicity():
 
 
 
+def test_isira_whisker_eigenvalues():
+    # K_12 with two leaves (12, 13) and two 2-paths (0-14-15, 0-16-17) on vertex 0.  The leaf
+    # mode (+1 on 12, -1 on 13, 0 elsewhere) is an eigenvector of L for eigenvalue 1 (each
+    # leaf row reads x_leaf - x_0 = x_leaf); the antisymmetric 2-path modes (a, b on 14, 15 and
+    # -a, -b on 16, 17) reduce to the 2x2 matrix [[2, -1], [-1, 1]], eigenvalues
+    # (3 -+ sqrt 5) / 2.
+    g = gg.whiskered_clique(12)
+    golden = (3.0 - math.sqrt(5.0)) / 2.0  # 0.3819660112501051
+    # the leaf mode is an exact eigenvector for 1, entry by entry
+    x = np.zeros(g.n)
+    x[12], x[13] = 1.0, -1.0
+    assert np.array_equal(O.laplacian_apply(g, x), x)
+    k = 4
+    res = O.isira(g, k, 0.0, 1e-11, gg.start_block(g.n, 2, 4), inner_rtol=1e-10)
+    ev = np.sort(res.evals)
+    assert abs(ev[0] - golden) <= 1e-10 * golden
+    assert np.sum(np.abs(ev - 1.0) <= 1e-10) == 2  # the leaf mode and one more mode at 1
+    # the remaining value against a dense eigensolver (not a closed form)
+    lam = np.linalg.eigvalsh(dense_laplacian_from_edges(g))
+    assert abs(ev[1] - lam[2]) <= 1e-9 * lam[2]
+
+
 def _minres_norm_check(K, b, P, x, rel):
     # eta is the P-norm of the residual (P the preconditioner, the inverse of M)
     r = b - K @ x
