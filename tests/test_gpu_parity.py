@@ -304,7 +304,9 @@ def test_solve_whisker_closed_form(P, prec):
     vertex): the solve reaches the closed-form eigenvalues (3 - sqrt 5) / 2 and 1 (twice)."""
     g = gg.whiskered_clique(12)
     ctx = P.Context.from_graph(g)
-    ev, X, resid, st = ctx.solve(4, 0.0, 1e-11, u0=gg.start_block(g.n, 2, 4), inner_prec=prec)
+    # 18 vertices: the basis must stay below n - 1 - k columns
+    ev, X, resid, st = ctx.solve(4, 0.0, 1e-11, u0=gg.start_block(g.n, 2, 4), inner_prec=prec,
+                                 q=6, m=12)
     ev = np.sort(ev)
     golden = (3.0 - math.sqrt(5.0)) / 2.0
     assert st["n_converged"] == 4
