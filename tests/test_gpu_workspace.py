@@ -117,3 +117,32 @@ def test_workspace_too_small(P):
     assert e.value.code == P.isira.ISIRA_E_WORKSPACE
     ev, X, r, st = ctx.solve(k, 0.0, 1e-8)  # the sized solve still runs afterwards
     assert st["n_converged"] == k
+
+
+def test_workspace_multilevel_hierarchy(P):
+    """The multilevel hierarchy's buffers come from the workspace too: with room for them
+    the cycle-preconditioned solve is bit-identical to an allocating context's; without it
+    the set-up fails with ISIRA_E_WORKSPACE and the context keeps working with Jacobi."""
+    g = gg.grid3d(24, 22, 20, weights=(0.5, 1.5), seed=6)
+    k = 6
+    U0 = gg.start_block(g.n, 4, 6)
+    own = P.Context.from_graph(g)
+    info = own.ml_setup()
+    ref = own.solve(k, 0.0, 1e-9, u0=U0, inner_prec=P.isira.FP32, precond=P.isira.PC_MULTILEVEL)
+    plain = own.solve(k, 0.0, 1e-9, u0=U0)
+    own.close()
+    base = P.isira.workspace_bytes(g.n, g.nnz, k, w_dtype=P.isira.W_F64)
+    # room for the hierarchy: its device bytes plus one 256-byte block per buffer
+    ws = torch.empty(base + info["device_bytes"] + (1 << 20), dtype=torch.uint8, device="cuda")
+    rp, col, w = g.row_ptr, g.col, g.w
+    ctx = P.Context.with_workspace(g.n, rp, col, w, workspace=ws, k=k)
+    assert ctx.ml_setup()["rows"] == info["rows"]
+    _same(ref, ctx.solve(k, 0.0, 1e-9, u0=U0, inner_prec=P.isira.FP32, precond=P.isira.PC_MULTILEVEL))
+    assert ctx.memory_info()["peak"] <= ws.numel()
+    ctx.close()
+    tight = torch.empty(base, dtype=torch.uint8, device="cuda")
+    ctx = P.Context.with_workspace(g.n, rp, col, w, workspace=tight, k=k)
+    with pytest.raises(P.isira.IsiraError) as e:
+        ctx.ml_setup()
+    assert e.value.code == P.isira.ISIRA_E_WORKSPACE
+    _same(plain, ctx.solve(k, 0.0, 1e-9, u0=U0))
