@@ -1894,12 +1894,10 @@ __global__ __launch_bounds__(1024) void k_tsgemm_mfma_g(int n, double* U, int64_
 template <int NTW, int G>
 static void launch_tsgemm_mfma_g(int n, double* U, int64_t ld, int k, const double* St, int q,
                                  size_t lds, hipStream_t s) {
-  static bool lds_raised = false;
-  if (!lds_raised) {
-    (void)hipFuncSetAttribute((const void*)k_tsgemm_mfma_g<NTW, G>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTsMfmaLds);
-    lds_raised = true;
-  }
+  // set on every call (rotations are rare): the attribute is per device, and a process may
+  // drive several; a failure shows as the launch's error
+  (void)hipFuncSetAttribute((const void*)k_tsgemm_mfma_g<NTW, G>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTsMfmaLds);
   constexpr int RT = 16 / G;
   int grid = (((n + 15) >> 4) + RT - 1) / RT;
   if (grid > 1024) grid = 1024;
@@ -1910,12 +1908,8 @@ template <int NT>
 static void launch_tsgemm_mfma_nt(int n, double* U, int64_t ld, int k, const double* St, int q,
                                   size_t lds, hipStream_t s) {
   constexpr int TH = 1024;  // up to four tiles: accumulators and S fragments fit
-  static bool lds_raised = false;
-  if (!lds_raised) {
-    (void)hipFuncSetAttribute((const void*)k_tsgemm_mfma<NT, TH>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTsMfmaLds);
-    lds_raised = true;
-  }
+  (void)hipFuncSetAttribute((const void*)k_tsgemm_mfma<NT, TH>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTsMfmaLds);
   int grid = (((n + 15) >> 4) + (TH / 64) - 1) / (TH / 64);
   if (grid > 1024) grid = 1024;
   k_tsgemm_mfma<NT, TH><<<grid, TH, lds, s>>>(n, U, ld, k, St, q);
@@ -1947,13 +1941,10 @@ void launch_tsgemm_inplace(int n, double* U, int64_t ld, int k, const double* St
   // S too large for the LDS of one workgroup (k and q both near ISIRA_MAX_BASIS)
   int grid = (n + kTsRows - 1) / kTsRows;
   if (grid > 2048) grid = 2048;
-  static bool lds_raised = false;  // k <= 192 needs up to 96 KB of dynamic LDS
-  if (!lds_raised) {
-    (void)hipFuncSetAttribute((const void*)k_tsgemm_inplace,
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              ISIRA_MAX_BASIS * kTsRows * (int)sizeof(double));
-    lds_raised = true;
-  }
+  // k <= 192 needs up to 96 KB of dynamic LDS (set on every call, as above)
+  (void)hipFuncSetAttribute((const void*)k_tsgemm_inplace,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            ISIRA_MAX_BASIS * kTsRows * (int)sizeof(double));
   k_tsgemm_inplace<<<grid, kBlock, (size_t)k * kTsRows * sizeof(double), s>>>(n, U, ld, k, St, q);
   HIP_LAUNCH_CHECK();
 }
