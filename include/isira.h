@@ -16,7 +16,9 @@
  *     of the GPU the context was created on (e.g. torch CUDA tensors on ROCm).  The caller
  *     owns every pointer it passes; the library copies what it keeps.
  *   - Vectors passed to or returned from a context use the caller's vertex labels.
- *     Internally the library relabels vertices (by decreasing row length) and maps back.
+ *     Internally the library relabels vertices (by decreasing row length, or in reverse
+ *     Cuthill-McKee order when no row is longer than a product work unit and the gathers do
+ *     not concentrate on a few hubs) and maps back.
  *   - Dense n-by-c blocks are column-major with leading dimension n unless stated.
  *   - A context is not thread-safe; calls on one context must not overlap.
  *   - All GPU work of a context runs on the stream given at creation (NULL = default).
